@@ -1,0 +1,228 @@
+"""CPU oracle for the pair-yield evaluation (arXiv:1704.08919) -- TEST INFRASTRUCTURE.
+
+Only the test-suite, the smoke check and the benchmark's CPU-baseline leg import this package.
+The product path (the HIP library and its Python binding) never imports, links or calls it,
+and it shares no code with that path.
+
+The numerical work lives in oracle.cpp (plain C++, long double for parity references and double
+for the timed baseline); this module only marshals numpy arrays through ctypes.  Every function
+cites the passage of the paper it follows in oracle.cpp.  The MLP reference lives in
+oracle/mlp.py.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I = ctypes.POINTER(ctypes.c_int)
+_U32 = ctypes.POINTER(ctypes.c_uint32)
+_I32 = ctypes.POINTER(ctypes.c_int32)
+_U8 = ctypes.POINTER(ctypes.c_uint8)
+
+NORM_NONE, NORM_PEAK, NORM_ENERGY = 0, 1, 2
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.LIB
+        if not os.path.exists(path):
+            _build.build()
+        L = ctypes.CDLL(path)
+        c_int, c_long, c_double = ctypes.c_int, ctypes.c_long, ctypes.c_double
+        sig = {
+            "orc_bspline_ld": (None, [c_int, c_int, c_double, c_double, c_double, _D]),
+            "orc_spectra_ld": (c_int, [c_int, c_int, c_double, c_double, c_double, _D, c_int, _D, _D, _D]),
+            "orc_field_at_ld": (None, [c_int, c_int, c_double, c_double, c_double, _D, c_int, _D, _D, _D]),
+            "orc_synth_ld": (None, [c_int, c_int, c_double, c_double, c_double, c_int, c_int, c_double,
+                                    _D, _D, _D, _D, _D]),
+            "orc_synth_d": (None, [c_int, c_int, c_double, c_double, c_double, c_int, c_int, c_double,
+                                   _D, _D, _D, _D, _D]),
+            "orc_evolve_points_ld": (None, [c_int, c_double, _D, _D, c_long, _D, _D, c_int]),
+            "orc_evolve_points_d": (None, [c_int, c_double, _D, _D, c_long, _D, _D, c_int]),
+            "orc_evolve_state_ld": (c_double, [c_int, c_double, _D, _D, _D, _D]),
+            "orc_free_spinors_ld": (c_double, [_D, _D, _D]),
+            "orc_grid_points": (c_double, [_I, _D, _D, _D]),
+            "orc_yield": (c_double, [_I, _D, _D, _D]),
+            "orc_evaluate_ld": (c_double, [c_int, c_int, c_double, c_double, c_double, c_int, c_int, c_double,
+                                           _D, _I, _D, _D, _D, c_int]),
+            "orc_evaluate_d": (c_double, [c_int, c_int, c_double, c_double, c_double, c_int, c_int, c_double,
+                                          _D, _I, _D, _D, _D, c_int]),
+            "orc_qke_points_ld": (None, [c_int, c_int, c_double, c_double, c_double, c_int, c_double, _D,
+                                         c_int, c_int, c_long, _D, _D, c_int]),
+            "orc_qke_tabulated_ld": (None, [c_int, c_double, _D, _D, _D, c_int, c_long, _D, _D, c_int]),
+            "orc_philox4x32_10": (None, [_U32, _U32, _U32]),
+            "orc_de_propose": (None, [c_int, c_int, c_int, c_double, c_double, c_double, c_double,
+                                      ctypes.c_uint64, ctypes.c_int64, _D, _D, _I32]),
+            "orc_de_select": (None, [c_int, c_int, _D, _D, _D, _D, _U8]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return a.ctypes.data_as(_D)
+
+
+def _arr(x, dtype=np.float64):
+    return np.ascontiguousarray(np.asarray(x, dtype=dtype))
+
+
+# ----------------------------------------------------------------------------------- pulses
+def bspline_basis(order, ns, wmin, wmax, w):
+    """b_i^{(k)}(w), i = 0..ns-1 (Sec. III, Cox-de Boor recursion on clamped knots)."""
+    out = np.zeros(ns)
+    lib().orc_bspline_ld(order, ns, wmin, wmax, float(w), _d(out))
+    return out
+
+
+def spectra(spec, coeff):
+    """(Omega_j, E[2][N+1], Phi[2][N+1]) sampled from the B-spline expansions (Sec. III)."""
+    coeff = _arr(coeff)
+    cap = 1 << 16
+    Om, E, Ph = np.zeros(cap), np.zeros(2 * cap), np.zeros(2 * cap)
+    n = lib().orc_spectra_ld(spec["n_s"], spec["order"], spec["omega_min"], spec["omega_max"], spec["T"],
+                             _d(coeff), cap, _d(Om), _d(E), _d(Ph))
+    return Om[:n].copy(), E[:2 * n].reshape(2, n).copy(), Ph[:2 * n].reshape(2, n).copy()
+
+
+def field_at(spec, coeff, t):
+    """Unscaled E(t)[n][2] and A(t)[n][2] (Sec. III, Eq. field and Eq. vector_potential)."""
+    coeff, t = _arr(coeff), _arr(t).ravel()
+    E, A = np.zeros((t.size, 2)), np.zeros((t.size, 2))
+    lib().orc_field_at_ld(spec["n_s"], spec["order"], spec["omega_min"], spec["omega_max"], spec["T"],
+                          _d(coeff), t.size, _d(t), _d(E), _d(A))
+    return E, A
+
+
+def synth(spec, coeff, precision="ld", with_E=True):
+    """Scaled tables of one pulse: A_mid[nt][2], E_mid[nt][2], A_edge[2][2], scale."""
+    coeff = _arr(coeff)
+    nt = spec["nt"]
+    A, E, edge, sc = np.zeros((nt, 2)), np.zeros((nt, 2)), np.zeros((2, 2)), np.zeros(1)
+    fn = lib().orc_synth_ld if precision == "ld" else lib().orc_synth_d
+    fn(spec["n_s"], spec["order"], spec["omega_min"], spec["omega_max"], spec["T"], nt, spec["norm"],
+       spec["norm_value"], _d(coeff), _d(A), _d(E) if with_E else None, _d(edge), _d(sc))
+    return A, (E if with_E else None), edge, float(sc[0])
+
+
+# --------------------------------------------------------------------------------- dynamics
+def evolve_points(A_mid, A_edge, dt, p, precision="ld", nthreads=0):
+    """Pair density f at momenta p[m][3] for any A table (Sec. II A)."""
+    A_mid, A_edge, p = _arr(A_mid), _arr(A_edge), _arr(p).reshape(-1, 3)
+    f = np.zeros(p.shape[0])
+    fn = lib().orc_evolve_points_ld if precision == "ld" else lib().orc_evolve_points_d
+    fn(A_mid.shape[0], float(dt), _d(A_mid), _d(A_edge), p.shape[0], _d(p), _d(f), int(nthreads))
+    return f
+
+
+def evolve_state(A_mid, A_edge, dt, p):
+    """(f, psi[2][4] complex) of one mode; psi evolved from unit-normalised v_s^in."""
+    A_mid, A_edge, p = _arr(A_mid), _arr(A_edge), _arr(p).ravel()
+    psi = np.zeros((2, 4, 2))
+    f = lib().orc_evolve_state_ld(A_mid.shape[0], float(dt), _d(A_mid), _d(A_edge), _d(p), _d(psi))
+    return f, psi[..., 0] + 1j * psi[..., 1]
+
+
+def free_spinors(P):
+    """Unit-normalised u_s, v_s (Sec. II A) at kinematic momentum P; returns (u[2][4], v[2][4], omega)."""
+    P = _arr(P).ravel()
+    u, v = np.zeros((2, 4, 2)), np.zeros((2, 4, 2))
+    w = lib().orc_free_spinors_ld(_d(P), _d(u), _d(v))
+    return u[..., 0] + 1j * u[..., 1], v[..., 0] + 1j * v[..., 1], w
+
+
+def _grid_arrays(grid):
+    n = np.ascontiguousarray(np.asarray(grid["n"], dtype=np.int32))
+    lo, hi = _arr(grid["lo"]), _arr(grid["hi"])
+    return n, lo, hi
+
+
+def grid_points(grid):
+    """Cell-centred momenta p[m][3] (x fastest) and the cell volume."""
+    n, lo, hi = _grid_arrays(grid)
+    p = np.zeros((int(np.prod(n.astype(np.int64))), 3))
+    dv = lib().orc_grid_points(n.ctypes.data_as(_I), _d(lo), _d(hi), _d(p))
+    return p, dv
+
+
+def pair_yield(grid, f):
+    """J = Delta V sum_p f(p) (Sec. IV A, Eq. opt_prob; midpoint rule)."""
+    n, lo, hi = _grid_arrays(grid)
+    f = _arr(f)
+    return lib().orc_yield(n.ctypes.data_as(_I), _d(lo), _d(hi), _d(f))
+
+
+def evaluate(spec, grid, coeff, precision="ld", nthreads=0, want_f=False):
+    """J for one pulse (synthesis, every grid mode, yield); optionally the f array."""
+    coeff = _arr(coeff)
+    n, lo, hi = _grid_arrays(grid)
+    m = int(np.prod(n.astype(np.int64)))
+    f = np.zeros(m) if want_f else None
+    fn = lib().orc_evaluate_ld if precision == "ld" else lib().orc_evaluate_d
+    J = fn(spec["n_s"], spec["order"], spec["omega_min"], spec["omega_max"], spec["T"], spec["nt"],
+           spec["norm"], spec["norm_value"], _d(coeff), n.ctypes.data_as(_I), _d(lo), _d(hi),
+           _d(f) if want_f else None, int(nthreads))
+    return (J, f) if want_f else J
+
+
+def qke_points(spec, coeff, p, nt, linear=False, nthreads=0):
+    """Kinetic-equation f = 1 - chi_1 (Sec. II B, Eq. qke) by RK4 with nt steps."""
+    coeff, p = _arr(coeff), _arr(p).reshape(-1, 3)
+    f = np.zeros(p.shape[0])
+    lib().orc_qke_points_ld(spec["n_s"], spec["order"], spec["omega_min"], spec["omega_max"], spec["T"],
+                            spec["norm"], spec["norm_value"], _d(coeff), int(bool(linear)), int(nt),
+                            p.shape[0], _d(p), _d(f), int(nthreads))
+    return f
+
+
+def qke_tabulated(E, Ed, A, dt, p, linear=False, nthreads=0):
+    """Kinetic-equation f = 1 - chi_1 for caller-supplied E, dE/dt, A at the 2 nt + 1 RK4 points."""
+    E, Ed, A, p = _arr(E), _arr(Ed), _arr(A), _arr(p).reshape(-1, 3)
+    nt = (E.shape[0] - 1) // 2
+    f = np.zeros(p.shape[0])
+    lib().orc_qke_tabulated_ld(nt, float(dt), _d(E), _d(Ed), _d(A), int(bool(linear)), p.shape[0], _d(p), _d(f),
+                               int(nthreads))
+    return f
+
+
+# ------------------------------------------------------------------------------------- DE
+def philox4x32_10(ctr, key):
+    c = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint32))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint32))
+    o = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(c.ctypes.data_as(_U32), k.ctypes.data_as(_U32), o.ctypes.data_as(_U32))
+    return o
+
+
+def de_propose(pop, generation, F, CR, lo, hi, seed, n_s=0):
+    """DE/rand/1/bin trial vectors (Sec. IV B); returns (trial, idx[N][4] = a, b, c, R)."""
+    pop = _arr(pop)
+    N, D = pop.shape
+    trial = np.zeros_like(pop)
+    idx = np.zeros((N, 4), dtype=np.int32)
+    lib().orc_de_propose(N, D, int(n_s), float(F), float(CR), float(lo), float(hi), int(seed), int(generation),
+                         _d(pop), _d(trial), idx.ctypes.data_as(_I32))
+    return trial, idx
+
+
+def de_select(pop, fit, trial, trial_fit, mask=None):
+    """Greedy selection for maximisation; returns new (pop, fit)."""
+    pop, fit = _arr(pop).copy(), _arr(fit).copy()
+    trial, trial_fit = _arr(trial), _arr(trial_fit)
+    N, D = pop.shape
+    m = None
+    if mask is not None:
+        mask = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
+        m = mask.ctypes.data_as(_U8)
+    lib().orc_de_select(N, D, _d(pop), _d(fit), _d(trial), _d(trial_fit), m)
+    return pop, fit

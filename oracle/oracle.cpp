@@ -1,0 +1,736 @@
+// Plain CPU oracle for the pair-yield evaluation of Fillion-Gourdeau, Hebenstreit,
+// Gagnon & MacLean, "Pulse shape optimization for electron-positron production in
+// rotating fields" (arXiv:1704.08919).
+//
+// TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or calls this
+// file; only the test-suite, the smoke check and the benchmark's CPU-baseline leg do.
+// It shares no code, header, constant or table with the HIP path.
+//
+// Every routine is written from the paper's definitions, slowly and literally:
+//   * B-splines: Cox-de Boor recursion on a clamped knot vector (Sec. III, the
+//     B-spline recursion and knot-vector equations).
+//   * Field: cosine sum of the sampled spectrum times the Hann window (Sec. III, Eq. field
+//     and Eq. hann); vector potential A(t) = -int_{t_f}^t E (Sec. III, Eq. vector_potential
+//     with A(t_f) = 0), written as a definite integral that stays regular at zero frequency.
+//   * Dirac evolution: the literal 4x4 momentum-space Dirac Hamiltonian in the Dirac
+//     representation (Sec. II A, Eq. dirac_eq_mom), one exact exponential of the frozen
+//     Hamiltonian at each step midpoint (a second-order unitary scheme).
+//   * Projection: spin-traced overlap of the evolved negative-energy spinors with the
+//     outgoing positive-energy spinors (Sec. II A, Eq. pair_prod_homo, free-spinor
+//     equations), J as the midpoint-rule momentum integral (Sec. IV A, Eq. opt_prob).
+//   * Quantum kinetic equation: the 6-component ODE of Sec. II B (Eq. qke, Eq. matrix)
+//     with classical fourth-order Runge-Kutta; a cross-check, not part of the hot path.
+//   * Differential evolution DE/rand/1/bin (Sec. IV B) driven by Philox4x32-10
+//     (Salmon, Moraes, Dror, Shaw, SC'11), implemented from that paper's definition.
+//
+// Units: c = hbar = m = 1 and the charge is absorbed into the fields (eE -> E, eA -> A),
+// so the Schwinger field is 1 (Sec. II).  The field lies in the x-y plane; p_z is the
+// out-of-plane momentum (the paper's e_1 direction).
+//
+// Every routine is templated on the real type; the _ld entry points compute in long
+// double (the parity reference), the _d entry points in double (the timed baseline).
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include <omp.h>
+
+namespace {
+
+inline int nthreads_or_default(int n) { return n > 0 ? n : omp_get_max_threads(); }
+
+template <class R> inline R pi_() { return R(3.141592653589793238462643383279502884L); }
+
+// ---------------------------------------------------------------------------------------
+// B-splines (Sec. III): order k means degree k-1; clamped knots with multiplicity k at
+// omega_min and omega_max and n - 2 equidistant simple interior knots, N_s = n + k - 2.
+// ---------------------------------------------------------------------------------------
+template <class R>
+std::vector<R> knots(int k, int ns, R wmin, R wmax) {
+  const int n = ns - k + 2;  // breakpoints, including the two end points
+  std::vector<R> t;
+  for (int i = 0; i < k; ++i) t.push_back(wmin);
+  for (int i = 1; i < n - 1; ++i) t.push_back(wmin + (wmax - wmin) * R(i) / R(n - 1));
+  for (int i = 0; i < k; ++i) t.push_back(wmax);
+  return t;  // 2k + n - 2 = ns + k knots
+}
+
+// b_i^{(k)}(w), 0-based i, by the recursion with 0/0 := 0.  b^{(1)} is the indicator of the
+// half-open knot span, except that the last non-empty span is closed at omega_max so that
+// the sampled frequency Omega_N = omega_max is covered.
+template <class R>
+R bspline(int i, int k, const std::vector<R>& t, R w) {
+  if (k == 1) {
+    if (t[i] <= w && w < t[i + 1]) return R(1);
+    if (w == t.back() && t[i] < t[i + 1] && t[i + 1] == t.back()) return R(1);
+    return R(0);
+  }
+  R left = 0, right = 0;
+  const R d1 = t[i + k - 1] - t[i];
+  if (d1 != 0) left = (w - t[i]) / d1 * bspline(i, k - 1, t, w);
+  const R d2 = t[i + k] - t[i + 1];
+  if (d2 != 0) right = (t[i + k] - w) / d2 * bspline(i + 1, k - 1, t, w);
+  return left + right;
+}
+
+// ---------------------------------------------------------------------------------------
+// Spectral sampling and field synthesis (Sec. III).
+// coeff layout per pulse: [component l in {x,y}][kind in {amplitude, phase}][N_s];
+// a phase coefficient c in [-1,1] maps to a^(phi) = pi (c + 1) in [0, 2 pi].
+// ---------------------------------------------------------------------------------------
+template <class R>
+struct Pulse {
+  int ns = 0, order = 0, nt = 0, norm = 0;
+  R wmin = 0, wmax = 0, T = 0, norm_value = 0;
+  R dw = 0;           // Delta omega = 2 pi / T
+  long nmin = 0;      // N_min = omega_min / Delta omega
+  int nmodes = 0;     // N + 1
+  std::vector<R> Om;  // Omega_j
+  std::vector<R> Ej[2], Phj[2];
+  R scale = 1;
+};
+
+template <class R>
+Pulse<R> make_pulse(int ns, int order, double wmin, double wmax, double T, int nt, int norm,
+                    double norm_value, const double* coeff) {
+  Pulse<R> P;
+  P.ns = ns; P.order = order; P.nt = nt; P.norm = norm;
+  P.wmin = R(wmin); P.wmax = R(wmax); P.T = R(T); P.norm_value = R(norm_value);
+  P.dw = R(2) * pi_<R>() / P.T;
+  P.nmin = std::lround((long double)(P.wmin / P.dw));
+  const long N = (long)std::floor((long double)((P.wmax - P.wmin) / P.dw) + 1e-9L);
+  P.nmodes = (int)N + 1;
+  const std::vector<R> t = knots<R>(order, ns, P.wmin, P.wmax);
+  P.Om.resize(P.nmodes);
+  for (int l = 0; l < 2; ++l) { P.Ej[l].assign(P.nmodes, 0); P.Phj[l].assign(P.nmodes, 0); }
+  for (int j = 0; j < P.nmodes; ++j) {
+    P.Om[j] = R(P.nmin + j) * P.dw;
+    for (int i = 0; i < ns; ++i) {
+      const R b = bspline<R>(i, order, t, P.Om[j]);
+      for (int l = 0; l < 2; ++l) {
+        const R aE = R(coeff[(l * 2 + 0) * ns + i]);
+        const R aP = pi_<R>() * (R(coeff[(l * 2 + 1) * ns + i]) + R(1));
+        P.Ej[l][j] += aE * b;
+        P.Phj[l][j] += aP * b;
+      }
+    }
+  }
+  return P;
+}
+
+// Hann-windowed cosine sum, unscaled: E_l(t) = cos^2(pi t / T) sum_j E_lj cos(Om_j t - Phi_lj).
+template <class R>
+void field(const Pulse<R>& P, R t, R E[2]) {
+  const R g = std::cos(pi_<R>() * t / P.T);
+  for (int l = 0; l < 2; ++l) {
+    R s = 0;
+    for (int j = 0; j < P.nmodes; ++j) s += P.Ej[l][j] * std::cos(P.Om[j] * t - P.Phj[l][j]);
+    E[l] = g * g * s;
+  }
+}
+
+// Time derivative of the unscaled field (used by the kinetic-equation cross-check only).
+template <class R>
+void field_dot(const Pulse<R>& P, R t, R Ed[2]) {
+  const R a = pi_<R>() * t / P.T;
+  const R g = std::cos(a) * std::cos(a);
+  const R gd = -R(2) * std::cos(a) * std::sin(a) * pi_<R>() / P.T;
+  for (int l = 0; l < 2; ++l) {
+    R s = 0, sd = 0;
+    for (int j = 0; j < P.nmodes; ++j) {
+      const R ph = P.Om[j] * t - P.Phj[l][j];
+      s += P.Ej[l][j] * std::cos(ph);
+      sd -= P.Ej[l][j] * P.Om[j] * std::sin(ph);
+    }
+    Ed[l] = gd * s + g * sd;
+  }
+}
+
+// I(w, phi; t) = int_{t_f}^{t} cos(w s + phi) ds = (t - t_f) cos(w (t + t_f)/2 + phi) sinc(w (t - t_f)/2)
+template <class R>
+R cos_integral(R w, R phi, R t, R tf) {
+  const R h = t - tf;
+  const R z = w * h / R(2);
+  const R sinc = (z == 0) ? R(1) : std::sin(z) / z;
+  return h * std::cos(w * (t + tf) / R(2) + phi) * sinc;
+}
+
+// Unscaled A_l(t) = -int_{t_f}^t E_l.  With cos^2 = (1 + cos(2 Om_T s))/2 and 2 Om_T = Delta omega,
+// each spectral line splits into frequencies Om_j and Delta omega +- Om_j.
+template <class R>
+void potential(const Pulse<R>& P, R t, R A[2]) {
+  const R tf = P.T / R(2);
+  for (int l = 0; l < 2; ++l) {
+    R s = 0;
+    for (int j = 0; j < P.nmodes; ++j) {
+      const R w = P.Om[j], ph = P.Phj[l][j];
+      const R I0 = cos_integral<R>(w, -ph, t, tf);
+      const R Ip = cos_integral<R>(P.dw + w, -ph, t, tf);
+      const R Im = cos_integral<R>(P.dw - w, ph, t, tf);
+      s += P.Ej[l][j] * (I0 / R(2) + Ip / R(4) + Im / R(4));
+    }
+    A[l] = -s;
+  }
+}
+
+// Normalisation: 0 = none, 1 = peak |E| over the Nt+1 step nodes, 2 = energy U = int E^2 dt
+// (midpoint rule on the step midpoints), Sec. III Eq. energy and Sec. IV B (global renormalisation).
+template <class R>
+void set_scale(Pulse<R>& P) {
+  const R dt = P.T / R(P.nt);
+  const R ti = -P.T / R(2);
+  if (P.norm == 1) {
+    R peak = 0;
+    for (int n = 0; n <= P.nt; ++n) {
+      R E[2];
+      field<R>(P, ti + R(n) * dt, E);
+      peak = std::max(peak, std::sqrt(E[0] * E[0] + E[1] * E[1]));
+    }
+    P.scale = (peak > 0) ? P.norm_value / peak : R(0);
+  } else if (P.norm == 2) {
+    R U = 0;
+    for (int n = 0; n < P.nt; ++n) {
+      R E[2];
+      field<R>(P, ti + (R(n) + R(0.5)) * dt, E);
+      U += E[0] * E[0] + E[1] * E[1];
+    }
+    U *= dt;
+    P.scale = (U > 0) ? std::sqrt(P.norm_value / U) : R(0);
+  } else {
+    P.scale = 1;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Dirac equation in momentum space (Sec. II A).  Dirac representation:
+// alpha = sigma_x (x) sigma, beta = sigma_z (x) 1, so H(P) = [[m, sigma.P], [sigma.P, -m]].
+// ---------------------------------------------------------------------------------------
+template <class R> using C = std::complex<R>;
+
+template <class R>
+void sigma_dot(const R P[3], C<R> s[2][2]) {
+  s[0][0] = C<R>(P[2], 0);     s[0][1] = C<R>(P[0], -P[1]);
+  s[1][0] = C<R>(P[0], P[1]);  s[1][1] = C<R>(-P[2], 0);
+}
+
+template <class R>
+void hamiltonian(const R P[3], C<R> H[4][4]) {
+  C<R> s[2][2];
+  sigma_dot<R>(P, s);
+  for (int a = 0; a < 4; ++a) for (int b = 0; b < 4; ++b) H[a][b] = 0;
+  for (int a = 0; a < 2; ++a) {
+    H[a][a] = R(1);
+    H[a + 2][a + 2] = R(-1);
+    for (int b = 0; b < 2; ++b) { H[a][b + 2] = s[a][b]; H[a + 2][b] = s[a][b]; }
+  }
+}
+
+// Free spinors at kinematic momentum P (Sec. II A): norm^2 = 2 omega.
+// u_s = [(omega+m) xi_s, (sigma.P) xi_s] / sqrt(omega+m),
+// v_s = [-(sigma.P) eta_s, (omega+m) eta_s] / sqrt(omega+m),
+// xi_1 = eta_2 = (1,0), xi_2 = eta_1 = (0,1).
+template <class R>
+void free_spinors(const R P[3], C<R> u[2][4], C<R> v[2][4], R* omega) {
+  const R w = std::sqrt(R(1) + P[0] * P[0] + P[1] * P[1] + P[2] * P[2]);
+  const R nrm = R(1) / std::sqrt(w + R(1));
+  C<R> s[2][2];
+  sigma_dot<R>(P, s);
+  const int xi_up[2] = {0, 1};   // xi_1 = (1,0) -> component 0; xi_2 = (0,1) -> component 1
+  const int eta_up[2] = {1, 0};  // eta_1 = (0,1), eta_2 = (1,0)
+  for (int sp = 0; sp < 2; ++sp) {
+    const int a = xi_up[sp];
+    u[sp][0] = (a == 0 ? C<R>(w + 1) : C<R>(0)) * nrm;
+    u[sp][1] = (a == 1 ? C<R>(w + 1) : C<R>(0)) * nrm;
+    u[sp][2] = s[0][a] * nrm;
+    u[sp][3] = s[1][a] * nrm;
+    const int b = eta_up[sp];
+    v[sp][0] = -s[0][b] * nrm;
+    v[sp][1] = -s[1][b] * nrm;
+    v[sp][2] = (b == 0 ? C<R>(w + 1) : C<R>(0)) * nrm;
+    v[sp][3] = (b == 1 ? C<R>(w + 1) : C<R>(0)) * nrm;
+  }
+  *omega = w;
+}
+
+// Evolves both negative-energy spinors of one momentum mode through the A table and returns
+// the spin-traced pair density
+//   f = sum_{s,s'} |u_{s'}^out^dagger psi_s(t_f)|^2 / (2 omega_out 2 omega_in).
+// One step: exact exponential of the Hamiltonian frozen at the midpoint t_{n+1/2};
+// since H^2 = omega^2, exp(-i H dt) = cos(omega dt) - i sin(omega dt)/omega H.
+// Optionally returns the final state psi[s][4] (scaled by 1/sqrt(2 omega_in)).
+template <class R>
+R evolve_mode(int nt, R dt, const double* Amid, const double Ain[2], const double Aout[2],
+              const double p[3], double* psi_out /* [2][4][2] or null */) {
+  const R px = R(p[0]), py = R(p[1]), pz = R(p[2]);
+  R Pin[3] = {px - R(Ain[0]), py - R(Ain[1]), pz};
+  C<R> u[2][4], v[2][4];
+  R w_in;
+  free_spinors<R>(Pin, u, v, &w_in);
+  C<R> psi[2][4];
+  for (int s = 0; s < 2; ++s) for (int a = 0; a < 4; ++a) psi[s][a] = v[s][a];
+  C<R> H[4][4], U[4][4];
+  for (int n = 0; n < nt; ++n) {
+    R P[3] = {px - R(Amid[2 * n]), py - R(Amid[2 * n + 1]), pz};
+    const R w = std::sqrt(R(1) + P[0] * P[0] + P[1] * P[1] + P[2] * P[2]);
+    const R c = std::cos(w * dt), sw = std::sin(w * dt) / w;
+    hamiltonian<R>(P, H);
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b)
+        U[a][b] = (a == b ? C<R>(c) : C<R>(0)) - C<R>(0, 1) * sw * H[a][b];
+    for (int s = 0; s < 2; ++s) {
+      C<R> nxt[4];
+      for (int a = 0; a < 4; ++a) {
+        nxt[a] = 0;
+        for (int b = 0; b < 4; ++b) nxt[a] += U[a][b] * psi[s][b];
+      }
+      for (int a = 0; a < 4; ++a) psi[s][a] = nxt[a];
+    }
+  }
+  R Pout[3] = {px - R(Aout[0]), py - R(Aout[1]), pz};
+  C<R> uo[2][4], vo[2][4];
+  R w_out;
+  free_spinors<R>(Pout, uo, vo, &w_out);
+  R f = 0;
+  for (int s = 0; s < 2; ++s)
+    for (int sp = 0; sp < 2; ++sp) {
+      C<R> ov = 0;
+      for (int a = 0; a < 4; ++a) ov += std::conj(uo[sp][a]) * psi[s][a];
+      f += std::norm(ov);
+    }
+  f /= (R(2) * w_out) * (R(2) * w_in);
+  if (psi_out) {
+    const R nrm = R(1) / std::sqrt(R(2) * w_in);
+    for (int s = 0; s < 2; ++s)
+      for (int a = 0; a < 4; ++a) {
+        psi_out[(s * 4 + a) * 2 + 0] = double(psi[s][a].real() * nrm);
+        psi_out[(s * 4 + a) * 2 + 1] = double(psi[s][a].imag() * nrm);
+      }
+  }
+  return f;
+}
+
+// ---------------------------------------------------------------------------------------
+// Quantum kinetic equation (Sec. II B), 6 components, classical RK4.  The paper's field
+// plane (e_2, e_3) is the x-y plane here and e_1 is z (a cyclic relabelling, so
+// (E x Edot).e_1 = Ex Edot_y - Ey Edot_x and p_1 = p_z).  f = 1 - chi_1.
+// For a field along x only, the signed Q = E_x sqrt(1 + P_y^2 + p_z^2) / omega^2 is used:
+// the unsigned root flips the e_2 basis vector whenever E crosses zero.
+// ---------------------------------------------------------------------------------------
+// Field samples needed by RK4 over [-T/2, T/2] with nt steps: E, dE/dt and A at the 2 nt + 1
+// points t_i + h dt/2, h = 0..2nt (scaled), tabulated once per pulse and shared by all modes.
+template <class R>
+struct QkeTable {
+  std::vector<R> E, Ed, A;  // [2nt+1][2]
+};
+
+template <class R>
+QkeTable<R> qke_table(const Pulse<R>& Pu, int nt) {
+  QkeTable<R> tb;
+  const int nh = 2 * nt + 1;
+  tb.E.resize(2 * nh); tb.Ed.resize(2 * nh); tb.A.resize(2 * nh);
+  const R dt = Pu.T / R(nt), ti = -Pu.T / R(2);
+  for (int h = 0; h < nh; ++h) {
+    const R t = ti + R(h) * dt / R(2);
+    R E[2], Ed[2], A[2];
+    field<R>(Pu, t, E);
+    field_dot<R>(Pu, t, Ed);
+    potential<R>(Pu, t, A);
+    for (int l = 0; l < 2; ++l) {
+      tb.E[2 * h + l] = Pu.scale * E[l];
+      tb.Ed[2 * h + l] = Pu.scale * Ed[l];
+      tb.A[2 * h + l] = Pu.scale * A[l];
+    }
+  }
+  return tb;
+}
+
+// Right-hand side N(t,P) chi at table point h.
+template <class R>
+void qke_rhs(const QkeTable<R>& tb, bool linear, int h, const R p[3], const R chi[6], R out[6]) {
+  const R* E = &tb.E[2 * h];
+  const R* Ed = &tb.Ed[2 * h];
+  const R* A = &tb.A[2 * h];
+  const R Px = p[0] - A[0], Py = p[1] - A[1], pz = p[2];
+  const R w2 = R(1) + Px * Px + Py * Py + pz * pz;
+  const R w = std::sqrt(w2);
+  const R eperp = std::sqrt(R(1) + pz * pz);
+  R Q, Rr;
+  if (linear) {
+    Q = E[0] * std::sqrt(R(1) + Py * Py + pz * pz) / w2;
+    Rr = 0;
+  } else {
+    const R EE = E[0] * E[0] + E[1] * E[1];
+    const R EP = E[0] * Px + E[1] * Py;
+    const R X = w2 * EE - EP * EP;
+    Q = std::sqrt(std::max(X, R(0))) / w2;
+    Rr = (X > 0) ? eperp * w * (E[0] * Ed[1] - E[1] * Ed[0]) / X : R(0);
+  }
+  // N(t,P), skew-symmetric (Eq. matrix)
+  out[0] = -Q * chi[1];
+  out[1] = Q * chi[0] - R(2) * w * chi[2] + Rr * chi[3];
+  out[2] = R(2) * w * chi[1] - Rr * chi[4];
+  out[3] = -Rr * chi[1] + R(2) * w * chi[4];
+  out[4] = Rr * chi[2] - R(2) * w * chi[3] + Q * chi[5];
+  out[5] = -Q * chi[4];
+}
+
+template <class R>
+R qke_mode(const QkeTable<R>& tb, bool linear, int nt, R dt, const double p[3]) {
+  const R pr[3] = {R(p[0]), R(p[1]), R(p[2])};
+  R chi[6] = {1, 0, 0, 0, 0, 0};
+  R k1[6], k2[6], k3[6], k4[6], tmp[6];
+  for (int n = 0; n < nt; ++n) {
+    qke_rhs<R>(tb, linear, 2 * n, pr, chi, k1);
+    for (int i = 0; i < 6; ++i) tmp[i] = chi[i] + dt / R(2) * k1[i];
+    qke_rhs<R>(tb, linear, 2 * n + 1, pr, tmp, k2);
+    for (int i = 0; i < 6; ++i) tmp[i] = chi[i] + dt / R(2) * k2[i];
+    qke_rhs<R>(tb, linear, 2 * n + 1, pr, tmp, k3);
+    for (int i = 0; i < 6; ++i) tmp[i] = chi[i] + dt * k3[i];
+    qke_rhs<R>(tb, linear, 2 * n + 2, pr, tmp, k4);
+    for (int i = 0; i < 6; ++i) chi[i] += dt / R(6) * (k1[i] + R(2) * k2[i] + R(2) * k3[i] + k4[i]);
+  }
+  return R(1) - chi[0];
+}
+
+// ---------------------------------------------------------------------------------------
+// Momentum grid: cell-centred points p_d = lo_d + (i + 1/2) (hi_d - lo_d)/n_d; a dimension
+// with n_d = 1 and lo_d = hi_d is a sheet (p_d = lo_d, no measure factor).  Mode order:
+// x fastest, then y, then z.
+// ---------------------------------------------------------------------------------------
+inline void grid_point(const int n[3], const double lo[3], const double hi[3], long idx, double p[3]) {
+  long ix = idx % n[0];
+  long iy = (idx / n[0]) % n[1];
+  long iz = idx / ((long)n[0] * n[1]);
+  const long id[3] = {ix, iy, iz};
+  for (int d = 0; d < 3; ++d) {
+    if (n[d] == 1 && lo[d] == hi[d]) p[d] = lo[d];
+    else p[d] = lo[d] + (double(id[d]) + 0.5) * (hi[d] - lo[d]) / double(n[d]);
+  }
+}
+
+inline double cell_volume(const int n[3], const double lo[3], const double hi[3]) {
+  double v = 1;
+  for (int d = 0; d < 3; ++d)
+    if (!(n[d] == 1 && lo[d] == hi[d])) v *= (hi[d] - lo[d]) / double(n[d]);
+  return v;
+}
+
+// ---------------------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): 10 rounds of the 4x32 Philox S-box with
+// multipliers 0xD2511F53, 0xCD9E8D57 and Weyl key increments 0x9E3779B9, 0xBB67AE85.
+// ---------------------------------------------------------------------------------------
+void philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+    const uint64_t m0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t m1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t hi0 = (uint32_t)(m0 >> 32), lo0 = (uint32_t)m0;
+    const uint32_t hi1 = (uint32_t)(m1 >> 32), lo1 = (uint32_t)m1;
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+// Draw word w (0..3) of block b for individual i in generation g.
+inline uint32_t de_word(uint64_t seed, int64_t g, int i, int b, int w) {
+  const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  const uint32_t ctr[4] = {(uint32_t)i, (uint32_t)b, (uint32_t)(uint64_t)g, (uint32_t)((uint64_t)g >> 32)};
+  uint32_t o[4];
+  philox(ctr, key, o);
+  return o[w];
+}
+
+inline uint32_t uniform_index(uint32_t u, uint32_t n) { return (uint32_t)(((uint64_t)u * n) >> 32); }
+inline double uniform_open01(uint32_t u) { return (double(u) + 0.5) * (1.0 / 4294967296.0); }
+
+// Neumaier-compensated sum of f in mode order, times the cell volume.
+double yield_sum(const int n[3], const double lo[3], const double hi[3], const double* f) {
+  const long nm = (long)n[0] * n[1] * n[2];
+  double s = 0, c = 0;
+  for (long m = 0; m < nm; ++m) {
+    const double x = f[m];
+    const double t = s + x;
+    if (std::fabs(s) >= std::fabs(x)) c += (s - t) + x; else c += (x - t) + s;
+    s = t;
+  }
+  return cell_volume(n, lo, hi) * (s + c);
+}
+
+template <class R>
+void synth_impl(int ns, int order, double wmin, double wmax, double T, int nt, int norm,
+                       double norm_value, const double* coeff, double* Amid, double* Emid,
+                       double* Aedge, double* scale) {
+  auto P = make_pulse<R>(ns, order, wmin, wmax, T, nt, norm, norm_value, coeff);
+  set_scale<R>(P);
+  const R dt = P.T / R(nt), ti = -P.T / R(2), tf = P.T / R(2);
+  for (int n = 0; n < nt; ++n) {
+    const R t = ti + (R(n) + R(0.5)) * dt;
+    R a[2];
+    potential<R>(P, t, a);
+    Amid[2 * n] = double(P.scale * a[0]);
+    Amid[2 * n + 1] = double(P.scale * a[1]);
+    if (Emid) {
+      R e[2];
+      field<R>(P, t, e);
+      Emid[2 * n] = double(P.scale * e[0]);
+      Emid[2 * n + 1] = double(P.scale * e[1]);
+    }
+  }
+  R a0[2], a1[2];
+  potential<R>(P, ti, a0);
+  potential<R>(P, tf, a1);
+  Aedge[0] = double(P.scale * a0[0]); Aedge[1] = double(P.scale * a0[1]);
+  Aedge[2] = double(P.scale * a1[0]); Aedge[3] = double(P.scale * a1[1]);
+  *scale = double(P.scale);
+}
+
+template <class R>
+void evolve_impl(int nt, double dt, const double* Amid, const double* Aedge, long nm,
+                        const double* p, double* f, int nthreads) {
+  const int nth = nthreads_or_default(nthreads);
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nth)
+  for (long m = 0; m < nm; ++m)
+    f[m] = double(evolve_mode<R>(nt, R(dt), Amid, Aedge, Aedge + 2, p + 3 * m, nullptr));
+}
+
+template <class R>
+double evaluate_impl(int ns, int order, double wmin, double wmax, double T, int nt, int norm,
+                            double norm_value, const double* coeff, const int* n, const double* lo,
+                            const double* hi, double* f, int nthreads) {
+  std::vector<double> Amid(2 * (size_t)nt), Aedge(4);
+  double scale;
+  synth_impl<R>(ns, order, wmin, wmax, T, nt, norm, norm_value, coeff, Amid.data(), nullptr, Aedge.data(), &scale);
+  const long nm = (long)n[0] * n[1] * n[2];
+  std::vector<double> p(3 * (size_t)nm), ff((size_t)nm);
+  for (long m = 0; m < nm; ++m) grid_point(n, lo, hi, m, p.data() + 3 * m);
+  evolve_impl<R>(nt, T / nt, Amid.data(), Aedge.data(), nm, p.data(), ff.data(), nthreads);
+  if (f) std::memcpy(f, ff.data(), sizeof(double) * nm);
+  return yield_sum(n, lo, hi, ff.data());
+}
+
+}  // namespace
+
+// =======================================================================================
+// C entry points (ctypes).  Sizes are plain ints; arrays are contiguous, row-major.
+// =======================================================================================
+extern "C" {
+
+int orc_version(void) { return 1; }
+
+// B-spline basis values b_i^{(k)}(w) for i = 0..ns-1.
+void orc_bspline_ld(int order, int ns, double wmin, double wmax, double w, double* out) {
+  using R = long double;
+  const auto t = knots<R>(order, ns, wmin, wmax);
+  for (int i = 0; i < ns; ++i) out[i] = double(bspline<R>(i, order, t, R(w)));
+}
+
+// Spectral samples: Omega[N+1], E[2][N+1], Phi[2][N+1]; returns N+1 (or the required size if
+// cap is too small, without writing).
+int orc_spectra_ld(int ns, int order, double wmin, double wmax, double T, const double* coeff,
+                   int cap, double* Om, double* E, double* Ph) {
+  auto P = make_pulse<long double>(ns, order, wmin, wmax, T, 2, 0, 0, coeff);
+  if (P.nmodes > cap) return P.nmodes;
+  for (int j = 0; j < P.nmodes; ++j) {
+    Om[j] = double(P.Om[j]);
+    for (int l = 0; l < 2; ++l) {
+      E[l * P.nmodes + j] = double(P.Ej[l][j]);
+      Ph[l * P.nmodes + j] = double(P.Phj[l][j]);
+    }
+  }
+  return P.nmodes;
+}
+
+// Unscaled E(t) and A(t) at arbitrary times: E[n][2], A[n][2].
+void orc_field_at_ld(int ns, int order, double wmin, double wmax, double T, const double* coeff,
+                     int n, const double* t, double* E, double* A) {
+  auto P = make_pulse<long double>(ns, order, wmin, wmax, T, 2, 0, 0, coeff);
+  for (int i = 0; i < n; ++i) {
+    long double e[2], a[2];
+    field<long double>(P, (long double)t[i], e);
+    potential<long double>(P, (long double)t[i], a);
+    E[2 * i] = double(e[0]); E[2 * i + 1] = double(e[1]);
+    A[2 * i] = double(a[0]); A[2 * i + 1] = double(a[1]);
+  }
+}
+
+// Full synthesis of one pulse: scaled A and E at the nt step midpoints (A_mid[nt][2],
+// E_mid[nt][2] or null), A_edge = [A(t_i), A(t_f)] (4 values), scale.
+void orc_synth_ld(int ns, int order, double wmin, double wmax, double T, int nt, int norm,
+                  double norm_value, const double* coeff, double* Amid, double* Emid,
+                  double* Aedge, double* scale) {
+  synth_impl<long double>(ns, order, wmin, wmax, T, nt, norm, norm_value, coeff, Amid, Emid, Aedge, scale);
+}
+void orc_synth_d(int ns, int order, double wmin, double wmax, double T, int nt, int norm,
+                 double norm_value, const double* coeff, double* Amid, double* Emid,
+                 double* Aedge, double* scale) {
+  synth_impl<double>(ns, order, wmin, wmax, T, nt, norm, norm_value, coeff, Amid, Emid, Aedge, scale);
+}
+
+// Pair density f at explicit momenta p[nm][3] for an A table (any table, not only a synthesised
+// one).  nthreads <= 0 uses the OpenMP default.
+void orc_evolve_points_ld(int nt, double dt, const double* Amid, const double* Aedge, long nm,
+                          const double* p, double* f, int nthreads) {
+  evolve_impl<long double>(nt, dt, Amid, Aedge, nm, p, f, nthreads);
+}
+void orc_evolve_points_d(int nt, double dt, const double* Amid, const double* Aedge, long nm,
+                         const double* p, double* f, int nthreads) {
+  evolve_impl<double>(nt, dt, Amid, Aedge, nm, p, f, nthreads);
+}
+
+// Final state of one mode: psi[2 spins][4][re,im], unit-normalised initial spinors.
+double orc_evolve_state_ld(int nt, double dt, const double* Amid, const double* Aedge,
+                           const double* p, double* psi) {
+  return double(evolve_mode<long double>(nt, (long double)dt, Amid, Aedge, Aedge + 2, p, psi));
+}
+
+// Unit-normalised free spinors at kinematic momentum P: u[2][4][2], v[2][4][2]; returns omega.
+double orc_free_spinors_ld(const double* P, double* u, double* v) {
+  using R = long double;
+  R Pr[3] = {R(P[0]), R(P[1]), R(P[2])};
+  C<R> uu[2][4], vv[2][4];
+  R w;
+  free_spinors<R>(Pr, uu, vv, &w);
+  const R nrm = R(1) / std::sqrt(R(2) * w);
+  for (int s = 0; s < 2; ++s)
+    for (int a = 0; a < 4; ++a) {
+      u[(s * 4 + a) * 2] = double(uu[s][a].real() * nrm); u[(s * 4 + a) * 2 + 1] = double(uu[s][a].imag() * nrm);
+      v[(s * 4 + a) * 2] = double(vv[s][a].real() * nrm); v[(s * 4 + a) * 2 + 1] = double(vv[s][a].imag() * nrm);
+    }
+  return double(w);
+}
+
+// Grid points of a cell-centred grid: p[nx*ny*nz][3]; returns the cell volume.
+double orc_grid_points(const int* n, const double* lo, const double* hi, double* p) {
+  const long nm = (long)n[0] * n[1] * n[2];
+  for (long m = 0; m < nm; ++m) grid_point(n, lo, hi, m, p + 3 * m);
+  return cell_volume(n, lo, hi);
+}
+
+// J = Delta V * sum_p f(p), Neumaier-compensated, in mode order.
+double orc_yield(const int* n, const double* lo, const double* hi, const double* f) {
+  return yield_sum(n, lo, hi, f);
+}
+
+// Whole objective for one pulse: synthesis, evolution of every grid mode, yield.
+// f (optional) receives the per-mode densities in mode order.
+double orc_evaluate_ld(int ns, int order, double wmin, double wmax, double T, int nt, int norm,
+                       double norm_value, const double* coeff, const int* n, const double* lo,
+                       const double* hi, double* f, int nthreads) {
+  return evaluate_impl<long double>(ns, order, wmin, wmax, T, nt, norm, norm_value, coeff, n, lo, hi, f, nthreads);
+}
+double orc_evaluate_d(int ns, int order, double wmin, double wmax, double T, int nt, int norm,
+                      double norm_value, const double* coeff, const int* n, const double* lo,
+                      const double* hi, double* f, int nthreads) {
+  return evaluate_impl<double>(ns, order, wmin, wmax, T, nt, norm, norm_value, coeff, n, lo, hi, f, nthreads);
+}
+
+// Kinetic-equation cross-check: f = 1 - chi_1 at momenta p[nm][3] for a synthesised pulse,
+// RK4 with nt steps over [-T/2, T/2].  linear != 0 selects the signed-Q linear form.
+void orc_qke_points_ld(int ns, int order, double wmin, double wmax, double T, int norm, double norm_value,
+                       const double* coeff, int linear, int nt, long nm, const double* p, double* f,
+                       int nthreads) {
+  using R = long double;
+  auto P = make_pulse<R>(ns, order, wmin, wmax, T, nt, norm, norm_value, coeff);
+  set_scale<R>(P);
+  const auto tb = qke_table<R>(P, nt);
+  const int nth = nthreads_or_default(nthreads);
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nth)
+  for (long m = 0; m < nm; ++m) f[m] = double(qke_mode<R>(tb, linear != 0, nt, P.T / R(nt), p + 3 * m));
+}
+
+// Kinetic-equation cross-check on caller-supplied samples: E, dE/dt and A at the 2 nt + 1 RK4
+// points t_i + h dt / 2 (arrays [2nt+1][2]); the same RK4 as above.
+void orc_qke_tabulated_ld(int nt, double dt, const double* E, const double* Ed, const double* A, int linear,
+                          long nm, const double* p, double* f, int nthreads) {
+  using R = long double;
+  QkeTable<R> tb;
+  const int nh = 2 * nt + 1;
+  tb.E.assign(E, E + 2 * nh); tb.Ed.assign(Ed, Ed + 2 * nh); tb.A.assign(A, A + 2 * nh);
+  const int nth = nthreads_or_default(nthreads);
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nth)
+  for (long m = 0; m < nm; ++m) f[m] = double(qke_mode<R>(tb, linear != 0, nt, R(dt), p + 3 * m));
+}
+
+// Philox4x32-10 block.
+void orc_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out) { philox(ctr, key, out); }
+
+// DE/rand/1/bin proposal (Sec. IV B), one trial per individual.
+//   pop[N][D] -> trial[N][D]; idx[N][4] receives (a, b, c, R) when non-null.
+// Random words: key = seed; counter = (i, block, generation lo, generation hi).  Block 0 gives
+// (a, b, c, R); blocks 1.. the crossover uniforms (gene j -> block 1 + j/4, word j%4); the next
+// ceil(D/4) blocks the redraw uniforms for genes that leave [lo, hi].
+// Genes in odd blocks of n_s (the phase coefficients) wrap periodically into [lo, hi]; the
+// others are redrawn uniformly in [lo, hi].  n_s = 0 makes every gene an amplitude gene.
+// Mutation is u = a + F (b - c), each operation rounded separately: the file is compiled with
+// floating-point contraction off, so no multiply-add is fused.
+void orc_de_propose(int N, int D, int n_s, double F, double CR, double lo, double hi, uint64_t seed,
+                    int64_t gen, const double* pop, double* trial, int32_t* idx) {
+  const int nb = (D + 3) / 4;
+  for (int i = 0; i < N; ++i) {
+    const uint32_t w0 = de_word(seed, gen, i, 0, 0), w1 = de_word(seed, gen, i, 0, 1);
+    const uint32_t w2 = de_word(seed, gen, i, 0, 2), w3 = de_word(seed, gen, i, 0, 3);
+    // a, b, c: uniform over the individuals not yet excluded, ascending skip of exclusions.
+    std::vector<int> excl = {i};
+    int pick[3];
+    const uint32_t words[3] = {w0, w1, w2};
+    for (int r = 0; r < 3; ++r) {
+      int x = (int)uniform_index(words[r], (uint32_t)(N - 1 - r));
+      std::vector<int> e = excl;
+      std::sort(e.begin(), e.end());
+      for (int ex : e) if (x >= ex) ++x;
+      pick[r] = x;
+      excl.push_back(x);
+    }
+    const int Rj = (int)uniform_index(w3, (uint32_t)D);
+    if (idx) { idx[4 * i] = pick[0]; idx[4 * i + 1] = pick[1]; idx[4 * i + 2] = pick[2]; idx[4 * i + 3] = Rj; }
+    const double* a = pop + (size_t)pick[0] * D;
+    const double* b = pop + (size_t)pick[1] * D;
+    const double* c = pop + (size_t)pick[2] * D;
+    const double* x = pop + (size_t)i * D;
+    for (int j = 0; j < D; ++j) {
+      const double r = uniform_open01(de_word(seed, gen, i, 1 + j / 4, j % 4));
+      double y;
+      if (r <= CR || j == Rj) {
+        const double diff = b[j] - c[j];
+        const double step = F * diff;
+        y = a[j] + step;
+      } else {
+        y = x[j];
+      }
+      const bool phase = (n_s > 0) && ((j / n_s) % 2 == 1);
+      if (y < lo || y > hi) {
+        if (phase) {
+          const double w = hi - lo;
+          const double k = std::floor((y - lo) / w);
+          y = y - w * k;
+        } else {
+          const double r2 = uniform_open01(de_word(seed, gen, i, 1 + nb + j / 4, j % 4));
+          y = lo + (hi - lo) * r2;
+        }
+      }
+      trial[(size_t)i * D + j] = y;
+    }
+  }
+}
+
+// Selection (maximisation): individual i takes the trial iff mask[i] != 0 (or mask is null)
+// and trial_fit[i] >= fit[i].
+void orc_de_select(int N, int D, double* pop, double* fit, const double* trial, const double* trial_fit,
+                   const uint8_t* mask) {
+  for (int i = 0; i < N; ++i) {
+    if (mask && !mask[i]) continue;
+    if (trial_fit[i] >= fit[i]) {
+      for (int j = 0; j < D; ++j) pop[(size_t)i * D + j] = trial[(size_t)i * D + j];
+      fit[i] = trial_fit[i];
+    }
+  }
+}
+
+}  // extern "C"
