@@ -1,0 +1,212 @@
+/*
+ * pairopt.h -- C ABI of libpairopt.so, the gfx950 (MI355X) implementation of the pair-yield
+ * objective of Fillion-Gourdeau, Hebenstreit, Gagnon & MacLean, "Pulse shape optimization
+ * for electron-positron production in rotating fields" (arXiv:1704.08919), and of the
+ * differential-evolution loop that maximises it.
+ *
+ * Units: c = hbar = m = 1 with the charge absorbed into the fields (eE -> E, eA -> A), so the
+ * Schwinger field is 1 (Sec. II).  The field E(t) = (E_x, E_y, 0) lies in the x-y plane; p_z is
+ * the out-of-plane momentum (the paper's e_1 axis).
+ *
+ * Conventions shared by every call
+ *  - Pointers named d_* are DEVICE pointers on the current HIP device (e.g. the data pointer
+ *    of a contiguous torch tensor of the stated dtype).  They are owned by the caller; the
+ *    library never frees them and keeps none of them after the call returns.  Each one is
+ *    checked on the host before any work is enqueued: it must lie inside one device
+ *    allocation that is large enough for the documented extent, and be 8-byte aligned
+ *    (4-byte for int32/float, 2-byte for bf16, 1-byte for uint8).
+ *  - Host arrays (specs, grids, params) are read during the call only.
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  Every call is
+ *    asynchronous on that stream; results are valid once the stream reaches them.
+ *  - Work buffers that a call needs beyond its arguments are taken from the stream-ordered
+ *    memory pool (hipMallocAsync / hipFreeAsync on `stream`), so calls on different streams
+ *    never share scratch memory.
+ *  - Errors: every argument is validated before anything is enqueued.  Invalid arguments
+ *    return PO_ERR_INVALID, HIP failures PO_ERR_DEVICE; in both cases po_last_error() gives a
+ *    message (thread-local).  No C++ exception crosses the ABI.  Nothing is enqueued when a
+ *    call returns an error from validation.
+ *  - Results are bitwise reproducible: reductions use a fixed order that depends only on the
+ *    sizes of the problem, not on launch shapes or scheduling.
+ *
+ * Packed multi-pulse layout: pulse i owns nt_i table rows, starting at row sum_{j<i} nt_j,
+ * and M_i = n_x n_y n_z momentum modes, starting at sum_{j<i} M_j.  Coefficients of pulse i
+ * start at sum_{j<i} 4 n_s,j and are laid out [2 components (x, y)][2 kinds (amplitude,
+ * phase)][n_s].
+ */
+#ifndef PAIROPT_H
+#define PAIROPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PO_OK = 0,
+  PO_ERR_INVALID = -1,     /* bad argument; nothing was enqueued */
+  PO_ERR_DEVICE = -2,      /* a HIP call failed */
+  PO_ERR_NOMEM = -3,       /* the stream-ordered pool could not supply a work buffer */
+  PO_ERR_NUMERIC = -4,     /* a non-finite value was found where a finite one is required */
+  PO_ERR_UNSUPPORTED = -5  /* valid request the library does not implement */
+} po_status;
+
+enum { PO_NORM_NONE = 0, PO_NORM_PEAK = 1, PO_NORM_ENERGY = 2 };
+
+/* Pulse description (Sec. III).
+ *  n_s            B-spline coefficients per spectral function (amplitude and phase each).
+ *  order          B-spline order k in the paper's convention (degree k - 1; 4 = cubic).
+ *                 Knots: multiplicity k at omega_min and omega_max, n_s - k equidistant
+ *                 interior knots (Sec. III, clamped knot vector).  Requires 1 <= k <= n_s <= 64.
+ *  omega_min/max  band [omega_min, omega_max] of angular frequencies, in units of m.
+ *                 omega_min / Delta omega must be an integer to 1e-9, Delta omega = 2 pi / T.
+ *  T              pulse length; time runs over [-T/2, T/2]; sampled lines
+ *                 Omega_j = (N_min + j) Delta omega, j = 0..N, N = floor((omega_max -
+ *                 omega_min)/Delta omega + 1e-9) (Sec. III, Eq. field).  N + 1 <= 8192.
+ *  nt             time steps, dt = T / nt, 2 <= nt <= 2^24.
+ *  norm           PO_NORM_PEAK: scale so that max |E| over the nt + 1 step nodes equals
+ *                 norm_value; PO_NORM_ENERGY: scale so that U = int |E|^2 dt (midpoint rule)
+ *                 equals norm_value (Sec. III, Eq. energy); PO_NORM_NONE: no scaling.
+ *                 The amplitude coefficients are relative weights (Sec. IV B). */
+typedef struct {
+  int32_t n_s;
+  int32_t order;
+  double omega_min;
+  double omega_max;
+  double T;
+  int32_t nt;
+  int32_t norm;
+  double norm_value;
+} po_pulse_spec;
+
+/* Cell-centred momentum grid: p_d = lo_d + (i + 1/2)(hi_d - lo_d)/n_d, i = 0..n_d - 1; mode
+ * index = (i_z n_y + i_y) n_x + i_x.  A dimension with n_d = 1 and lo_d = hi_d is a sheet
+ * (p_d = lo_d, no measure factor), e.g. the p_z = 0 plane of the paper's 2-D problem (Sec. V B).
+ * Requires n_d >= 1, lo_d <= hi_d, and lo_d < hi_d whenever n_d > 1. */
+typedef struct {
+  int32_t n[3];
+  double lo[3];
+  double hi[3];
+} po_grid;
+
+/* Library version of this ABI (bumped on any incompatible change). */
+int po_abi_version(void);
+
+/* Thread-local message describing the last non-OK status returned on this thread. */
+const char* po_last_error(void);
+
+/* ---------------------------------------------------------------------------------------
+ * po_pulse_synth -- coefficients -> field tables (Sec. III: B-spline expansions Eq.
+ * coeff_basis_E / coeff_basis_phi, sampled spectrum, Eq. field with the Hann window Eq. hann,
+ * vector potential Eq. vector_potential with A(t_f) = 0, and the global renormalisation of
+ * Sec. IV B).
+ *  d_coeff   [sum 4 n_s] double: amplitude coefficients a^(E) are used as given; a phase
+ *            coefficient c maps to a^(phi) = pi (c + 1).
+ *  d_A       out [sum nt][2] double: scaled A(t) at the step midpoints t_i + (n + 1/2) dt.
+ *  d_E       out [sum nt][2] double or NULL: scaled E(t) at the same midpoints.
+ *  d_A_edge  out [n_pulses][2][2] double: scaled A(t_i) and A(t_f) (= 0).
+ *  d_scale   out [n_pulses] double or NULL: the applied scale factor s (E = s E_raw).
+ * Returns PO_ERR_INVALID for n_pulses < 1 or an invalid spec.
+ * --------------------------------------------------------------------------------------- */
+po_status po_pulse_synth(int32_t n_pulses, const po_pulse_spec* specs, const double* d_coeff,
+                         double* d_A, double* d_E, double* d_A_edge, double* d_scale, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * po_evolve_modes -- per-mode time evolution and projection (Sec. II A: momentum-space Dirac
+ * equation Eq. dirac_eq_mom, initial negative-energy spinors and the pair density
+ * Eq. pair_prod_homo summed over both spin labels) for ANY A table, not only a synthesised one.
+ * Each step applies the exact exponential of the Hamiltonian frozen at the step midpoint
+ * (second-order, unitary).  The Hamiltonian splits into two 2x2 blocks that are evolved
+ * separately and f is their sum, f in [0, 2].
+ *  specs     only nt and T are read (dt = T / nt).
+ *  d_A       [sum nt][2] double: A at the step midpoints.
+ *  d_A_edge  [n_pulses][2][2] double: A(t_i) (initial state) and A(t_f) (projection).
+ *  d_f       out [sum M] double or NULL: f(t_f, p) per mode.
+ *  d_J       out [n_pulses] double or NULL: J = Delta V sum_p f (Sec. IV A, Eq. opt_prob).
+ *            At least one of d_f, d_J must be non-NULL.
+ *  plan      NULL (default launch) or a plan from po_plan_create for these same pulses.
+ * --------------------------------------------------------------------------------------- */
+struct po_plan;
+po_status po_evolve_modes(int32_t n_pulses, const po_pulse_spec* specs, const po_grid* grids,
+                          const double* d_A, const double* d_A_edge, double* d_f, double* d_J,
+                          const struct po_plan* plan, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * po_pair_yield -- J = Delta V sum_p f(p) per pulse (Sec. IV A, Eq. opt_prob, midpoint rule on
+ * the cell-centred grid).  Same summation order as the fused reduction of po_evolve_modes,
+ * so both give identical bits.
+ *  d_f  [sum M] double;  d_J  out [n_pulses] double.
+ * --------------------------------------------------------------------------------------- */
+po_status po_pair_yield(int32_t n_pulses, const po_grid* grids, const double* d_f, double* d_J,
+                        void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * po_evaluate -- fused po_pulse_synth -> po_evolve_modes -> J.  Arguments as above; d_E is
+ * not produced; d_f may be NULL.
+ * --------------------------------------------------------------------------------------- */
+po_status po_evaluate(int32_t n_pulses, const po_pulse_spec* specs, const po_grid* grids,
+                      const double* d_coeff, double* d_A, double* d_A_edge, double* d_scale,
+                      double* d_f, double* d_J, const struct po_plan* plan, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Differential evolution, DE/rand/1/bin with greedy selection for maximisation (Sec. IV B).
+ *  pop, dim  population size N >= 4 and genes per individual D >= 1.
+ *  n_s       genes in odd blocks of n_s (phase coefficients) wrap periodically into [lo, hi];
+ *            the others are redrawn uniformly in [lo, hi] when a mutant leaves it.  0 makes every
+ *            gene an amplitude gene.
+ *  F, CR     differential weight in [0, 2] and crossover probability in [0, 1].
+ *  seed      key of the Philox4x32-10 counter-based generator (Salmon et al., SC'11).
+ * Random words for individual i in generation g: Philox(counter = (i, block, g_lo, g_hi),
+ * key = (seed_lo, seed_hi)).  Block 0: words -> a, b, c (distinct, != i) and the forced
+ * crossover gene R; blocks 1..ceil(D/4): crossover uniforms (gene j -> block 1 + j/4, word
+ * j%4); the next ceil(D/4) blocks: redraw uniforms.  Index in [0, n) = floor(u n / 2^32),
+ * skipping the excluded indices in ascending order; uniform real = (u + 1/2) / 2^32.
+ * The mutant a + F (b - c) rounds each operation separately (no fused multiply-add), so the
+ * proposal is bitwise reproducible on any IEEE-754 machine.
+ * --------------------------------------------------------------------------------------- */
+typedef struct {
+  int32_t pop;
+  int32_t dim;
+  int32_t n_s;
+  double F;
+  double CR;
+  double lo;
+  double hi;
+  uint64_t seed;
+} po_de_params;
+
+/* d_pop [N][D] double -> d_trial out [N][D] double; d_idx out [N][4] int32 (a, b, c, R) or NULL. */
+po_status po_de_propose(const po_de_params* prm, int64_t generation, const double* d_pop,
+                        double* d_trial, int32_t* d_idx, void* stream);
+
+/* In place: individual i takes trial i iff (d_mask == NULL or d_mask[i] != 0) and
+ * d_trial_fit[i] >= d_fit[i] (ties move; NaN never moves).  d_mask [N] uint8 or NULL. */
+po_status po_de_select(const po_de_params* prm, double* d_pop, double* d_fit, const double* d_trial,
+                       const double* d_trial_fit, const uint8_t* d_mask, void* stream);
+
+/* One generation on a population of pulses that share one spec and one grid (dim must equal
+ * 4 spec->n_s): propose -> evaluate every trial (synthesis, evolution, yield) -> select.
+ *  d_pop [N][D], d_fit [N]     in/out population and fitness (J).
+ *  d_trial [N][D], d_trial_fit [N]   out: this generation's trials and their J (kept for the
+ *                              caller, e.g. as surrogate training data).
+ * Scratch tables (N nt 16 bytes) come from the stream-ordered pool. */
+po_status po_de_generation(const po_de_params* prm, int64_t generation, const po_pulse_spec* spec,
+                           const po_grid* grid, double* d_pop, double* d_fit, double* d_trial,
+                           double* d_trial_fit, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Kernel timers (diagnostics, not part of the method).  While enabled, every po_evolve_modes /
+ * po_evaluate / po_de_generation call records a pair of HIP events on its stream around the
+ * launches of the per-mode evolution kernel.  po_timer_read waits for the recorded events,
+ * returns the summed elapsed milliseconds and the number of bracketed calls, and clears them.
+ * Timers are process-wide; enable them from one thread at a time.
+ * --------------------------------------------------------------------------------------- */
+po_status po_timer_enable(int on);
+po_status po_timer_read(double* ms_total, int64_t* calls);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAIROPT_H */

@@ -1,0 +1,83 @@
+"""ctypes loader of libpairopt.so (built in-tree by paper_1704_08919_amd.build).
+
+The product path has no fallback: if the HIP library is missing or does not load, every call
+raises, naming the file that is expected.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpairopt.so")
+
+PO_OK, PO_ERR_INVALID, PO_ERR_DEVICE, PO_ERR_NOMEM, PO_ERR_NUMERIC, PO_ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+PO_NORM_NONE, PO_NORM_PEAK, PO_NORM_ENERGY = 0, 1, 2
+
+_STATUS_NAMES = {PO_OK: "PO_OK", PO_ERR_INVALID: "PO_ERR_INVALID", PO_ERR_DEVICE: "PO_ERR_DEVICE",
+                 PO_ERR_NOMEM: "PO_ERR_NOMEM", PO_ERR_NUMERIC: "PO_ERR_NUMERIC",
+                 PO_ERR_UNSUPPORTED: "PO_ERR_UNSUPPORTED"}
+
+
+class POError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class PulseSpec(ctypes.Structure):
+    _fields_ = [("n_s", ctypes.c_int32), ("order", ctypes.c_int32), ("omega_min", ctypes.c_double),
+                ("omega_max", ctypes.c_double), ("T", ctypes.c_double), ("nt", ctypes.c_int32),
+                ("norm", ctypes.c_int32), ("norm_value", ctypes.c_double)]
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3)]
+
+
+class DEParams(ctypes.Structure):
+    _fields_ = [("pop", ctypes.c_int32), ("dim", ctypes.c_int32), ("n_s", ctypes.c_int32), ("F", ctypes.c_double),
+                ("CR", ctypes.c_double), ("lo", ctypes.c_double), ("hi", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+_P = ctypes.c_void_p
+_I32, _I64 = ctypes.c_int32, ctypes.c_int64
+
+# name -> argtypes (restype po_status = int unless stated)
+SIGNATURES = {
+    "po_abi_version": ([], ctypes.c_int),
+    "po_last_error": ([], ctypes.c_char_p),
+    "po_pulse_synth": ([_I32, ctypes.POINTER(PulseSpec), _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "po_evolve_modes": ([_I32, ctypes.POINTER(PulseSpec), ctypes.POINTER(Grid), _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "po_pair_yield": ([_I32, ctypes.POINTER(Grid), _P, _P, _P], ctypes.c_int),
+    "po_evaluate": ([_I32, ctypes.POINTER(PulseSpec), ctypes.POINTER(Grid), _P, _P, _P, _P, _P, _P, _P, _P],
+                    ctypes.c_int),
+    "po_de_propose": ([ctypes.POINTER(DEParams), _I64, _P, _P, _P, _P], ctypes.c_int),
+    "po_de_select": ([ctypes.POINTER(DEParams), _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "po_de_generation": ([ctypes.POINTER(DEParams), _I64, ctypes.POINTER(PulseSpec), ctypes.POINTER(Grid), _P, _P, _P,
+                          _P, _P], ctypes.c_int),
+    "po_timer_enable": ([ctypes.c_int], ctypes.c_int),
+    "po_timer_read": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+}
+
+_lib = None
+
+
+def load():
+    """Loads libpairopt.so once; raises if it is missing (no CPU fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                               "(run python -m paper_1704_08919_amd.build)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+    return _lib
+
+
+def check(status):
+    if status != PO_OK:
+        msg = load().po_last_error()
+        raise POError(status, msg.decode() if msg else "")

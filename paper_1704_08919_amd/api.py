@@ -1,0 +1,152 @@
+"""Python binding of the libpairopt C ABI (include/pairopt.h), one function per entry point.
+
+Argument marshalling only: every step runs in the HIP kernels of libpairopt.so.  Device
+arrays are torch tensors on the current HIP device (float64 unless stated, contiguous); work is
+enqueued on torch's current stream.  Specs and grids are dicts as produced by
+paper_1704_08919_amd.workloads.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import DEParams, Grid, PulseSpec, check, load
+
+
+def _spec_array(specs):
+    arr = (PulseSpec * len(specs))()
+    for i, s in enumerate(specs):
+        arr[i] = PulseSpec(int(s["n_s"]), int(s["order"]), float(s["omega_min"]), float(s["omega_max"]), float(s["T"]),
+                           int(s["nt"]), int(s["norm"]), float(s["norm_value"]))
+    return arr
+
+
+def _grid_array(grids):
+    arr = (Grid * len(grids))()
+    for i, g in enumerate(grids):
+        arr[i].n[:] = [int(x) for x in g["n"]]
+        arr[i].lo[:] = [float(x) for x in g["lo"]]
+        arr[i].hi[:] = [float(x) for x in g["hi"]]
+    return arr
+
+
+def _ptr(t, dtype=torch.float64):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError("expected a device (cuda/HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"expected dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _de_params(pop, dim, n_s, F, CR, lo, hi, seed):
+    return DEParams(int(pop), int(dim), int(n_s), float(F), float(CR), float(lo), float(hi), int(seed) & (2 ** 64 - 1))
+
+
+def abi_version():
+    return load().po_abi_version()
+
+
+# ------------------------------------------------------------------------------- raw ABI
+def po_pulse_synth(specs, coeff, A, A_edge, E=None, scale=None, stream=None):
+    sp = _spec_array(specs)
+    check(load().po_pulse_synth(len(specs), sp, _ptr(coeff), _ptr(A), _ptr(E), _ptr(A_edge), _ptr(scale),
+                                _stream(stream)))
+
+
+def po_evolve_modes(specs, grids, A, A_edge, f=None, J=None, stream=None):
+    sp, gr = _spec_array(specs), _grid_array(grids)
+    check(load().po_evolve_modes(len(specs), sp, gr, _ptr(A), _ptr(A_edge), _ptr(f), _ptr(J), None, _stream(stream)))
+
+
+def po_pair_yield(grids, f, J, stream=None):
+    gr = _grid_array(grids)
+    check(load().po_pair_yield(len(grids), gr, _ptr(f), _ptr(J), _stream(stream)))
+
+
+def po_evaluate(specs, grids, coeff, A, A_edge, J, scale=None, f=None, stream=None):
+    sp, gr = _spec_array(specs), _grid_array(grids)
+    check(load().po_evaluate(len(specs), sp, gr, _ptr(coeff), _ptr(A), _ptr(A_edge), _ptr(scale), _ptr(f), _ptr(J),
+                             None, _stream(stream)))
+
+
+def po_de_propose(params, generation, pop, trial, idx=None, stream=None):
+    check(load().po_de_propose(ctypes.byref(params), int(generation), _ptr(pop), _ptr(trial),
+                               _ptr(idx, torch.int32), _stream(stream)))
+
+
+def po_de_select(params, pop, fit, trial, trial_fit, mask=None, stream=None):
+    check(load().po_de_select(ctypes.byref(params), _ptr(pop), _ptr(fit), _ptr(trial), _ptr(trial_fit),
+                              _ptr(mask, torch.uint8), _stream(stream)))
+
+
+def po_de_generation(params, generation, spec, grid, pop, fit, trial, trial_fit, stream=None):
+    sp, gr = _spec_array([spec]), _grid_array([grid])
+    check(load().po_de_generation(ctypes.byref(params), int(generation), sp, gr, _ptr(pop), _ptr(fit), _ptr(trial),
+                                  _ptr(trial_fit), _stream(stream)))
+
+
+def po_timer_enable(on=True):
+    check(load().po_timer_enable(1 if on else 0))
+
+
+def po_timer_read():
+    """(summed ms of the bracketed evolution launches, number of bracketed calls); clears them."""
+    ms, n = ctypes.c_double(0.0), ctypes.c_int64(0)
+    check(load().po_timer_read(ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+# ------------------------------------------------------------------------ conveniences
+def table_rows(specs):
+    return sum(int(s["nt"]) for s in specs)
+
+
+def n_modes(grids):
+    return sum(int(g["n"][0]) * int(g["n"][1]) * int(g["n"][2]) for g in grids)
+
+
+def synth(specs, coeff, want_E=False, device="cuda"):
+    """Allocates outputs and runs po_pulse_synth: returns (A, A_edge, scale, E or None)."""
+    rows = table_rows(specs)
+    coeff = torch.as_tensor(coeff, dtype=torch.float64).reshape(-1).contiguous().to(device)
+    A = torch.empty((rows, 2), dtype=torch.float64, device=device)
+    E = torch.empty((rows, 2), dtype=torch.float64, device=device) if want_E else None
+    edge = torch.empty((len(specs), 2, 2), dtype=torch.float64, device=device)
+    scale = torch.empty(len(specs), dtype=torch.float64, device=device)
+    po_pulse_synth(specs, coeff, A, edge, E=E, scale=scale)
+    return A, edge, scale, E
+
+
+def evolve(specs, grids, A, A_edge, want_f=True, want_J=True, device="cuda"):
+    """Allocates outputs and runs po_evolve_modes: returns (f or None, J or None)."""
+    f = torch.empty(n_modes(grids), dtype=torch.float64, device=device) if want_f else None
+    J = torch.empty(len(specs), dtype=torch.float64, device=device) if want_J else None
+    po_evolve_modes(specs, grids, A, A_edge, f=f, J=J)
+    return f, J
+
+
+def evaluate(specs, grids, coeff, want_f=False, device="cuda"):
+    """Synthesis -> evolution -> J for a batch of pulses; returns (J, f or None)."""
+    rows = table_rows(specs)
+    coeff = torch.as_tensor(coeff, dtype=torch.float64).reshape(-1).contiguous().to(device)
+    A = torch.empty((rows, 2), dtype=torch.float64, device=device)
+    edge = torch.empty((len(specs), 2, 2), dtype=torch.float64, device=device)
+    J = torch.empty(len(specs), dtype=torch.float64, device=device)
+    f = torch.empty(n_modes(grids), dtype=torch.float64, device=device) if want_f else None
+    po_evaluate(specs, grids, coeff, A, edge, J, f=f)
+    return J, f
+
+
+def de_params(pop, dim, n_s, F=0.8, CR=0.9, lo=-1.0, hi=1.0, seed=0):
+    return _de_params(pop, dim, n_s, F, CR, lo, hi, seed)

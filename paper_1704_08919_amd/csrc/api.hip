@@ -1,0 +1,420 @@
+// C ABI of libpairopt.so: argument validation, per-pulse descriptors, scratch management and
+// the sequencing of the synthesis, evolution, reduction and differential-evolution kernels.
+#include <cmath>
+#include <cstdarg>
+#include <mutex>
+#include <utility>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "common.hpp"
+
+namespace po {
+
+static thread_local std::string g_error;
+
+po_status set_error(po_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return s;
+}
+
+po_status device_error(hipError_t e, const char* what) {
+  (void)hipGetLastError();
+  return set_error(e == hipErrorOutOfMemory ? PO_ERR_NOMEM : PO_ERR_DEVICE, "%s failed: %s", what,
+                   hipGetErrorString(e));
+}
+
+po_status check_device_range(const void* p, size_t bytes, size_t align, const char* name) {
+  if (!p) return set_error(PO_ERR_INVALID, "%s is NULL", name);
+  if (reinterpret_cast<uintptr_t>(p) % align) return set_error(PO_ERR_INVALID, "%s is not %zu-byte aligned", name, align);
+  hipPointerAttribute_t attr;
+  std::memset(&attr, 0, sizeof attr);
+  hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(PO_ERR_INVALID, "%s is not a device pointer (%s)", name, hipGetErrorString(e));
+  }
+  if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+    return set_error(PO_ERR_INVALID, "%s is not device memory (type %d)", name, int(attr.type));
+  int dev = -1;
+  PO_HIP(hipGetDevice(&dev));
+  if (attr.type == hipMemoryTypeDevice && attr.device != dev)
+    return set_error(PO_ERR_INVALID, "%s lives on device %d, current device is %d", name, attr.device, dev);
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  e = hipMemGetAddressRange(&base, &size, const_cast<void*>(p));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(PO_ERR_INVALID, "%s: allocation range unknown (%s)", name, hipGetErrorString(e));
+  }
+  const uintptr_t lo = reinterpret_cast<uintptr_t>(base), q = reinterpret_cast<uintptr_t>(p);
+  if (q < lo || q - lo > size || bytes > size - (q - lo))
+    return set_error(PO_ERR_INVALID, "%s: %zu bytes needed, allocation holds %zu from this pointer", name, bytes,
+                     size_t(lo + size - q));
+  return PO_OK;
+}
+
+po_status Scratch::alloc(size_t bytes, hipStream_t s) {
+  stream = s;
+  if (bytes == 0) bytes = 8;
+  hipError_t e = hipMallocAsync(&ptr, bytes, s);
+  if (e != hipSuccess) {
+    ptr = nullptr;
+    return device_error(e, "hipMallocAsync");
+  }
+  return PO_OK;
+}
+
+po_status validate_spec(const po_pulse_spec& s, int i) {
+  if (!(s.T > 0.0) || !std::isfinite(s.T)) return set_error(PO_ERR_INVALID, "spec %d: T must be finite and > 0", i);
+  if (s.nt < 2 || s.nt > (1 << 24)) return set_error(PO_ERR_INVALID, "spec %d: nt must be in [2, 2^24]", i);
+  if (s.order < 1 || s.n_s < s.order || s.n_s > kMaxNs)
+    return set_error(PO_ERR_INVALID, "spec %d: need 1 <= order <= n_s <= %d", i, kMaxNs);
+  if (!(s.omega_min >= 0.0) || !(s.omega_max > s.omega_min) || !std::isfinite(s.omega_max))
+    return set_error(PO_ERR_INVALID, "spec %d: need 0 <= omega_min < omega_max", i);
+  const double dw = 2.0 * M_PI / s.T;
+  const double r = s.omega_min / dw;
+  if (std::fabs(r - std::nearbyint(r)) > 1e-9) return set_error(PO_ERR_INVALID, "spec %d: omega_min / (2 pi / T) must be an integer", i);
+  const double nl = std::floor((s.omega_max - s.omega_min) / dw + 1e-9) + 1.0;
+  if (nl > kMaxLines) return set_error(PO_ERR_INVALID, "spec %d: %g spectral lines exceed %d", i, nl, kMaxLines);
+  if (s.norm != PO_NORM_NONE && s.norm != PO_NORM_PEAK && s.norm != PO_NORM_ENERGY)
+    return set_error(PO_ERR_INVALID, "spec %d: unknown norm %d", i, s.norm);
+  if (s.norm != PO_NORM_NONE && !(s.norm_value > 0.0 && std::isfinite(s.norm_value)))
+    return set_error(PO_ERR_INVALID, "spec %d: norm_value must be finite and > 0", i);
+  return PO_OK;
+}
+
+po_status validate_grid(const po_grid& g, int i) {
+  for (int d = 0; d < 3; ++d) {
+    if (g.n[d] < 1) return set_error(PO_ERR_INVALID, "grid %d: n[%d] must be >= 1", i, d);
+    if (!std::isfinite(g.lo[d]) || !std::isfinite(g.hi[d]) || g.lo[d] > g.hi[d])
+      return set_error(PO_ERR_INVALID, "grid %d: need finite lo[%d] <= hi[%d]", i, d, d);
+    if (g.n[d] > 1 && !(g.lo[d] < g.hi[d])) return set_error(PO_ERR_INVALID, "grid %d: n[%d] > 1 needs lo < hi", i, d);
+  }
+  const int64_t m = int64_t(g.n[0]) * g.n[1] * g.n[2];
+  if (m > (int64_t(1) << 31) * kTile / 4) return set_error(PO_ERR_INVALID, "grid %d: too many modes", i);
+  return PO_OK;
+}
+
+po_status build_batch(int32_t n, const po_pulse_spec* specs, const po_grid* grids, PulseDev* out, Batch* b) {
+  *b = Batch{};
+  b->n_pulses = n;
+  int64_t tab = 0, modes = 0, coeff = 0, spec = 0;
+  int64_t tiles = 0;
+  for (int i = 0; i < n; ++i) {
+    PulseDev d;
+    std::memset(&d, 0, sizeof d);
+    d.tab_off = tab;
+    d.mode_off = modes;
+    d.coeff_off = coeff;
+    d.spec_off = spec;
+    d.tile_off = int32_t(tiles);
+    if (specs) {
+      const po_pulse_spec& s = specs[i];
+      d.nt = s.nt;
+      d.ns = s.n_s;
+      d.order = s.order;
+      d.T = s.T;
+      d.dt = s.T / double(s.nt);
+      d.dw = 2.0 * M_PI / s.T;
+      d.wmin = s.omega_min;
+      d.wmax = s.omega_max;
+      d.nmin = int32_t(std::nearbyint(s.omega_min / d.dw));
+      d.nlines = int32_t(std::floor((s.omega_max - s.omega_min) / d.dw + 1e-9)) + 1;
+      d.norm = s.norm;
+      d.norm_value = s.norm_value;
+      d.stat_blocks = s.norm == PO_NORM_NONE ? 0 : (s.nt + 1 + 255) / 256;
+      tab += s.nt;
+      coeff += 4 * int64_t(s.n_s);
+      spec += 4 * int64_t(d.nlines);
+      b->max_nt = std::max(b->max_nt, s.nt);
+      b->max_stat_blocks = std::max(b->max_stat_blocks, d.stat_blocks);
+      if (i > 0 && (s.nt != specs[0].nt || s.T != specs[0].T)) b->uniform = false;
+    }
+    if (grids) {
+      const po_grid& g = grids[i];
+      double dv = 1.0;
+      for (int k = 0; k < 3; ++k) {
+        d.n[k] = g.n[k];
+        d.lo[k] = g.lo[k];
+        const bool sheet = g.n[k] == 1 && g.lo[k] == g.hi[k];
+        d.dp[k] = sheet ? 0.0 : (g.hi[k] - g.lo[k]) / double(g.n[k]);
+        if (!sheet) dv *= d.dp[k];
+      }
+      d.dv = dv;
+      const int64_t m = int64_t(g.n[0]) * g.n[1] * g.n[2];
+      d.ntiles = int32_t((m + kTile - 1) / kTile);
+      modes += m;
+      tiles += d.ntiles;
+      b->max_tiles = std::max(b->max_tiles, d.ntiles);
+      if (i > 0 && std::memcmp(&g, &grids[0], sizeof g) != 0) b->uniform = false;
+    }
+    out[i] = d;
+  }
+  if (tiles > (int64_t(1) << 31) - 1) return set_error(PO_ERR_INVALID, "batch has too many tiles");
+  b->total_rows = tab;
+  b->total_modes = modes;
+  b->total_coeff = coeff;
+  b->total_spec = spec;
+  b->total_tiles = int32_t(tiles);
+  return PO_OK;
+}
+
+namespace {
+
+po_status check_specs(int32_t n, const po_pulse_spec* specs) {
+  if (!specs) return set_error(PO_ERR_INVALID, "specs is NULL");
+  for (int i = 0; i < n; ++i) PO_TRY(validate_spec(specs[i], i));
+  return PO_OK;
+}
+
+po_status check_grids(int32_t n, const po_grid* grids) {
+  if (!grids) return set_error(PO_ERR_INVALID, "grids is NULL");
+  for (int i = 0; i < n; ++i) PO_TRY(validate_grid(grids[i], i));
+  return PO_OK;
+}
+
+// Uploads the descriptors into a stream-ordered buffer.
+po_status upload(const std::vector<PulseDev>& h, Scratch& sc, hipStream_t s) {
+  PO_TRY(sc.alloc(sizeof(PulseDev) * h.size(), s));
+  PO_HIP(hipMemcpyAsync(sc.ptr, h.data(), sizeof(PulseDev) * h.size(), hipMemcpyHostToDevice, s));
+  return PO_OK;
+}
+
+po_status synth_impl(int32_t n, const po_pulse_spec* specs, const double* d_coeff, double* d_A, double* d_E,
+                     double* d_A_edge, double* d_scale, hipStream_t s, const Batch& b, const PulseDev* d_desc) {
+  Scratch spec, part, scl;
+  PO_TRY(spec.alloc(sizeof(double) * b.total_spec, s));
+  PO_TRY(part.alloc(sizeof(double) * size_t(std::max(1, b.max_stat_blocks)) * n, s));
+  PO_TRY(scl.alloc(sizeof(double) * n, s));
+  return launch_synth(b, d_desc, d_coeff, static_cast<double*>(spec.ptr), static_cast<double*>(part.ptr),
+                      static_cast<double*>(scl.ptr), d_A, d_E, d_A_edge, d_scale, s);
+}
+
+// Event pairs bracketing evolution launches while timers are enabled.
+std::mutex g_timer_mu;
+bool g_timer_on = false;
+std::vector<std::pair<hipEvent_t, hipEvent_t>> g_timer_events;
+
+po_status timer_record(hipStream_t s, hipEvent_t* ev) {
+  PO_HIP(hipEventCreate(ev));
+  PO_HIP(hipEventRecord(*ev, s));
+  return PO_OK;
+}
+
+po_status evolve_impl(const Batch& b, const PulseDev* d_desc, const double* d_A, const double* d_A_edge, double* d_f,
+                      double* d_J, hipStream_t s) {
+  Scratch tiles;
+  double* d_tiles = nullptr;
+  if (d_J) {
+    PO_TRY(tiles.alloc(sizeof(double) * size_t(b.total_tiles), s));
+    d_tiles = static_cast<double*>(tiles.ptr);
+  }
+  bool timed;
+  {
+    std::lock_guard<std::mutex> lk(g_timer_mu);
+    timed = g_timer_on;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (timed) PO_TRY(timer_record(s, &e0));
+  PO_TRY(launch_evolve(b, d_desc, d_A, d_A_edge, d_f, d_tiles, s));
+  if (timed) {
+    PO_TRY(timer_record(s, &e1));
+    std::lock_guard<std::mutex> lk(g_timer_mu);
+    g_timer_events.emplace_back(e0, e1);
+  }
+  if (d_J) PO_TRY(launch_yield_from_tiles(b, d_desc, d_tiles, d_J, s));
+  return PO_OK;
+}
+
+}  // namespace
+}  // namespace po
+
+using namespace po;
+
+extern "C" {
+
+int po_abi_version(void) { return 1; }
+
+const char* po_last_error(void) { return g_error.c_str(); }
+
+po_status po_pulse_synth(int32_t n, const po_pulse_spec* specs, const double* d_coeff, double* d_A, double* d_E,
+                         double* d_A_edge, double* d_scale, void* stream) {
+  if (n < 1) return set_error(PO_ERR_INVALID, "n_pulses must be >= 1");
+  PO_TRY(check_specs(n, specs));
+  std::vector<PulseDev> h(n);
+  Batch b;
+  PO_TRY(build_batch(n, specs, nullptr, h.data(), &b));
+  PO_TRY(check_device_range(d_coeff, sizeof(double) * b.total_coeff, 8, "d_coeff"));
+  PO_TRY(check_device_range(d_A, sizeof(double) * 2 * b.total_rows, 8, "d_A"));
+  if (d_E) PO_TRY(check_device_range(d_E, sizeof(double) * 2 * b.total_rows, 8, "d_E"));
+  PO_TRY(check_device_range(d_A_edge, sizeof(double) * 4 * n, 8, "d_A_edge"));
+  if (d_scale) PO_TRY(check_device_range(d_scale, sizeof(double) * n, 8, "d_scale"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Scratch desc;
+  PO_TRY(upload(h, desc, s));
+  return synth_impl(n, specs, d_coeff, d_A, d_E, d_A_edge, d_scale, s, b, static_cast<PulseDev*>(desc.ptr));
+}
+
+po_status po_evolve_modes(int32_t n, const po_pulse_spec* specs, const po_grid* grids, const double* d_A,
+                          const double* d_A_edge, double* d_f, double* d_J, const struct po_plan* plan, void* stream) {
+  if (n < 1) return set_error(PO_ERR_INVALID, "n_pulses must be >= 1");
+  if (plan) return set_error(PO_ERR_UNSUPPORTED, "plans are not supported by this build");
+  PO_TRY(check_specs(n, specs));
+  PO_TRY(check_grids(n, grids));
+  if (!d_f && !d_J) return set_error(PO_ERR_INVALID, "at least one of d_f, d_J must be non-NULL");
+  std::vector<PulseDev> h(n);
+  Batch b;
+  PO_TRY(build_batch(n, specs, grids, h.data(), &b));
+  PO_TRY(check_device_range(d_A, sizeof(double) * 2 * b.total_rows, 8, "d_A"));
+  PO_TRY(check_device_range(d_A_edge, sizeof(double) * 4 * n, 8, "d_A_edge"));
+  if (d_f) PO_TRY(check_device_range(d_f, sizeof(double) * b.total_modes, 8, "d_f"));
+  if (d_J) PO_TRY(check_device_range(d_J, sizeof(double) * n, 8, "d_J"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Scratch desc;
+  PO_TRY(upload(h, desc, s));
+  return evolve_impl(b, static_cast<PulseDev*>(desc.ptr), d_A, d_A_edge, d_f, d_J, s);
+}
+
+po_status po_pair_yield(int32_t n, const po_grid* grids, const double* d_f, double* d_J, void* stream) {
+  if (n < 1) return set_error(PO_ERR_INVALID, "n_pulses must be >= 1");
+  PO_TRY(check_grids(n, grids));
+  std::vector<PulseDev> h(n);
+  Batch b;
+  PO_TRY(build_batch(n, nullptr, grids, h.data(), &b));
+  PO_TRY(check_device_range(d_f, sizeof(double) * b.total_modes, 8, "d_f"));
+  PO_TRY(check_device_range(d_J, sizeof(double) * n, 8, "d_J"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Scratch desc, tiles;
+  PO_TRY(upload(h, desc, s));
+  PO_TRY(tiles.alloc(sizeof(double) * size_t(b.total_tiles), s));
+  const PulseDev* d_desc = static_cast<PulseDev*>(desc.ptr);
+  PO_TRY(launch_tile_sums_from_f(b, d_desc, d_f, static_cast<double*>(tiles.ptr), s));
+  return launch_yield_from_tiles(b, d_desc, static_cast<double*>(tiles.ptr), d_J, s);
+}
+
+po_status po_evaluate(int32_t n, const po_pulse_spec* specs, const po_grid* grids, const double* d_coeff, double* d_A,
+                      double* d_A_edge, double* d_scale, double* d_f, double* d_J, const struct po_plan* plan,
+                      void* stream) {
+  if (n < 1) return set_error(PO_ERR_INVALID, "n_pulses must be >= 1");
+  if (plan) return set_error(PO_ERR_UNSUPPORTED, "plans are not supported by this build");
+  PO_TRY(check_specs(n, specs));
+  PO_TRY(check_grids(n, grids));
+  if (!d_f && !d_J) return set_error(PO_ERR_INVALID, "at least one of d_f, d_J must be non-NULL");
+  std::vector<PulseDev> h(n);
+  Batch b;
+  PO_TRY(build_batch(n, specs, grids, h.data(), &b));
+  PO_TRY(check_device_range(d_coeff, sizeof(double) * b.total_coeff, 8, "d_coeff"));
+  PO_TRY(check_device_range(d_A, sizeof(double) * 2 * b.total_rows, 8, "d_A"));
+  PO_TRY(check_device_range(d_A_edge, sizeof(double) * 4 * n, 8, "d_A_edge"));
+  if (d_scale) PO_TRY(check_device_range(d_scale, sizeof(double) * n, 8, "d_scale"));
+  if (d_f) PO_TRY(check_device_range(d_f, sizeof(double) * b.total_modes, 8, "d_f"));
+  if (d_J) PO_TRY(check_device_range(d_J, sizeof(double) * n, 8, "d_J"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Scratch desc;
+  PO_TRY(upload(h, desc, s));
+  const PulseDev* d_desc = static_cast<PulseDev*>(desc.ptr);
+  PO_TRY(synth_impl(n, specs, d_coeff, d_A, nullptr, d_A_edge, d_scale, s, b, d_desc));
+  return evolve_impl(b, d_desc, d_A, d_A_edge, d_f, d_J, s);
+}
+
+po_status po_timer_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_timer_mu);
+  g_timer_on = on != 0;
+  return PO_OK;
+}
+
+po_status po_timer_read(double* ms_total, int64_t* calls) {
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  {
+    std::lock_guard<std::mutex> lk(g_timer_mu);
+    ev.swap(g_timer_events);
+  }
+  double total = 0.0;
+  po_status st = PO_OK;
+  for (auto& p : ev) {
+    float ms = 0.0f;
+    hipError_t e = hipEventSynchronize(p.second);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, p.first, p.second);
+    if (e != hipSuccess && st == PO_OK) st = device_error(e, "hipEventElapsedTime");
+    total += ms;
+    (void)hipEventDestroy(p.first);
+    (void)hipEventDestroy(p.second);
+  }
+  if (ms_total) *ms_total = total;
+  if (calls) *calls = int64_t(ev.size());
+  return st;
+}
+
+static po_status check_de(const po_de_params* p) {
+  if (!p) return set_error(PO_ERR_INVALID, "params is NULL");
+  if (p->pop < 4) return set_error(PO_ERR_INVALID, "pop must be >= 4");
+  if (p->dim < 1) return set_error(PO_ERR_INVALID, "dim must be >= 1");
+  if (p->n_s < 0) return set_error(PO_ERR_INVALID, "n_s must be >= 0");
+  if (!(p->F >= 0.0 && p->F <= 2.0)) return set_error(PO_ERR_INVALID, "F must be in [0, 2]");
+  if (!(p->CR >= 0.0 && p->CR <= 1.0)) return set_error(PO_ERR_INVALID, "CR must be in [0, 1]");
+  if (!(p->lo < p->hi) || !std::isfinite(p->lo) || !std::isfinite(p->hi))
+    return set_error(PO_ERR_INVALID, "need finite lo < hi");
+  return PO_OK;
+}
+
+po_status po_de_propose(const po_de_params* prm, int64_t generation, const double* d_pop, double* d_trial,
+                        int32_t* d_idx, void* stream) {
+  PO_TRY(check_de(prm));
+  const size_t nd = size_t(prm->pop) * prm->dim;
+  PO_TRY(check_device_range(d_pop, sizeof(double) * nd, 8, "d_pop"));
+  PO_TRY(check_device_range(d_trial, sizeof(double) * nd, 8, "d_trial"));
+  if (d_idx) PO_TRY(check_device_range(d_idx, sizeof(int32_t) * 4 * prm->pop, 4, "d_idx"));
+  return launch_de_propose(*prm, generation, d_pop, d_trial, d_idx, static_cast<hipStream_t>(stream));
+}
+
+po_status po_de_select(const po_de_params* prm, double* d_pop, double* d_fit, const double* d_trial,
+                       const double* d_trial_fit, const uint8_t* d_mask, void* stream) {
+  PO_TRY(check_de(prm));
+  const size_t nd = size_t(prm->pop) * prm->dim;
+  PO_TRY(check_device_range(d_pop, sizeof(double) * nd, 8, "d_pop"));
+  PO_TRY(check_device_range(d_fit, sizeof(double) * prm->pop, 8, "d_fit"));
+  PO_TRY(check_device_range(d_trial, sizeof(double) * nd, 8, "d_trial"));
+  PO_TRY(check_device_range(d_trial_fit, sizeof(double) * prm->pop, 8, "d_trial_fit"));
+  if (d_mask) PO_TRY(check_device_range(d_mask, prm->pop, 1, "d_mask"));
+  return launch_de_select(*prm, d_pop, d_fit, d_trial, d_trial_fit, d_mask, static_cast<hipStream_t>(stream));
+}
+
+po_status po_de_generation(const po_de_params* prm, int64_t generation, const po_pulse_spec* spec, const po_grid* grid,
+                           double* d_pop, double* d_fit, double* d_trial, double* d_trial_fit, void* stream) {
+  PO_TRY(check_de(prm));
+  PO_TRY(check_specs(1, spec));
+  PO_TRY(check_grids(1, grid));
+  if (prm->dim != 4 * spec->n_s) return set_error(PO_ERR_INVALID, "dim must equal 4 n_s");
+  const int32_t n = prm->pop;
+  const size_t nd = size_t(n) * prm->dim;
+  PO_TRY(check_device_range(d_pop, sizeof(double) * nd, 8, "d_pop"));
+  PO_TRY(check_device_range(d_fit, sizeof(double) * n, 8, "d_fit"));
+  PO_TRY(check_device_range(d_trial, sizeof(double) * nd, 8, "d_trial"));
+  PO_TRY(check_device_range(d_trial_fit, sizeof(double) * n, 8, "d_trial_fit"));
+  std::vector<po_pulse_spec> specs(n, *spec);
+  std::vector<po_grid> grids(n, *grid);
+  std::vector<PulseDev> h(n);
+  Batch b;
+  PO_TRY(build_batch(n, specs.data(), grids.data(), h.data(), &b));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Scratch desc, tab, edge;
+  PO_TRY(upload(h, desc, s));
+  PO_TRY(tab.alloc(sizeof(double) * 2 * b.total_rows, s));
+  PO_TRY(edge.alloc(sizeof(double) * 4 * n, s));
+  const PulseDev* d_desc = static_cast<PulseDev*>(desc.ptr);
+  double* d_A = static_cast<double*>(tab.ptr);
+  double* d_edge = static_cast<double*>(edge.ptr);
+  PO_TRY(launch_de_propose(*prm, generation, d_pop, d_trial, nullptr, s));
+  PO_TRY(synth_impl(n, specs.data(), d_trial, d_A, nullptr, d_edge, nullptr, s, b, d_desc));
+  PO_TRY(evolve_impl(b, d_desc, d_A, d_edge, nullptr, d_trial_fit, s));
+  return launch_de_select(*prm, d_pop, d_fit, d_trial, d_trial_fit, nullptr, s);
+}
+
+}  // extern "C"

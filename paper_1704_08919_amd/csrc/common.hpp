@@ -1,0 +1,94 @@
+// Internal declarations shared by the translation units of libpairopt.so (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "pairopt.h"
+
+namespace po {
+
+// ------------------------------------------------------------------------------- errors
+po_status set_error(po_status s, const char* fmt, ...);
+po_status device_error(hipError_t e, const char* what);
+
+#define PO_HIP(call)                                                  \
+  do {                                                                \
+    hipError_t e__ = (call);                                          \
+    if (e__ != hipSuccess) return ::po::device_error(e__, #call);     \
+  } while (0)
+
+#define PO_TRY(expr)                          \
+  do {                                        \
+    po_status s__ = (expr);                   \
+    if (s__ != PO_OK) return s__;             \
+  } while (0)
+
+// Host-side check that [p, p + bytes) lies in one device allocation of the current device.
+po_status check_device_range(const void* p, size_t bytes, size_t align, const char* name);
+
+// ---------------------------------------------------------------- per-pulse descriptors
+// One record per pulse, uploaded to device memory for every multi-pulse launch.
+constexpr int kTile = 256;        // momentum modes per reduction tile (fixed: sets the sum order)
+constexpr int kMaxLines = 8192;   // spectral lines per pulse
+constexpr int kMaxNs = 64;        // B-spline coefficients per spectral function
+
+struct PulseDev {
+  int64_t tab_off;    // first table row (rows of 2 doubles)
+  int64_t mode_off;   // first mode in the packed f array
+  int64_t coeff_off;  // first coefficient (doubles)
+  int64_t spec_off;   // first spectral record in the scratch spectra (4 doubles per line)
+  int32_t nt, ns, order, nlines;
+  int32_t nmin, norm, stat_blocks, pad0;
+  int32_t n[3];
+  int32_t tile_off;   // first reduction tile of this pulse in the batch
+  int32_t ntiles;
+  int32_t pad1;
+  double T, dt, dw, wmin, wmax, norm_value, dv;
+  double lo[3], dp[3];  // p_d = lo_d + (i + 1/2) dp_d; dp_d = 0 for a sheet (then p_d = lo_d)
+};
+
+struct Batch {
+  int32_t n_pulses = 0;
+  int64_t total_rows = 0, total_modes = 0, total_coeff = 0, total_spec = 0;
+  int32_t total_tiles = 0;
+  int32_t max_tiles = 0;       // largest per-pulse tile count
+  int32_t max_stat_blocks = 0; // largest per-pulse block count of the field statistics pass
+  int32_t max_nt = 0;
+  bool uniform = true;         // all pulses share nt/grid (lets kernels skip the binary search)
+};
+
+po_status validate_spec(const po_pulse_spec& s, int i);
+po_status validate_grid(const po_grid& g, int i);
+// Fills host descriptors; specs/grids may be NULL when a call does not need them.
+po_status build_batch(int32_t n, const po_pulse_spec* specs, const po_grid* grids, PulseDev* out,
+                      Batch* b);
+
+// Stream-ordered scratch buffer released on destruction (hipFreeAsync on the same stream).
+struct Scratch {
+  void* ptr = nullptr;
+  hipStream_t stream = nullptr;
+  ~Scratch() {
+    if (ptr) (void)hipFreeAsync(ptr, stream);
+  }
+  po_status alloc(size_t bytes, hipStream_t s);
+};
+
+// --------------------------------------------------------------------- kernel launchers
+po_status launch_synth(const Batch& b, const PulseDev* d_desc, const double* d_coeff, double* d_spec,
+                       double* d_part, double* d_scale_ws, double* d_A, double* d_E, double* d_A_edge,
+                       double* d_scale_out, hipStream_t s);
+po_status launch_evolve(const Batch& b, const PulseDev* d_desc, const double* d_A, const double* d_A_edge,
+                        double* d_f, double* d_tile_sums, hipStream_t s);
+po_status launch_tile_sums_from_f(const Batch& b, const PulseDev* d_desc, const double* d_f,
+                                  double* d_tile_sums, hipStream_t s);
+po_status launch_yield_from_tiles(const Batch& b, const PulseDev* d_desc, const double* d_tile_sums,
+                                  double* d_J, hipStream_t s);
+po_status launch_de_propose(const po_de_params& p, int64_t gen, const double* d_pop, double* d_trial,
+                            int32_t* d_idx, hipStream_t s);
+po_status launch_de_select(const po_de_params& p, double* d_pop, double* d_fit, const double* d_trial,
+                           const double* d_trial_fit, const uint8_t* d_mask, hipStream_t s);
+
+}  // namespace po

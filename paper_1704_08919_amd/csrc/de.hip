@@ -1,0 +1,140 @@
+// Differential evolution DE/rand/1/bin (Sec. IV B of arXiv:1704.08919) on the GPU.
+//
+// Random numbers: Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of the 4x32
+// Philox S-box with multipliers 0xD2511F53 / 0xCD9E8D57 and Weyl key increments 0x9E3779B9 /
+// 0xBB67AE85.  Counter = (individual, block, generation lo, generation hi), key = seed.
+// The arithmetic of a proposal rounds every operation separately (contraction is off in this
+// file), so trials are identical bit for bit to any IEEE-754 evaluation of the same rules.
+#include "common.hpp"
+
+#pragma clang fp contract(off)
+
+namespace po {
+namespace {
+
+struct U4 {
+  uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t m0 = uint64_t(0xD2511F53u) * c.x;
+    const uint64_t m1 = uint64_t(0xCD9E8D57u) * c.z;
+    c = U4{uint32_t(m1 >> 32) ^ c.y ^ k0, uint32_t(m1), uint32_t(m0 >> 32) ^ c.w ^ k1, uint32_t(m0)};
+  }
+  return c;
+}
+
+__device__ __forceinline__ uint32_t word(const U4& u, int w) {
+  return w == 0 ? u.x : w == 1 ? u.y : w == 2 ? u.z : u.w;
+}
+
+__device__ __forceinline__ uint32_t index_below(uint32_t u, uint32_t n) {
+  return uint32_t((uint64_t(u) * n) >> 32);
+}
+
+__device__ __forceinline__ double open01(uint32_t u) { return (double(u) + 0.5) * (1.0 / 4294967296.0); }
+
+__global__ void __launch_bounds__(128) k_de_propose(po_de_params prm, int64_t gen, const double* __restrict__ pop,
+                                                    double* __restrict__ trial, int32_t* __restrict__ idx) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int N = prm.pop, D = prm.dim;
+  if (i >= N) return;
+  const uint32_t k0 = uint32_t(prm.seed), k1 = uint32_t(prm.seed >> 32);
+  const uint32_t g0 = uint32_t(uint64_t(gen)), g1 = uint32_t(uint64_t(gen) >> 32);
+  const U4 r0 = philox4x32_10(U4{uint32_t(i), 0u, g0, g1}, k0, k1);
+  // a, b, c: uniform over the individuals not yet excluded; exclusions skipped in ascending order.
+  int ex[4] = {i, 0, 0, 0};
+  int nex = 1;
+  int pick[3];
+  const uint32_t w3[3] = {r0.x, r0.y, r0.z};
+  for (int r = 0; r < 3; ++r) {
+    int x = int(index_below(w3[r], uint32_t(N - 1 - r)));
+    int srt[4];
+    for (int q = 0; q < nex; ++q) srt[q] = ex[q];
+    for (int q = 1; q < nex; ++q)  // insertion sort of at most 3 values
+      for (int z = q; z > 0 && srt[z - 1] > srt[z]; --z) {
+        const int t = srt[z]; srt[z] = srt[z - 1]; srt[z - 1] = t;
+      }
+    for (int q = 0; q < nex; ++q)
+      if (x >= srt[q]) ++x;
+    pick[r] = x;
+    ex[nex++] = x;
+  }
+  const int R = int(index_below(r0.w, uint32_t(D)));
+  if (idx) {
+    idx[4 * i + 0] = pick[0];
+    idx[4 * i + 1] = pick[1];
+    idx[4 * i + 2] = pick[2];
+    idx[4 * i + 3] = R;
+  }
+  const double* a = pop + size_t(pick[0]) * D;
+  const double* b = pop + size_t(pick[1]) * D;
+  const double* c = pop + size_t(pick[2]) * D;
+  const double* x = pop + size_t(i) * D;
+  double* y = trial + size_t(i) * D;
+  const int nb = (D + 3) / 4;
+  U4 cr{}, rd{};
+  for (int j = 0; j < D; ++j) {
+    if ((j & 3) == 0) {
+      cr = philox4x32_10(U4{uint32_t(i), uint32_t(1 + j / 4), g0, g1}, k0, k1);
+      rd = philox4x32_10(U4{uint32_t(i), uint32_t(1 + nb + j / 4), g0, g1}, k0, k1);
+    }
+    const double r = open01(word(cr, j & 3));
+    double v;
+    if (r <= prm.CR || j == R) {
+      const double diff = b[j] - c[j];
+      const double st = prm.F * diff;
+      v = a[j] + st;
+    } else {
+      v = x[j];
+    }
+    if (v < prm.lo || v > prm.hi) {
+      const bool phase = prm.n_s > 0 && ((j / prm.n_s) & 1);
+      const double w = prm.hi - prm.lo;
+      if (phase) {
+        const double k = floor((v - prm.lo) / w);
+        v = v - w * k;
+      } else {
+        v = prm.lo + w * open01(word(rd, j & 3));
+      }
+    }
+    y[j] = v;
+  }
+}
+
+__global__ void __launch_bounds__(128) k_de_select(po_de_params prm, double* __restrict__ pop, double* __restrict__ fit,
+                                                   const double* __restrict__ trial, const double* __restrict__ tfit,
+                                                   const uint8_t* __restrict__ mask) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= prm.pop) return;
+  if (mask && !mask[i]) return;
+  if (tfit[i] >= fit[i]) {
+    for (int j = 0; j < prm.dim; ++j) pop[size_t(i) * prm.dim + j] = trial[size_t(i) * prm.dim + j];
+    fit[i] = tfit[i];
+  }
+}
+
+}  // namespace
+
+po_status launch_de_propose(const po_de_params& p, int64_t gen, const double* d_pop, double* d_trial, int32_t* d_idx,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_de_propose, dim3((p.pop + 127) / 128), dim3(128), 0, s, p, gen, d_pop, d_trial, d_idx);
+  PO_HIP(hipGetLastError());
+  return PO_OK;
+}
+
+po_status launch_de_select(const po_de_params& p, double* d_pop, double* d_fit, const double* d_trial,
+                           const double* d_trial_fit, const uint8_t* d_mask, hipStream_t s) {
+  hipLaunchKernelGGL(k_de_select, dim3((p.pop + 127) / 128), dim3(128), 0, s, p, d_pop, d_fit, d_trial, d_trial_fit,
+                     d_mask);
+  PO_HIP(hipGetLastError());
+  return PO_OK;
+}
+
+}  // namespace po

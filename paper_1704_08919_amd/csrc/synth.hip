@@ -1,0 +1,250 @@
+// Pulse synthesis on gfx950: B-spline spectra -> field statistics -> scale -> A/E tables.
+//
+// Sec. III of arXiv:1704.08919: the spectral density and phase of each component are B-spline
+// expansions; the field is a Hann-windowed cosine sum over the lines Omega_j = (N_min + j) dw,
+// dw = 2 pi / T; A(t) is its antiderivative with A(t_f) = 0.  The global renormalisation of
+// Sec. IV B scales E and A by one factor per pulse (peak |E| or energy U).
+//
+// Time is indexed by half-steps h: t = -T/2 + h dt / 2 (h even: step nodes, h odd: midpoints).
+// Every line frequency is an integer multiple k of dw, so the phase Omega_k t equals
+// pi k (h - nt) / nt exactly; it is reduced modulo 2 in integers and evaluated with sincospi,
+// which keeps all trig arguments in [0, 2) whatever T is.
+#include "common.hpp"
+
+namespace po {
+namespace {
+
+// Knot w_i of the clamped knot vector (multiplicity k at both ends, equidistant interior knots).
+__device__ __forceinline__ double knot(int i, int k, int ns, double wmin, double wmax) {
+  if (i < k) return wmin;
+  if (i >= ns) return wmax;
+  const int nb = ns - k + 2;  // breakpoints
+  return wmin + (wmax - wmin) * double(i - k + 1) / double(nb - 1);
+}
+
+// All basis values b_i^{(k)}(w), i < ns, by raising the order of the indicator functions
+// (Cox-de Boor recursion, 0/0 := 0); the last non-empty span is closed at omega_max.
+__device__ void bspline_all(int k, int ns, double wmin, double wmax, double w, double* b /*[ns+k]*/) {
+  const int nk = ns + k;
+  for (int i = 0; i < nk - 1; ++i) {
+    const double a = knot(i, k, ns, wmin, wmax), c = knot(i + 1, k, ns, wmin, wmax);
+    b[i] = (a <= w && w < c) ? 1.0 : 0.0;
+    if (w == wmax && a < c && c == wmax) b[i] = 1.0;
+  }
+  for (int r = 2; r <= k; ++r) {
+    for (int i = 0; i < nk - r; ++i) {
+      const double ti = knot(i, k, ns, wmin, wmax), tir1 = knot(i + r - 1, k, ns, wmin, wmax);
+      const double ti1 = knot(i + 1, k, ns, wmin, wmax), tir = knot(i + r, k, ns, wmin, wmax);
+      double v = 0.0;
+      if (tir1 != ti) v += (w - ti) / (tir1 - ti) * b[i];
+      if (tir != ti1) v += (tir - w) / (tir - ti1) * b[i + 1];
+      b[i] = v;
+    }
+  }
+}
+
+// One block per pulse; each thread fills lines j.  Output per line: (E cos Phi, E sin Phi) for x
+// and y, i.e. spec[off + 4 j + {0,1,2,3}] = (cEx, sEx, cEy, sEy).
+__global__ void __launch_bounds__(128) k_spectra(const PulseDev* __restrict__ desc,
+                                                 const double* __restrict__ coeff, double* __restrict__ spec) {
+  const PulseDev d = desc[blockIdx.x];
+  const double* a = coeff + d.coeff_off;
+  double b[2 * kMaxNs + 2];
+  for (int j = threadIdx.x; j < d.nlines; j += blockDim.x) {
+    const double w = double(d.nmin + j) * d.dw;
+    bspline_all(d.order, d.ns, d.wmin, d.wmax, w, b);
+    double out[4];
+    for (int l = 0; l < 2; ++l) {
+      double E = 0.0, ph = 0.0;
+      for (int i = 0; i < d.ns; ++i) {
+        E += a[(l * 2 + 0) * d.ns + i] * b[i];
+        ph += M_PI * (a[(l * 2 + 1) * d.ns + i] + 1.0) * b[i];
+      }
+      double sp, cp;
+      sincos(ph, &sp, &cp);
+      out[2 * l] = E * cp;
+      out[2 * l + 1] = E * sp;
+    }
+    double4* dst = reinterpret_cast<double4*>(spec + d.spec_off) + j;
+    *dst = make_double4(out[0], out[1], out[2], out[3]);
+  }
+}
+
+// sincos(pi k (h - nt) / nt) with the argument reduced exactly in integers.
+__device__ __forceinline__ void line_phase(int64_t k, int64_t hm, int64_t two_nt, double inv_nt, double* s, double* c) {
+  int64_t r = (k * hm) % two_nt;
+  if (r < 0) r += two_nt;
+  sincospi(double(r) * inv_nt, s, c);
+}
+
+// Unscaled field (want_E) and potential (want_A) at half-step index h.
+__device__ void field_at(const PulseDev& d, const double4* __restrict__ sp, int64_t h, bool want_E, bool want_A,
+                         double E[2], double A[2]) {
+  const int64_t nt = d.nt, two_nt = 2 * int64_t(d.nt);
+  const int64_t hm = h - nt;
+  const double inv_nt = 1.0 / double(d.nt);
+  double ex = 0.0, ey = 0.0, ax = 0.0, ay = 0.0;
+  double sd = 0.0, cd = 1.0;  // Delta omega t
+  if (want_A) line_phase(1, hm, two_nt, inv_nt, &sd, &cd);
+  const double tmf = double(h - two_nt) * (0.5 * d.dt);  // t - t_f
+  for (int j = 0; j < d.nlines; ++j) {
+    const int64_t k = int64_t(d.nmin) + j;
+    double s, c;
+    line_phase(k, hm, two_nt, inv_nt, &s, &c);
+    const double4 q = sp[j];  // (cEx, sEx, cEy, sEy)
+    if (want_E) {
+      ex += q.x * c + q.y * s;
+      ey += q.z * c + q.w * s;
+    }
+    if (want_A) {
+      // E_j [I(Om, -Phi)/2 + I(dw + Om, -Phi)/4 + I(dw - Om, +Phi)/4], I(w, phi; t) = int_{t_f}^t cos(w s + phi) ds
+      //   = [sin(w t + phi) - (-1)^k' sin(phi)] / w with w t_f = k' pi; (t - t_f) cos(phi) when w = 0.
+      const double sgn = (k & 1) ? -1.0 : 1.0;
+      const double cp = c * cd - s * sd, spp = s * cd + c * sd;  // (Om + dw) t
+      const double cm = cd * c + sd * s, smm = sd * c - cd * s;  // (dw - Om) t
+      const double om = double(k) * d.dw, wp = double(k + 1) * d.dw, wm = double(1 - k) * d.dw;
+      double tx, ty;
+      // main line
+      if (k == 0) {
+        tx = 0.5 * tmf * q.x;
+        ty = 0.5 * tmf * q.z;
+      } else {
+        tx = 0.5 * (q.x * s - q.y * c + sgn * q.y) / om;
+        ty = 0.5 * (q.z * s - q.w * c + sgn * q.w) / om;
+      }
+      // upper side line dw + Om (never zero)
+      tx += 0.25 * (q.x * spp - q.y * cp - sgn * q.y) / wp;
+      ty += 0.25 * (q.z * spp - q.w * cp - sgn * q.w) / wp;
+      // lower side line dw - Om
+      if (k == 1) {
+        tx += 0.25 * tmf * q.x;
+        ty += 0.25 * tmf * q.z;
+      } else {
+        tx += 0.25 * (q.x * smm + q.y * cm + sgn * q.y) / wm;
+        ty += 0.25 * (q.z * smm + q.w * cm + sgn * q.w) / wm;
+      }
+      ax -= tx;
+      ay -= ty;
+    }
+  }
+  if (want_E) {
+    const double g = cospi(double(hm) * (0.5 * inv_nt));  // cos(pi t / T)
+    E[0] = g * g * ex;
+    E[1] = g * g * ey;
+  }
+  if (want_A) {
+    A[0] = ax;
+    A[1] = ay;
+  }
+}
+
+// Per block: max |E| over step nodes (PEAK) or sum |E|^2 over midpoints (ENERGY) -> part[pulse][block].
+__global__ void __launch_bounds__(256) k_field_stats(const PulseDev* __restrict__ desc,
+                                                     const double* __restrict__ spec, int stride,
+                                                     double* __restrict__ part) {
+  const PulseDev d = desc[blockIdx.y];
+  if (d.norm == PO_NORM_NONE || int(blockIdx.x) >= d.stat_blocks) return;
+  const double4* sp = reinterpret_cast<const double4*>(spec + d.spec_off);
+  __shared__ double red[256];
+  const int64_t n = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  double v = 0.0;
+  if (d.norm == PO_NORM_PEAK) {
+    if (n <= d.nt) {
+      double E[2], A[2];
+      field_at(d, sp, 2 * n, true, false, E, A);
+      v = sqrt(E[0] * E[0] + E[1] * E[1]);
+    }
+  } else {
+    if (n < d.nt) {
+      double E[2], A[2];
+      field_at(d, sp, 2 * n + 1, true, false, E, A);
+      v = E[0] * E[0] + E[1] * E[1];
+    }
+  }
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) {
+      const double o = red[threadIdx.x + w];
+      red[threadIdx.x] = (d.norm == PO_NORM_PEAK) ? fmax(red[threadIdx.x], o) : red[threadIdx.x] + o;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[size_t(blockIdx.y) * stride + blockIdx.x] = red[0];
+}
+
+// One block per pulse: fixed-order reduction of the partials -> scale.
+__global__ void __launch_bounds__(256) k_scale(const PulseDev* __restrict__ desc, const double* __restrict__ part,
+                                               int stride, double* __restrict__ scale_ws,
+                                               double* __restrict__ scale_out) {
+  const PulseDev d = desc[blockIdx.x];
+  __shared__ double red[256];
+  const bool peak = d.norm == PO_NORM_PEAK;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < d.stat_blocks; i += 256) {
+    const double x = part[size_t(blockIdx.x) * stride + i];
+    v = peak ? fmax(v, x) : v + x;
+  }
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) red[threadIdx.x] = peak ? fmax(red[threadIdx.x], red[threadIdx.x + w])
+                                                      : red[threadIdx.x] + red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double s = 1.0;
+    if (d.norm == PO_NORM_PEAK) s = red[0] > 0.0 ? d.norm_value / red[0] : 0.0;
+    else if (d.norm == PO_NORM_ENERGY) {
+      const double U = red[0] * d.dt;
+      s = U > 0.0 ? sqrt(d.norm_value / U) : 0.0;
+    }
+    scale_ws[blockIdx.x] = s;
+    if (scale_out) scale_out[blockIdx.x] = s;
+  }
+}
+
+// Scaled A (and E) at every step midpoint; block (0, pulse) also writes A(t_i), A(t_f).
+__global__ void __launch_bounds__(256) k_tables(const PulseDev* __restrict__ desc, const double* __restrict__ spec,
+                                                const double* __restrict__ scale, double* __restrict__ Aout,
+                                                double* __restrict__ Eout, double* __restrict__ Aedge) {
+  const PulseDev d = desc[blockIdx.y];
+  const int64_t n = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const double4* sp = reinterpret_cast<const double4*>(spec + d.spec_off);
+  const double s = scale[blockIdx.y];
+  if (n < d.nt) {
+    double E[2], A[2];
+    field_at(d, sp, 2 * n + 1, Eout != nullptr, true, E, A);
+    reinterpret_cast<double2*>(Aout)[d.tab_off + n] = make_double2(s * A[0], s * A[1]);
+    if (Eout) reinterpret_cast<double2*>(Eout)[d.tab_off + n] = make_double2(s * E[0], s * E[1]);
+  }
+  if (blockIdx.x == 0 && threadIdx.x < 2) {
+    double E[2], A[2];
+    field_at(d, sp, threadIdx.x == 0 ? 0 : 2 * int64_t(d.nt), false, true, E, A);
+    reinterpret_cast<double2*>(Aedge)[2 * blockIdx.y + threadIdx.x] = make_double2(s * A[0], s * A[1]);
+  }
+}
+
+}  // namespace
+
+po_status launch_synth(const Batch& b, const PulseDev* d_desc, const double* d_coeff, double* d_spec,
+                       double* d_part, double* d_scale_ws, double* d_A, double* d_E, double* d_A_edge,
+                       double* d_scale_out, hipStream_t s) {
+  const int P = b.n_pulses;
+  hipLaunchKernelGGL(k_spectra, dim3(P), dim3(128), 0, s, d_desc, d_coeff, d_spec);
+  PO_HIP(hipGetLastError());
+  if (b.max_stat_blocks > 0) {
+    hipLaunchKernelGGL(k_field_stats, dim3(b.max_stat_blocks, P), dim3(256), 0, s, d_desc, d_spec,
+                       b.max_stat_blocks, d_part);
+    PO_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_scale, dim3(P), dim3(256), 0, s, d_desc, d_part, b.max_stat_blocks, d_scale_ws,
+                     d_scale_out);
+  PO_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_tables, dim3((b.max_nt + 255) / 256, P), dim3(256), 0, s, d_desc, d_spec, d_scale_ws,
+                     d_A, d_E, d_A_edge);
+  PO_HIP(hipGetLastError());
+  return PO_OK;
+}
+
+}  // namespace po

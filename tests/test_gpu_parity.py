@@ -1,0 +1,289 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the same seeded inputs.
+
+Tolerances (per mode, reference = long-double oracle): a mode passes iff
+    |f_gpu - f_ref| <= 1e-9 f_ref + 2 sqrt(f_ref) delta + delta^2,   delta = 4 * 2^-53 * sqrt(nt),
+i.e. relative 1e-9 plus the FP64 cancellation floor of a projection whose amplitude sqrt(f) is
+a difference of O(1) numbers carrying ~sqrt(nt) roundings.  J: relative 1e-8, no floor.
+Tables: |x_gpu - x_ref| <= 1e-12 max|x_ref|.  DE: bitwise.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - collected on CPU hosts, run on the GPU machine
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1704_08919_amd import api  # noqa: E402
+from paper_1704_08919_amd import workloads as W  # noqa: E402
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def mode_tol(f_ref, nt):
+    d = 4.0 * 2.0 ** -53 * math.sqrt(nt)
+    return 1e-9 * f_ref + 2.0 * np.sqrt(np.maximum(f_ref, 0.0)) * d + d * d
+
+
+def assert_modes(f_gpu, f_ref, nt, what):
+    f_gpu, f_ref = np.asarray(f_gpu), np.asarray(f_ref)
+    tol = mode_tol(f_ref, nt)
+    err = np.abs(f_gpu - f_ref)
+    bad = np.nonzero(err > tol)[0]
+    share = float(np.mean(err <= 1e-9 * f_ref)) if f_ref.size else 1.0
+    say(f"{what}: {f_ref.size} modes, max err/tol {np.max(err / tol):.3g}, share within plain 1e-9 rel {share:.3f}")
+    assert bad.size == 0, f"{what}: {bad.size} modes outside tolerance, first {bad[:5]}: {f_gpu[bad[:5]]} vs {f_ref[bad[:5]]}"
+
+
+def assert_J(J_gpu, J_ref, what):
+    rel = abs(J_gpu - J_ref) / abs(J_ref)
+    say(f"{what}: J gpu {J_gpu:.16e} ref {J_ref:.16e} rel {rel:.3g}")
+    assert rel <= 1e-8
+
+
+def dev(x, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def ragged_grid():
+    return W.grid((17, 13, 3), (-1.3, -0.9, -0.7), (1.1, 1.4, 0.8))
+
+
+# ------------------------------------------------------------------------------- synthesis
+@pytest.mark.parametrize("case", ["single_pulse", "two_pulses_T800", "energy_norm_ragged_nt"])
+def test_synth_tables_match_oracle(orc, case):
+    if case == "single_pulse":
+        w = W.single_pulse(0)
+        specs, coeff = w["specs"], w["coeff"]
+    elif case == "two_pulses_T800":
+        specs = [W.pulse_spec(n_s=8, T=800.0, nt=16384)] * 2
+        coeff = W.draw_coeff(3, 2, 8)
+    else:
+        specs = [W.pulse_spec(n_s=6, order=3, T=300.0, nt=1000, norm=W.NORM_ENERGY, norm_value=2.5),
+                 W.pulse_spec(n_s=8, T=400.0, nt=777, norm=W.NORM_NONE)]
+        coeff = np.concatenate([W.draw_coeff(5, 1, 6).ravel(), W.draw_coeff(6, 1, 8).ravel()])
+    say(f"synth case {case}")
+    A, edge, scale, E = api.synth(specs, coeff, want_E=True)
+    A, edge, scale, E = host(A), host(edge), host(scale), host(E)
+    off = 0
+    coff = 0
+    for i, s in enumerate(specs):
+        c = np.asarray(coeff).ravel()[coff:coff + 4 * s["n_s"]]
+        Ar, Er, er, sr = orc.synth(s, c)
+        nt = s["nt"]
+        assert abs(scale[i] - sr) <= 1e-13 * sr
+        assert np.max(np.abs(A[off:off + nt] - Ar)) <= 1e-12 * np.max(np.abs(Ar))
+        assert np.max(np.abs(E[off:off + nt] - Er)) <= 1e-12 * np.max(np.abs(Er))
+        assert np.max(np.abs(edge[i] - er)) <= 1e-12 * np.max(np.abs(Ar))
+        assert np.all(edge[i, 1] == 0.0)
+        off += nt
+        coff += 4 * s["n_s"]
+
+
+# ------------------------------------------------------------------------------- evolution
+def test_evolve_single_pulse_on_oracle_table(orc):
+    w = W.single_pulse(0)
+    spec, grid = w["specs"][0], w["grids"][0]
+    Ar, _, er, _ = orc.synth(spec, w["coeff"][0])
+    f, J = api.evolve([spec], [grid], dev(Ar), dev(er))
+    f, J = host(f), host(J)
+    p, _ = orc.grid_points(grid)
+    fr = orc.evolve_points(Ar, er, spec["T"] / spec["nt"], p)
+    assert_modes(f, fr, spec["nt"], "single pulse, oracle table")
+    assert_J(J[0], orc.pair_yield(grid, fr), "single pulse, oracle table")
+
+
+def test_evaluate_single_pulse_end_to_end(orc):
+    w = W.single_pulse(0)
+    spec, grid = w["specs"][0], w["grids"][0]
+    J, f = api.evaluate([spec], [grid], w["coeff"], want_f=True)
+    J, f = host(J), host(f)
+    Jr, fr = orc.evaluate(spec, grid, w["coeff"][0], want_f=True)
+    assert_modes(f, fr, spec["nt"], "single pulse end to end")
+    assert_J(J[0], Jr, "single pulse end to end")
+
+
+def test_ragged_heterogeneous_batch(orc):
+    # tiles with a ragged tail, nt not a multiple of the LDS chunk, sheet and box grids mixed
+    specs = [W.pulse_spec(n_s=4, T=300.0, nt=1000, norm_value=0.15),
+             W.pulse_spec(n_s=8, T=400.0, nt=257, norm_value=0.1),
+             W.pulse_spec(n_s=8, T=400.0, nt=2, norm_value=0.2)]
+    grids = [ragged_grid(), W.sheet_grid(5, 7, 1.2), W.grid((1, 1, 1), (0.3, -0.2, 0.1), (0.3, -0.2, 0.1))]
+    coeff = np.concatenate([W.draw_coeff(11, 1, 4).ravel(), W.draw_coeff(12, 1, 8).ravel(),
+                            W.draw_coeff(13, 1, 8).ravel()])
+    say("ragged batch")
+    J, f = api.evaluate(specs, grids, coeff, want_f=True)
+    J, f = host(J), host(f)
+    off, coff = 0, 0
+    for i, (s, g) in enumerate(zip(specs, grids)):
+        c = coeff[coff:coff + 4 * s["n_s"]]
+        Jr, fr = orc.evaluate(s, g, c, want_f=True)
+        m = W.n_modes(g)
+        assert_modes(f[off:off + m], fr, s["nt"], f"ragged pulse {i}")
+        assert_J(J[i], Jr, f"ragged pulse {i}")
+        off += m
+        coff += 4 * s["n_s"]
+
+
+@pytest.mark.parametrize("amp", [1.5, 40.0])
+def test_large_potential_series_variants(orc, amp):
+    # A large vector potential pushes (omega dt)^2 past the degree-6 range (degree 7 / angle halving).
+    nt, T = 600, 120.0
+    dt = T / nt
+    t = -T / 2 + (np.arange(nt) + 0.5) * dt
+    A = np.stack([amp * np.cos(np.pi * t / T) ** 4 * np.cos(0.3 * t), amp * np.cos(np.pi * t / T) ** 4 * np.sin(0.2 * t)], 1)
+    edge = np.zeros((2, 2))
+    spec = W.pulse_spec(n_s=4, T=T, nt=nt)
+    grid = W.box_grid(6, 5, 3)
+    say(f"series variant amp {amp}")
+    f, J = api.evolve([spec], [grid], dev(A), dev(edge))
+    f = host(f)
+    p, _ = orc.grid_points(grid)
+    fr = orc.evolve_points(A, edge, dt, p)
+    assert_modes(f, fr, nt, f"large potential {amp}")
+
+
+def test_sauter_pulse_closed_form_on_gpu():
+    E0, tau, T = 0.5, 2.0, 80.0
+    res = []
+    grid = W.grid((8, 4, 3), (-0.9, -0.5, -0.4), (0.9, 0.5, 0.4))
+    for nt in (8192, 16384):
+        dt = T / nt
+        t = -T / 2 + (np.arange(nt) + 0.5) * dt
+        A = np.zeros((nt, 2))
+        A[:, 0] = -E0 * tau * np.tanh(t / tau)
+        edge = np.array([[-E0 * tau * math.tanh(-T / 2 / tau), 0.0], [-E0 * tau * math.tanh(T / 2 / tau), 0.0]])
+        f, _ = api.evolve([W.pulse_spec(n_s=4, T=T, nt=nt)], [grid], dev(A), dev(edge), want_J=False)
+        res.append(host(f))
+    rich = (4 * res[1] - res[0]) / 3
+    n = grid["n"]
+    px = grid["lo"][0] + (np.arange(n[0]) + 0.5) * (grid["hi"][0] - grid["lo"][0]) / n[0]
+    py = grid["lo"][1] + (np.arange(n[1]) + 0.5) * (grid["hi"][1] - grid["lo"][1]) / n[1]
+    pz = grid["lo"][2] + (np.arange(n[2]) + 0.5) * (grid["hi"][2] - grid["lo"][2]) / n[2]
+    PZ, PY, PX = np.meshgrid(pz, py, px, indexing="ij")
+    PX, PY, PZ = PX.ravel(), PY.ravel(), PZ.ravel()
+    perp2 = PY ** 2 + PZ ** 2
+    wi = np.sqrt(1 + perp2 + (PX - E0 * tau) ** 2)
+    wo = np.sqrt(1 + perp2 + (PX + E0 * tau) ** 2)
+    D = wi - wo
+    f1 = np.sinh(np.pi * tau * (E0 * tau + D / 2)) * np.sinh(np.pi * tau * (E0 * tau - D / 2)) / (
+        np.sinh(np.pi * tau * wi) * np.sinh(np.pi * tau * wo))
+    np.testing.assert_allclose(rich, 2 * f1, rtol=1e-9)
+
+
+def test_zero_field_no_pairs_and_unit_bound():
+    nt = 1024
+    spec = W.pulse_spec(n_s=4, T=100.0, nt=nt)
+    grid = W.box_grid(16, 16, 4)
+    A = torch.zeros((nt, 2), dtype=torch.float64, device="cuda")
+    edge = torch.zeros((1, 2, 2), dtype=torch.float64, device="cuda")
+    f, J = api.evolve([spec], [grid], A, edge)
+    f = host(f)
+    assert np.max(np.abs(f)) < 1e-26
+
+
+def test_pair_yield_matches_fused_reduction_bitwise():
+    w = W.single_pulse(1)
+    specs = w["specs"] * 3
+    grids = [w["grids"][0], ragged_grid(), W.box_grid(20, 20, 3)]
+    coeff = W.draw_coeff(7, 3, 4)
+    J, f = api.evaluate(specs, grids, coeff, want_f=True)
+    J2 = torch.empty_like(J)
+    api.po_pair_yield(grids, f, J2)
+    J, J2, fh = host(J), host(J2), host(f)
+    assert np.array_equal(J, J2)
+    off = 0
+    for i, g in enumerate(grids):
+        m = W.n_modes(g)
+        dv = np.prod([(g["hi"][d] - g["lo"][d]) / g["n"][d] for d in range(3) if not (g["n"][d] == 1 and g["lo"][d] == g["hi"][d])])
+        assert abs(J[i] - dv * math.fsum(fh[off:off + m])) <= 1e-14 * J[i]
+        off += m
+
+
+def test_bitwise_reproducible():
+    w = W.single_pulse(2)
+    a = host(api.evaluate(w["specs"], w["grids"], w["coeff"], want_f=True)[1])
+    b = host(api.evaluate(w["specs"], w["grids"], w["coeff"], want_f=True)[1])
+    assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------------------------------------ DE
+def test_de_propose_bitwise_and_select(orc):
+    N, ns = 64, 8
+    D = 4 * ns
+    pop = W.rng(5).uniform(-1, 1, (N, D))
+    prm = api.de_params(N, D, ns, F=0.8, CR=0.9, seed=0xDEADBEEF12345)
+    for gen in (0, 1, 12345678901):
+        trial = torch.empty((N, D), dtype=torch.float64, device="cuda")
+        idx = torch.empty((N, 4), dtype=torch.int32, device="cuda")
+        api.po_de_propose(prm, gen, dev(pop), trial, idx)
+        tr, ir = orc.de_propose(pop, gen, 0.8, 0.9, -1.0, 1.0, seed=0xDEADBEEF12345, n_s=ns)
+        assert np.array_equal(host(idx), ir)
+        assert np.array_equal(host(trial), tr)
+    fit = W.rng(6).uniform(0, 1, N)
+    tfit = W.rng(7).uniform(0, 1, N)
+    tfit[3] = fit[3]
+    mask = (W.rng(8).uniform(0, 1, N) < 0.5).astype(np.uint8)
+    for m in (None, mask):
+        dp, df = dev(pop), dev(fit)
+        api.po_de_select(prm, dp, df, dev(tr), dev(tfit), None if m is None else dev(m, torch.uint8))
+        pr, fr = orc.de_select(pop, fit, tr, tfit, m)
+        assert np.array_equal(host(dp), pr) and np.array_equal(host(df), fr)
+
+
+def test_de_generation_equals_separate_calls(orc):
+    N, ns = 8, 4
+    spec = W.pulse_spec(n_s=ns, T=400.0, nt=512, norm_value=0.1)
+    grid = W.sheet_grid(16, 16, 1.5)
+    prm = api.de_params(N, 4 * ns, ns, seed=42)
+    pop = W.rng(9).uniform(-1, 1, (N, 4 * ns))
+    fit0, _ = api.evaluate([spec] * N, [grid] * N, pop)
+    dpop, dfit = dev(pop), fit0.clone()
+    trial = torch.empty_like(dpop)
+    tfit = torch.empty_like(dfit)
+    api.po_de_generation(prm, 3, spec, grid, dpop, dfit, trial, tfit)
+    # reference: the same steps through the separate entry points
+    trial2 = torch.empty_like(dpop)
+    api.po_de_propose(prm, 3, dev(pop), trial2)
+    tfit2, _ = api.evaluate([spec] * N, [grid] * N, trial2)
+    pop2, fit2 = dev(pop), fit0.clone()
+    api.po_de_select(prm, pop2, fit2, trial2, tfit2)
+    assert np.array_equal(host(trial), host(trial2))
+    assert np.array_equal(host(tfit), host(tfit2))
+    assert np.array_equal(host(dpop), host(pop2)) and np.array_equal(host(dfit), host(fit2))
+    # and the trial fitness agrees with the oracle
+    for i in (0, 5):
+        Jr = orc.evaluate(spec, grid, host(trial)[i])
+        assert_J(host(tfit)[i], Jr, f"de_generation trial {i}")
+
+
+# ------------------------------------------------------------------- full-size workloads
+def test_de_generation_workload_full_size_sampled(orc):
+    """64 pulses x 64x64x16 modes x nt=16384 in the benchmark's launch; sampled modes vs the oracle."""
+    w = W.de_generation(0)
+    specs, grids, coeff = w["specs"], w["grids"], w["coeff"]
+    say("full-size DE generation workload")
+    J, f = api.evaluate(specs, grids, coeff, want_f=True)
+    J, f = host(J), host(f)
+    M = W.n_modes(grids[0])
+    assert np.all(np.isfinite(f)) and np.all(f >= 0) and np.all(f <= 2)
+    for pi in (0, 37):
+        Ar, _, er, _ = orc.synth(specs[pi], coeff[pi])
+        idx = W.sample_mode_indices(pi, M, 24)
+        p, _ = orc.grid_points(grids[pi])
+        fr = orc.evolve_points(Ar, er, specs[pi]["T"] / specs[pi]["nt"], p[idx])
+        assert_modes(f[pi * M + idx], fr, specs[pi]["nt"], f"full size pulse {pi} sampled")
+    dv = (4 / 64) * (4 / 64) * (2 / 16)
+    for pi in range(0, 64, 9):
+        assert abs(J[pi] - dv * math.fsum(f[pi * M:(pi + 1) * M])) <= 1e-13 * J[pi]
