@@ -24,21 +24,31 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 128 FLOP/clk x 2.4 GHz
-# FP64 operations of one mode-step (an FMA counts 2): q (2 adds), x (2 FMA), the two series of
-# degree D (2 D FMA), S q (3 mul), and the rotation of two 2x2 blocks (8 outputs x (1 mul + 3 FMA)).
+# Series variants of the evolution kernel: tan(sqrt x)/sqrt x of degree n for (omega dt)^2 <= x_n.
+TAN_DEGREES = (6, 8, 10, 13, 19)
+TAN_XMAX = (0.0099, 0.0337, 0.0735, 0.1558, 0.3552)
+
+
 def flop_per_mode_step(degree):
-    return 2 + 4 + 4 * degree + 3 + 56
+    """FP64 operations of one mode-step of the tangent-form step (an FMA counts 2): q (2 adds),
+    x = |q|^2 (2 FMA), the series of degree n (n FMA), T q (3 mul), and 1 - i T Q applied to two
+    2x2 blocks (8 real components x 3 FMA)."""
+    return 2 + 4 + 2 * degree + 3 + 48
 
 
 def series_degree(A, edge, spec, grid, torch):
-    """Series degree the evolution kernel selects for this table (same bound as the kernel)."""
+    """Series degree the evolution kernel selects for this table (the kernel's own bound), or None
+    when the large-step path applies."""
     amax = float(torch.max(torch.sqrt((A ** 2).sum(-1))).item())
     amax = max(amax, float(torch.max(torch.sqrt((edge ** 2).sum(-1))).item()))
     pm = [max(abs(grid["lo"][d]), abs(grid["hi"][d])) for d in range(3)]
     dt = spec["T"] / spec["nt"]
     pr = math.hypot(pm[0], pm[1]) + amax
     xb = (pr * pr + 1.0 + pm[2] ** 2) * dt * dt * (1.0 + 1e-6)
-    return 6 if xb <= 0.14 else 7
+    for n, x in zip(TAN_DEGREES, TAN_XMAX):
+        if xb <= x:
+            return n
+    return None
 
 
 def cpu_baseline(w, sample_modes):
@@ -61,6 +71,33 @@ def cpu_baseline(w, sample_modes):
                       f"all {spec['nt']} steps ({ms:.3e} mode-steps, {dt:.1f} s, double build, OpenMP)"}
 
 
+def uneven_batch(api, W, torch, uniform_rate, reps=3):
+    """256 pulses of uneven nt and grids through one autotuned plan (persistent queue, HIP graph)."""
+    w = W.uneven_batch(0)
+    specs, grids = w["specs"], w["grids"]
+    t0 = time.perf_counter()
+    plan = api.Plan(specs, grids, config=None)
+    tune_s = time.perf_counter() - t0
+    coeff = torch.as_tensor(w["coeff"].ravel(), dtype=torch.float64, device="cuda")
+    J = torch.empty(len(specs), dtype=torch.float64, device="cuda")
+    plan.evaluate(coeff, J)  # captures the graph
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        plan.evaluate(coeff, J)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / reps
+    ms_total = W.mode_steps(specs, grids)
+    rate = ms_total / (ms / 1e3)
+    cfg = plan.config
+    plan.close()
+    return {"workload": w["name"], "mode_steps": ms_total, "ms_per_evaluation": ms, "mode_steps_per_s": rate,
+            "plan": cfg, "autotune_s": tune_s, "rate_vs_uniform_batch": rate / uniform_rate,
+            "timing": "HIP events on torch's current stream around graph replays"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,7 +105,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-modes", type=int, default=4096)
+    ap.add_argument("--cpu-sample-modes", type=int, default=65536)
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch plan measurement")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a plain 512 MiB device copy first (reference for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU layout is a design "
@@ -81,6 +121,13 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        src = torch.ones(64 * 2 ** 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = W.de_generation(args.seed)
     spec, grid = w["specs"][0], w["grids"][0]
     N = len(w["specs"])
@@ -89,6 +136,7 @@ def main():
     pop = torch.as_tensor(w["coeff"].reshape(N, D), dtype=torch.float64, device="cuda").contiguous()
     A, edge, _, _ = api.synth(w["specs"], pop)
     degree = series_degree(A, edge, spec, grid, torch)
+    assert degree is not None, "workload left the tangent-series range"
     del A, edge
     fit, _ = api.evaluate(w["specs"], w["grids"], pop)
     trial = torch.empty_like(pop)
@@ -138,6 +186,8 @@ def main():
                      "kernel": "k_evolve (per-mode evolution + projection)", "flop_per_mode_step": fps,
                      "series_degree": degree},
     }
+    if not args.no_uneven:
+        out["uneven_batch"] = uneven_batch(api, W, torch, mode_steps / ev_s)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_modes)
     print(json.dumps(out), flush=True)

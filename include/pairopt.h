@@ -125,7 +125,8 @@ po_status po_pulse_synth(int32_t n_pulses, const po_pulse_spec* specs, const dou
  *  d_f       out [sum M] double or NULL: f(t_f, p) per mode.
  *  d_J       out [n_pulses] double or NULL: J = Delta V sum_p f (Sec. IV A, Eq. opt_prob).
  *            At least one of d_f, d_J must be non-NULL.
- *  plan      NULL (default launch) or a plan from po_plan_create for these same pulses.
+ *  plan      NULL (one workgroup per 256 modes) or a plan created for the same specs and
+ *            grids, whose launch shape and queue are then used.
  * --------------------------------------------------------------------------------------- */
 struct po_plan;
 po_status po_evolve_modes(int32_t n_pulses, const po_pulse_spec* specs, const po_grid* grids,
@@ -194,6 +195,41 @@ po_status po_de_select(const po_de_params* prm, double* d_pop, double* d_fit, co
 po_status po_de_generation(const po_de_params* prm, int64_t generation, const po_pulse_spec* spec,
                            const po_grid* grid, double* d_pop, double* d_fit, double* d_trial,
                            double* d_trial_fit, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Plans: a fixed batch of (possibly uneven) pulses evaluated many times -- e.g. a DE population
+ * whose pulses differ in duration nt and momentum grid.  A plan owns every work buffer, the
+ * per-pulse descriptors and a device work queue of (pulse, block of modes) items ordered by
+ * decreasing cost (nt), so persistent workgroups take the longest work first.  The launch
+ * shape is given or chosen by timing the candidates on the plan's own batch (autotuning); the
+ * choice can be cached in a text file.  The first po_plan_evaluate with a given set of
+ * pointers captures synthesis -> series selection -> evolution -> yield into a HIP graph, later
+ * calls with the same pointers replay it.  Results do not depend on the launch shape: J is
+ * bitwise identical to po_evaluate's.  Calls on one plan must not overlap (they share its
+ * buffers); different plans are independent.
+ * --------------------------------------------------------------------------------------- */
+typedef struct {
+  int32_t threads;         /* lanes per workgroup: 64, 128 or 256; 0 = autotune */
+  int32_t modes_per_lane;  /* 1 or 2; 0 = autotune */
+  int32_t persistent;      /* 1 = persistent workgroups on the work queue, 0 = one workgroup per
+                              256 modes (threads must be 256, modes_per_lane 1), -1 = autotune */
+  int32_t workgroups;      /* persistent workgroups; 0 = what the device holds resident */
+} po_plan_config;
+
+/* cfg NULL = autotune everything.  cache_path NULL = no cache; otherwise a text file read before
+ * and appended after autotuning, keyed by the device and the batch shape.  Allocates device
+ * memory (sum nt x 32 bytes + modes / 8 bytes + small); runs and synchronises `stream` while
+ * autotuning. */
+po_status po_plan_create(int32_t n_pulses, const po_pulse_spec* specs, const po_grid* grids,
+                         const po_plan_config* cfg, const char* cache_path, void* stream,
+                         struct po_plan** out);
+/* The launch shape the plan uses (after autotuning). */
+po_status po_plan_get_config(const struct po_plan* plan, po_plan_config* out);
+/* d_coeff [sum 4 n_s] double; d_J out [n_pulses] double; d_f out [sum M] double or NULL.
+ * Tables are written to the plan's own buffers. */
+po_status po_plan_evaluate(struct po_plan* plan, const double* d_coeff, double* d_J, double* d_f,
+                           void* stream);
+void po_plan_destroy(struct po_plan* plan);
 
 /* ---------------------------------------------------------------------------------------
  * Kernel timers (diagnostics, not part of the method).  While enabled, every po_evolve_modes /

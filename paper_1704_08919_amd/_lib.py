@@ -38,6 +38,11 @@ class DEParams(ctypes.Structure):
                 ("CR", ctypes.c_double), ("lo", ctypes.c_double), ("hi", ctypes.c_double), ("seed", ctypes.c_uint64)]
 
 
+class PlanConfig(ctypes.Structure):
+    _fields_ = [("threads", ctypes.c_int32), ("modes_per_lane", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("workgroups", ctypes.c_int32)]
+
+
 _P = ctypes.c_void_p
 _I32, _I64 = ctypes.c_int32, ctypes.c_int64
 
@@ -54,6 +59,11 @@ SIGNATURES = {
     "po_de_select": ([ctypes.POINTER(DEParams), _P, _P, _P, _P, _P, _P], ctypes.c_int),
     "po_de_generation": ([ctypes.POINTER(DEParams), _I64, ctypes.POINTER(PulseSpec), ctypes.POINTER(Grid), _P, _P, _P,
                           _P, _P], ctypes.c_int),
+    "po_plan_create": ([_I32, ctypes.POINTER(PulseSpec), ctypes.POINTER(Grid), ctypes.POINTER(PlanConfig),
+                        ctypes.c_char_p, _P, ctypes.POINTER(_P)], ctypes.c_int),
+    "po_plan_get_config": ([_P, ctypes.POINTER(PlanConfig)], ctypes.c_int),
+    "po_plan_evaluate": ([_P, _P, _P, _P, _P], ctypes.c_int),
+    "po_plan_destroy": ([_P], None),
     "po_timer_enable": ([ctypes.c_int], ctypes.c_int),
     "po_timer_read": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
 }

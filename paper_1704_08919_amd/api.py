@@ -12,7 +12,7 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import DEParams, Grid, PulseSpec, check, load
+from ._lib import DEParams, Grid, PlanConfig, PulseSpec, check, load
 
 
 def _spec_array(specs):
@@ -64,9 +64,10 @@ def po_pulse_synth(specs, coeff, A, A_edge, E=None, scale=None, stream=None):
                                 _stream(stream)))
 
 
-def po_evolve_modes(specs, grids, A, A_edge, f=None, J=None, stream=None):
+def po_evolve_modes(specs, grids, A, A_edge, f=None, J=None, plan=None, stream=None):
     sp, gr = _spec_array(specs), _grid_array(grids)
-    check(load().po_evolve_modes(len(specs), sp, gr, _ptr(A), _ptr(A_edge), _ptr(f), _ptr(J), None, _stream(stream)))
+    ph = plan.handle if plan is not None else None
+    check(load().po_evolve_modes(len(specs), sp, gr, _ptr(A), _ptr(A_edge), _ptr(f), _ptr(J), ph, _stream(stream)))
 
 
 def po_pair_yield(grids, f, J, stream=None):
@@ -94,6 +95,47 @@ def po_de_generation(params, generation, spec, grid, pop, fit, trial, trial_fit,
     sp, gr = _spec_array([spec]), _grid_array([grid])
     check(load().po_de_generation(ctypes.byref(params), int(generation), sp, gr, _ptr(pop), _ptr(fit), _ptr(trial),
                                   _ptr(trial_fit), _stream(stream)))
+
+
+class Plan:
+    """po_plan_create / po_plan_evaluate / po_plan_destroy for a fixed batch of pulses.
+
+    config: None (autotune) or dict(threads=, modes_per_lane=, persistent=, workgroups=), where 0
+    (or -1 for persistent) leaves that choice to the autotuner."""
+
+    def __init__(self, specs, grids, config=None, cache_path=None, stream=None):
+        self.specs, self.grids = list(specs), list(grids)
+        sp, gr = _spec_array(self.specs), _grid_array(self.grids)
+        cfg = None
+        if config is not None:
+            cfg = PlanConfig(int(config.get("threads", 0)), int(config.get("modes_per_lane", 0)),
+                             int(config.get("persistent", -1)), int(config.get("workgroups", 0)))
+        h = ctypes.c_void_p()
+        path = cache_path.encode() if cache_path else None
+        check(load().po_plan_create(len(self.specs), sp, gr, ctypes.byref(cfg) if cfg is not None else None, path,
+                                    _stream(stream), ctypes.byref(h)))
+        self.handle = h
+
+    @property
+    def config(self):
+        c = PlanConfig()
+        check(load().po_plan_get_config(self.handle, ctypes.byref(c)))
+        return dict(threads=c.threads, modes_per_lane=c.modes_per_lane, persistent=c.persistent,
+                    workgroups=c.workgroups)
+
+    def evaluate(self, coeff, J, f=None, stream=None):
+        check(load().po_plan_evaluate(self.handle, _ptr(coeff), _ptr(J), _ptr(f), _stream(stream)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().po_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def po_timer_enable(on=True):

@@ -98,7 +98,7 @@ po_status validate_grid(const po_grid& g, int i) {
     if (g.n[d] > 1 && !(g.lo[d] < g.hi[d])) return set_error(PO_ERR_INVALID, "grid %d: n[%d] > 1 needs lo < hi", i, d);
   }
   const int64_t m = int64_t(g.n[0]) * g.n[1] * g.n[2];
-  if (m > (int64_t(1) << 31) * kTile / 4) return set_error(PO_ERR_INVALID, "grid %d: too many modes", i);
+  if (m > (int64_t(1) << 30)) return set_error(PO_ERR_INVALID, "grid %d: more than 2^30 modes", i);
   return PO_OK;
 }
 
@@ -106,7 +106,7 @@ po_status build_batch(int32_t n, const po_pulse_spec* specs, const po_grid* grid
   *b = Batch{};
   b->n_pulses = n;
   int64_t tab = 0, modes = 0, coeff = 0, spec = 0;
-  int64_t tiles = 0;
+  int64_t units = 0, items = 0;
   for (int i = 0; i < n; ++i) {
     PulseDev d;
     std::memset(&d, 0, sizeof d);
@@ -114,7 +114,8 @@ po_status build_batch(int32_t n, const po_pulse_spec* specs, const po_grid* grid
     d.mode_off = modes;
     d.coeff_off = coeff;
     d.spec_off = spec;
-    d.tile_off = int32_t(tiles);
+    d.unit_off = units;
+    d.item_off = int32_t(items);
     if (specs) {
       const po_pulse_spec& s = specs[i];
       d.nt = s.nt;
@@ -149,20 +150,22 @@ po_status build_batch(int32_t n, const po_pulse_spec* specs, const po_grid* grid
       }
       d.dv = dv;
       const int64_t m = int64_t(g.n[0]) * g.n[1] * g.n[2];
-      d.ntiles = int32_t((m + kTile - 1) / kTile);
+      d.nunits = int32_t((m + kUnit - 1) / kUnit);
+      d.nitems = int32_t((m + kItem - 1) / kItem);
       modes += m;
-      tiles += d.ntiles;
-      b->max_tiles = std::max(b->max_tiles, d.ntiles);
+      units += d.nunits;
+      items += d.nitems;
       if (i > 0 && std::memcmp(&g, &grids[0], sizeof g) != 0) b->uniform = false;
     }
     out[i] = d;
   }
-  if (tiles > (int64_t(1) << 31) - 1) return set_error(PO_ERR_INVALID, "batch has too many tiles");
+  if (items > (int64_t(1) << 31) - 1) return set_error(PO_ERR_INVALID, "batch has too many modes");
   b->total_rows = tab;
   b->total_modes = modes;
   b->total_coeff = coeff;
   b->total_spec = spec;
-  b->total_tiles = int32_t(tiles);
+  b->total_units = units;
+  b->total_items = int32_t(items);
   return PO_OK;
 }
 
@@ -202,38 +205,51 @@ std::mutex g_timer_mu;
 bool g_timer_on = false;
 std::vector<std::pair<hipEvent_t, hipEvent_t>> g_timer_events;
 
-po_status timer_record(hipStream_t s, hipEvent_t* ev) {
-  PO_HIP(hipEventCreate(ev));
-  PO_HIP(hipEventRecord(*ev, s));
-  return PO_OK;
-}
-
 po_status evolve_impl(const Batch& b, const PulseDev* d_desc, const double* d_A, const double* d_A_edge, double* d_f,
                       double* d_J, hipStream_t s) {
-  Scratch tiles;
-  double* d_tiles = nullptr;
+  Scratch units, sel;
+  double* d_units = nullptr;
   if (d_J) {
-    PO_TRY(tiles.alloc(sizeof(double) * size_t(b.total_tiles), s));
-    d_tiles = static_cast<double*>(tiles.ptr);
+    PO_TRY(units.alloc(sizeof(double) * size_t(b.total_units), s));
+    d_units = static_cast<double*>(units.ptr);
   }
-  bool timed;
-  {
-    std::lock_guard<std::mutex> lk(g_timer_mu);
-    timed = g_timer_on;
-  }
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (timed) PO_TRY(timer_record(s, &e0));
-  PO_TRY(launch_evolve(b, d_desc, d_A, d_A_edge, d_f, d_tiles, s));
-  if (timed) {
-    PO_TRY(timer_record(s, &e1));
-    std::lock_guard<std::mutex> lk(g_timer_mu);
-    g_timer_events.emplace_back(e0, e1);
-  }
-  if (d_J) PO_TRY(launch_yield_from_tiles(b, d_desc, d_tiles, d_J, s));
+  PO_TRY(sel.alloc(sizeof(int2) * size_t(b.n_pulses), s));
+  int2* d_sel = static_cast<int2*>(sel.ptr);
+  hipEvent_t e0 = nullptr;
+  const bool timed = timer_start(s, &e0);
+  PO_TRY(launch_series_select(b, d_desc, d_A, d_A_edge, d_sel, s));
+  PO_TRY(launch_evolve_grid(b, d_desc, d_A, d_A_edge, d_sel, d_f, d_units, s));
+  if (timed) timer_stop(s, e0);
+  if (d_J) PO_TRY(launch_yield_from_units(b, d_desc, d_units, d_J, s));
   return PO_OK;
 }
 
 }  // namespace
+
+bool timer_start(hipStream_t s, hipEvent_t* e0) {
+  {
+    std::lock_guard<std::mutex> lk(g_timer_mu);
+    if (!g_timer_on) return false;
+  }
+  if (hipEventCreate(e0) != hipSuccess) return false;
+  if (hipEventRecord(*e0, s) != hipSuccess) {
+    (void)hipEventDestroy(*e0);
+    return false;
+  }
+  return true;
+}
+
+void timer_stop(hipStream_t s, hipEvent_t e0) {
+  hipEvent_t e1 = nullptr;
+  if (hipEventCreate(&e1) != hipSuccess || hipEventRecord(e1, s) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return;
+  }
+  std::lock_guard<std::mutex> lk(g_timer_mu);
+  g_timer_events.emplace_back(e0, e1);
+}
+
 }  // namespace po
 
 using namespace po;
@@ -265,7 +281,6 @@ po_status po_pulse_synth(int32_t n, const po_pulse_spec* specs, const double* d_
 po_status po_evolve_modes(int32_t n, const po_pulse_spec* specs, const po_grid* grids, const double* d_A,
                           const double* d_A_edge, double* d_f, double* d_J, const struct po_plan* plan, void* stream) {
   if (n < 1) return set_error(PO_ERR_INVALID, "n_pulses must be >= 1");
-  if (plan) return set_error(PO_ERR_UNSUPPORTED, "plans are not supported by this build");
   PO_TRY(check_specs(n, specs));
   PO_TRY(check_grids(n, grids));
   if (!d_f && !d_J) return set_error(PO_ERR_INVALID, "at least one of d_f, d_J must be non-NULL");
@@ -277,6 +292,13 @@ po_status po_evolve_modes(int32_t n, const po_pulse_spec* specs, const po_grid* 
   if (d_f) PO_TRY(check_device_range(d_f, sizeof(double) * b.total_modes, 8, "d_f"));
   if (d_J) PO_TRY(check_device_range(d_J, sizeof(double) * n, 8, "d_J"));
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (plan) {
+    hipEvent_t e0 = nullptr;
+    const bool timed = timer_start(s, &e0);
+    PO_TRY(plan_evolve(plan, n, specs, grids, d_A, d_A_edge, d_f, d_J, s));
+    if (timed) timer_stop(s, e0);
+    return PO_OK;
+  }
   Scratch desc;
   PO_TRY(upload(h, desc, s));
   return evolve_impl(b, static_cast<PulseDev*>(desc.ptr), d_A, d_A_edge, d_f, d_J, s);
@@ -291,19 +313,18 @@ po_status po_pair_yield(int32_t n, const po_grid* grids, const double* d_f, doub
   PO_TRY(check_device_range(d_f, sizeof(double) * b.total_modes, 8, "d_f"));
   PO_TRY(check_device_range(d_J, sizeof(double) * n, 8, "d_J"));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  Scratch desc, tiles;
+  Scratch desc, units;
   PO_TRY(upload(h, desc, s));
-  PO_TRY(tiles.alloc(sizeof(double) * size_t(b.total_tiles), s));
+  PO_TRY(units.alloc(sizeof(double) * size_t(b.total_units), s));
   const PulseDev* d_desc = static_cast<PulseDev*>(desc.ptr);
-  PO_TRY(launch_tile_sums_from_f(b, d_desc, d_f, static_cast<double*>(tiles.ptr), s));
-  return launch_yield_from_tiles(b, d_desc, static_cast<double*>(tiles.ptr), d_J, s);
+  PO_TRY(launch_unit_sums_from_f(b, d_desc, d_f, static_cast<double*>(units.ptr), s));
+  return launch_yield_from_units(b, d_desc, static_cast<double*>(units.ptr), d_J, s);
 }
 
 po_status po_evaluate(int32_t n, const po_pulse_spec* specs, const po_grid* grids, const double* d_coeff, double* d_A,
                       double* d_A_edge, double* d_scale, double* d_f, double* d_J, const struct po_plan* plan,
                       void* stream) {
   if (n < 1) return set_error(PO_ERR_INVALID, "n_pulses must be >= 1");
-  if (plan) return set_error(PO_ERR_UNSUPPORTED, "plans are not supported by this build");
   PO_TRY(check_specs(n, specs));
   PO_TRY(check_grids(n, grids));
   if (!d_f && !d_J) return set_error(PO_ERR_INVALID, "at least one of d_f, d_J must be non-NULL");
@@ -321,6 +342,13 @@ po_status po_evaluate(int32_t n, const po_pulse_spec* specs, const po_grid* grid
   PO_TRY(upload(h, desc, s));
   const PulseDev* d_desc = static_cast<PulseDev*>(desc.ptr);
   PO_TRY(synth_impl(n, specs, d_coeff, d_A, nullptr, d_A_edge, d_scale, s, b, d_desc));
+  if (plan) {
+    hipEvent_t e0 = nullptr;
+    const bool timed = timer_start(s, &e0);
+    PO_TRY(plan_evolve(plan, n, specs, grids, d_A, d_A_edge, d_f, d_J, s));
+    if (timed) timer_stop(s, e0);
+    return PO_OK;
+  }
   return evolve_impl(b, d_desc, d_A, d_A_edge, d_f, d_J, s);
 }
 

@@ -31,7 +31,8 @@ po_status check_device_range(const void* p, size_t bytes, size_t align, const ch
 
 // ---------------------------------------------------------------- per-pulse descriptors
 // One record per pulse, uploaded to device memory for every multi-pulse launch.
-constexpr int kTile = 256;        // momentum modes per reduction tile (fixed: sets the sum order)
+constexpr int kUnit = 64;         // momentum modes per reduction unit, one wave (fixed: sets the sum order)
+constexpr int kItem = 256;        // modes per workgroup in the default (non-plan) evolution launch
 constexpr int kMaxLines = 8192;   // spectral lines per pulse
 constexpr int kMaxNs = 64;        // B-spline coefficients per spectral function
 
@@ -43,8 +44,10 @@ struct PulseDev {
   int32_t nt, ns, order, nlines;
   int32_t nmin, norm, stat_blocks, pad0;
   int32_t n[3];
-  int32_t tile_off;   // first reduction tile of this pulse in the batch
-  int32_t ntiles;
+  int64_t unit_off;   // first 64-mode reduction unit of this pulse in the batch
+  int32_t nunits;
+  int32_t item_off;   // first workgroup item of this pulse in the default evolution launch
+  int32_t nitems;
   int32_t pad1;
   double T, dt, dw, wmin, wmax, norm_value, dv;
   double lo[3], dp[3];  // p_d = lo_d + (i + 1/2) dp_d; dp_d = 0 for a sheet (then p_d = lo_d)
@@ -53,8 +56,8 @@ struct PulseDev {
 struct Batch {
   int32_t n_pulses = 0;
   int64_t total_rows = 0, total_modes = 0, total_coeff = 0, total_spec = 0;
-  int32_t total_tiles = 0;
-  int32_t max_tiles = 0;       // largest per-pulse tile count
+  int64_t total_units = 0;
+  int32_t total_items = 0;     // workgroups of the default evolution launch
   int32_t max_stat_blocks = 0; // largest per-pulse block count of the field statistics pass
   int32_t max_nt = 0;
   bool uniform = true;         // all pulses share nt/grid (lets kernels skip the binary search)
@@ -80,12 +83,36 @@ struct Scratch {
 po_status launch_synth(const Batch& b, const PulseDev* d_desc, const double* d_coeff, double* d_spec,
                        double* d_part, double* d_scale_ws, double* d_A, double* d_E, double* d_A_edge,
                        double* d_scale_out, hipStream_t s);
-po_status launch_evolve(const Batch& b, const PulseDev* d_desc, const double* d_A, const double* d_A_edge,
-                        double* d_f, double* d_tile_sums, hipStream_t s);
-po_status launch_tile_sums_from_f(const Batch& b, const PulseDev* d_desc, const double* d_f,
-                                  double* d_tile_sums, hipStream_t s);
-po_status launch_yield_from_tiles(const Batch& b, const PulseDev* d_desc, const double* d_tile_sums,
-                                  double* d_J, hipStream_t s);
+// Launch shape of the evolution kernel.  threads: lanes per workgroup (64, 128, 256);
+// mpl: modes per lane (1, 2); persistent: workgroups pull items from a device queue.
+struct EvolveConfig {
+  int threads = 256;
+  int mpl = 1;
+  int persistent = 0;
+};
+// Per-pulse series selection: x = mode (variant), y = number of angle halvings.
+// d_sel must hold n_pulses int2; d_units n = total_units doubles (one partial sum per 64 modes).
+po_status launch_series_select(const Batch& b, const PulseDev* d_desc, const double* d_A, const double* d_A_edge,
+                               int2* d_sel, hipStream_t s);
+po_status launch_evolve_grid(const Batch& b, const PulseDev* d_desc, const double* d_A, const double* d_A_edge,
+                             const int2* d_sel, double* d_f, double* d_units, hipStream_t s);
+// Persistent launch: items are {pulse, first mode} pairs of cfg.threads * cfg.mpl modes each,
+// taken in queue order through the counter (reset on the stream before the launch).
+po_status launch_evolve_persistent(const EvolveConfig& cfg, int n_pulses, const PulseDev* d_desc, const double* d_A,
+                                   const double* d_A_edge, const int2* d_sel, const int2* d_queue, int n_items,
+                                   int n_workgroups, int* d_counter, double* d_f, double* d_units, hipStream_t s);
+int evolve_workgroups_per_cu(const EvolveConfig& cfg);
+po_status launch_unit_sums_from_f(const Batch& b, const PulseDev* d_desc, const double* d_f, double* d_units,
+                                  hipStream_t s);
+po_status launch_yield_from_units(const Batch& b, const PulseDev* d_desc, const double* d_units, double* d_J,
+                                  hipStream_t s);
+// Plans (plan.hip): evolution of caller tables with a plan's launch shape.
+po_status plan_evolve(const po_plan* plan, int32_t n, const po_pulse_spec* specs, const po_grid* grids,
+                      const double* d_A, const double* d_edge, double* d_f, double* d_J, hipStream_t s);
+// Kernel timers (api.hip): start returns true (and records *e0) when timers are enabled.
+bool timer_start(hipStream_t s, hipEvent_t* e0);
+void timer_stop(hipStream_t s, hipEvent_t e0);
+
 po_status launch_de_propose(const po_de_params& p, int64_t gen, const double* d_pop, double* d_trial,
                             int32_t* d_idx, hipStream_t s);
 po_status launch_de_select(const po_de_params& p, double* d_pop, double* d_fit, const double* d_trial,

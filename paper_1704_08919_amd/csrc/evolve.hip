@@ -9,43 +9,81 @@
 // both spinors of the 4x4 form.
 //
 // One time step is the exact exponential of h frozen at the step midpoint (a second-order,
-// unitary scheme): with q = (p - A_{n+1/2}) dt, q_z = e_perp dt and x = |q|^2 = (omega dt)^2,
-//     U = C(x) 1 - i S(x) (q_x tau_x + s q_y tau_y + q_z tau_z),
-//     C(x) = cos sqrt(x),  S(x) = sin sqrt(x) / sqrt(x),
-// where C and S are evaluated as truncated Maclaurin series in x whose first omitted term is
-// below 2^-56 on the launch's range of x (angle halving beyond it).  C and S are shared by both
-// blocks, because omega does not depend on s.
+// unitary scheme): with q = (p - A_{n+1/2}) dt, q_z = e_perp dt, Q_s = q_x tau_x + s q_y tau_y +
+// q_z tau_z and x = |q|^2 = (omega dt)^2 (so Q_s^2 = x),
+//     U = C(x) 1 - i S(x) Q_s = C(x) [1 - i T(x) Q_s],
+//     C(x) = cos sqrt(x),  S(x) = sin sqrt(x) / sqrt(x),  T(x) = tan sqrt(x) / sqrt(x).
+// The scalar C is common to both blocks, and f is a ratio of squared norms, so the kernel
+// applies only 1 - i T Q_s (three FMAs per real component) and divides by the norms at the
+// end; the state is rescaled by an exact power of two once per LDS chunk to stay in range.
+// For any value of T, 1 - i T Q_s is a scalar multiple of a unitary matrix (its square modulus
+// is (1 + T^2 x) 1), so rounding in T perturbs only the rotation angle.  T -- or C and S on the
+// large-step path, which halves the angle -- is a truncated Maclaurin series in x whose
+// remainder is below 2^-56 on the pulse's whole range of x; it is shared by both blocks,
+// because omega does not depend on s.
 //
-// Work decomposition: a workgroup of 256 lanes (four 64-wide waves) owns one tile of 256
-// consecutive modes of one pulse, one mode per lane.  The pulse's table of -A dt is staged
-// through LDS in chunks of 256 steps (double-buffered, one barrier per chunk) and every lane
-// reads the same record, an LDS broadcast.  The state (2 blocks x 2 complex amplitudes) stays
-// in VGPRs for all nt steps.  Partial sums of f over each tile are formed in a fixed tree
-// order, so J does not depend on scheduling.
+// Work decomposition: a workgroup of THREADS lanes (64-wide waves) owns an item of
+// THREADS x MPL consecutive modes of one pulse, MPL modes per lane.  The pulse's table of -A dt
+// is staged through LDS in chunks of 256 steps (double-buffered, one barrier per chunk) and
+// every lane reads the same record, an LDS broadcast.  The states (2 blocks x 2 complex
+// amplitudes per mode) stay in VGPRs for all nt steps.  f is summed per 64-mode unit by one
+// wave in a fixed butterfly order, and units per pulse in a fixed tree, so J does not depend on
+// the launch shape or on scheduling.  Two launch forms share the item code: one workgroup per
+// 256-mode item, or persistent workgroups that pull items (longest pulses first) from a device
+// queue through an atomic counter.
 #include "common.hpp"
+
+// Every fused multiply-add below is written out: automatic contraction is off, so each mode's
+// arithmetic is the same instruction sequence in every launch shape (threads, modes per lane,
+// persistent or not) and f is bitwise independent of the launch.
+#pragma clang fp contract(off)
 
 namespace po {
 namespace {
 
 constexpr int kChunk = 256;   // steps staged per LDS buffer
-constexpr int kThreads = 256; // lanes per workgroup = modes per tile
 
 constexpr double factorial(int n) { return n <= 1 ? 1.0 : double(n) * factorial(n - 1); }
 // Maclaurin coefficients of cos(sqrt x) and sin(sqrt x)/sqrt x.
 constexpr double cos_coef(int k) { return (k % 2 ? -1.0 : 1.0) / factorial(2 * k); }
 constexpr double sinc_coef(int k) { return (k % 2 ? -1.0 : 1.0) / factorial(2 * k + 1); }
 
-// Largest x for which the first omitted term of the degree-D series, x^{D+1}/(2D+2)!, is below 2^-56.
-constexpr double kXmax6 = 0.14;
-constexpr double kXmax7 = 0.36;
+// Maclaurin coefficients of tan(z) = sum_k a_k z^k from tan' = 1 + tan^2:
+// (k + 1) a_{k+1} = [k == 0] + sum_{i+j=k} a_i a_j, so tan(sqrt x)/sqrt x = sum_n a_{2n+1} x^n.
+struct TanCoef {
+  double a[48];
+};
+constexpr TanCoef tan_coefs() {
+  TanCoef t{};
+  for (int k = 0; k + 1 < 48; ++k) {
+    double s = (k == 0) ? 1.0 : 0.0;
+    for (int i = 0; i <= k; ++i) s += t.a[i] * t.a[k - i];
+    t.a[k + 1] = s / double(k + 1);
+  }
+  return t;
+}
+constexpr TanCoef kTan = tan_coefs();
+constexpr double tan_coef(int n) { return kTan.a[2 * n + 1]; }
 
-// Horner step k of both series, with the coefficients forced to compile-time constants.
+// Series variants.  T-series degrees and the largest x at which the remainder
+// sum_{k>n} a_{2k+1} x^k <= a_{2n+3} x^{n+1} / (1 - 0.4053 x) (the coefficient ratio rises to
+// 4/pi^2 = 0.40528...) is below 2^-56.  Beyond the last, C and S of degree 7 (first omitted
+// term x^8/16! < 2^-56 for x <= 0.3612; both series alternate with decreasing terms) after h
+// angle halvings.
+constexpr int kNumTan = 4;
+constexpr int kTanDegree[kNumTan] = {6, 8, 10, 13};
+constexpr double kTanXmax[kNumTan] = {0.0099, 0.0337, 0.0735, 0.1558};
+constexpr double kCosSinXmax = 0.3612;
+constexpr int kHalvingMode = kNumTan;
+constexpr int kNumModes = kNumTan + 1;
+
+// Horner step k of the C and S series, coefficients forced to compile-time constants.
 template <int K>
-__device__ __forceinline__ void horner(double x, double& C, double& S) {
+__device__ __forceinline__ void horner_cs(double x, double& C, double& S) {
   constexpr double cc = cos_coef(K), sc = sinc_coef(K);
   C = fma(C, x, cc);
   S = fma(S, x, sc);
-  if constexpr (K > 0) horner<K - 1>(x, C, S);
+  if constexpr (K > 0) horner_cs<K - 1>(x, C, S);
 }
 
 template <int D>
@@ -53,41 +91,69 @@ __device__ __forceinline__ void cos_sinc(double x, double& C, double& S) {
   constexpr double cd = cos_coef(D), sd = sinc_coef(D);
   C = cd;
   S = sd;
-  horner<D - 1>(x, C, S);
+  horner_cs<D - 1>(x, C, S);
 }
 
-// State layout: st[0..3] = (a_r, a_i, b_r, b_i) of block s = +1, st[4..7] the same for s = -1.
+template <int K>
+__device__ __forceinline__ void horner_tan(double x, double& T) {
+  constexpr double c = tan_coef(K);
+  T = fma(T, x, c);
+  if constexpr (K > 0) horner_tan<K - 1>(x, T);
+}
+
+// T(x) = tan(sqrt x)/sqrt x, degree N.
+template <int N>
+__device__ __forceinline__ double tan_ratio(double x) {
+  constexpr double c = tan_coef(N);
+  double T = c;
+  horner_tan<N - 1>(x, T);
+  return T;
+}
+
+// (a_r, a_i, b_r, b_i) of block s = +1 and (c_r, c_i, d_r, d_i) of block s = -1.
 struct State {
   double ar, ai, br, bi, cr, ci, dr, di;
 };
 
-// Applies U_s for both blocks given C, S and q.
+// psi <- (C - i S Q_s) psi for both blocks:
+//   s = +1:  a' = (C - i sz) a + (-sy - i sx) b ;  b' = (sy - i sx) a + (C + i sz) b,  s_q = S q;
+//   s = -1:  the same with sy -> -sy.
 __device__ __forceinline__ void rotate(State& v, double C, double S, double qx, double qy, double qz) {
   const double sx = S * qx, sy = S * qy, sz = S * qz;
-  // s = +1:  a' = (C - i sz) a + (-sy - i sx) b ;  b' = (sy - i sx) a + (C + i sz) b
-  const double ar = C * v.ar + sz * v.ai - sy * v.br + sx * v.bi;
-  const double ai = C * v.ai - sz * v.ar - sy * v.bi - sx * v.br;
-  const double br = sy * v.ar + sx * v.ai + C * v.br - sz * v.bi;
-  const double bi = sy * v.ai - sx * v.ar + C * v.bi + sz * v.br;
-  // s = -1: same with sy -> -sy
-  const double cr = C * v.cr + sz * v.ci + sy * v.dr + sx * v.di;
-  const double ci = C * v.ci - sz * v.cr + sy * v.di - sx * v.dr;
-  const double dr = -sy * v.cr + sx * v.ci + C * v.dr - sz * v.di;
-  const double di = -sy * v.ci - sx * v.cr + C * v.di + sz * v.dr;
+  const double ar = fma(sx, v.bi, fma(-sy, v.br, fma(sz, v.ai, C * v.ar)));
+  const double ai = fma(-sx, v.br, fma(-sy, v.bi, fma(-sz, v.ar, C * v.ai)));
+  const double br = fma(-sz, v.bi, fma(C, v.br, fma(sx, v.ai, sy * v.ar)));
+  const double bi = fma(sz, v.br, fma(C, v.bi, fma(-sx, v.ar, sy * v.ai)));
+  const double cr = fma(sx, v.di, fma(sy, v.dr, fma(sz, v.ci, C * v.cr)));
+  const double ci = fma(-sx, v.dr, fma(sy, v.di, fma(-sz, v.cr, C * v.ci)));
+  const double dr = fma(-sz, v.di, fma(C, v.dr, fma(sx, v.ci, -sy * v.cr)));
+  const double di = fma(sz, v.dr, fma(C, v.di, fma(-sx, v.cr, -sy * v.ci)));
   v = State{ar, ai, br, bi, cr, ci, dr, di};
 }
 
-template <int D>
-__device__ __forceinline__ void step(State& v, double2 rec, double pxdt, double pydt, double qz, double qz2) {
+// psi <- (1 - i T Q_s) psi for both blocks: the rotation above with C -> 1 and S -> T.
+__device__ __forceinline__ void rotate_tan(State& v, double T, double qx, double qy, double qz) {
+  const double tx = T * qx, ty = T * qy, tz = T * qz;
+  const double ar = fma(tx, v.bi, fma(-ty, v.br, fma(tz, v.ai, v.ar)));
+  const double ai = fma(-tx, v.br, fma(-ty, v.bi, fma(-tz, v.ar, v.ai)));
+  const double br = fma(-tz, v.bi, fma(tx, v.ai, fma(ty, v.ar, v.br)));
+  const double bi = fma(tz, v.br, fma(-tx, v.ar, fma(ty, v.ai, v.bi)));
+  const double cr = fma(tx, v.di, fma(ty, v.dr, fma(tz, v.ci, v.cr)));
+  const double ci = fma(-tx, v.dr, fma(ty, v.di, fma(-tz, v.cr, v.ci)));
+  const double dr = fma(-tz, v.di, fma(tx, v.ci, fma(-ty, v.cr, v.dr)));
+  const double di = fma(tz, v.dr, fma(-tx, v.cr, fma(-ty, v.ci, v.di)));
+  v = State{ar, ai, br, bi, cr, ci, dr, di};
+}
+
+template <int N>
+__device__ __forceinline__ void step_tan(State& v, double2 rec, double pxdt, double pydt, double qz, double qz2) {
   const double qx = pxdt + rec.x;  // rec = -A dt
   const double qy = pydt + rec.y;
   const double x = fma(qx, qx, fma(qy, qy, qz2));
-  double C, S;
-  cos_sinc<D>(x, C, S);
-  rotate(v, C, S, qx, qy, qz);
+  rotate_tan(v, tan_ratio<N>(x), qx, qy, qz);
 }
 
-// Angle-halving variant for large steps: evaluate at x / 4^h, then double h times.
+// Large-step path: C, S at x / 4^h, then h double-angle steps; the step stays unitary.
 __device__ __forceinline__ void step_halving(State& v, double2 rec, double pxdt, double pydt, double qz, double qz2,
                                              int h, double inv4h) {
   const double qx = pxdt + rec.x;
@@ -95,9 +161,9 @@ __device__ __forceinline__ void step_halving(State& v, double2 rec, double pxdt,
   const double x = fma(qx, qx, fma(qy, qy, qz2));
   double xs = x * inv4h;
   double C, S;
-  cos_sinc<7>(xs, C, S);
+  cos_sinc<7>(xs, C, S);  // xs <= kCosSinXmax
   for (int i = 0; i < h; ++i) {
-    const double c2 = fma(C, C, -xs * S * S);  // cos 2t = cos^2 t - t^2 (sin t / t)^2
+    const double c2 = fma(C, C, -(xs * S) * S);  // cos 2t = cos^2 t - t^2 (sin t / t)^2
     S = S * C;                                 // sin 2t / 2t = (sin t / t) cos t
     C = c2;
     xs *= 4.0;
@@ -105,35 +171,43 @@ __device__ __forceinline__ void step_halving(State& v, double2 rec, double pxdt,
   rotate(v, C, S, qx, qy, qz);
 }
 
+// Rescales the state by an exact power of two (no rounding) so that |psi_{+1}|^2 is O(1).
+__device__ __forceinline__ void renormalise(State& v) {
+  const double n2 = fma(v.bi, v.bi, fma(v.br, v.br, fma(v.ai, v.ai, v.ar * v.ar)));
+  const int e = -(ilogb(n2) >> 1);
+  v.ar = ldexp(v.ar, e); v.ai = ldexp(v.ai, e); v.br = ldexp(v.br, e); v.bi = ldexp(v.bi, e);
+  v.cr = ldexp(v.cr, e); v.ci = ldexp(v.ci, e); v.dr = ldexp(v.dr, e); v.di = ldexp(v.di, e);
+}
+
 // Negative-energy eigenvector of h_s(P): (-(P_x - i s P_y), w + e) / sqrt(2 w (w + e)).
 __device__ __forceinline__ void init_state(State& v, double Px, double Py, double e) {
   const double w = sqrt(fma(Px, Px, fma(Py, Py, e * e)));
-  const double n = 1.0 / sqrt(2.0 * w * (w + e));
+  const double n = 1.0 / sqrt((2.0 * w) * (w + e));
   v.ar = -Px * n; v.ai = Py * n;  v.br = (w + e) * n; v.bi = 0.0;   // s = +1
   v.cr = -Px * n; v.ci = -Py * n; v.dr = (w + e) * n; v.di = 0.0;   // s = -1
 }
 
-// f = sum_s |<+_s(P)|psi_s>|^2 with |+_s> = (w + e, P_x + i s P_y) / sqrt(2 w (w + e)).
+// f = sum_s |<+_s(P)|psi_s>|^2 / |psi_s|^2 with |+_s> = (w + e, P_x + i s P_y) / sqrt(2 w (w + e)).
 __device__ __forceinline__ double project(const State& v, double Px, double Py, double e) {
   const double w = sqrt(fma(Px, Px, fma(Py, Py, e * e)));
   const double we = w + e;
-  const double n2 = 1.0 / (2.0 * w * we);
+  const double n2 = 1.0 / ((2.0 * w) * we);
   // s = +1: (w+e) a + (P_x - i P_y) b
-  const double r1 = we * v.ar + Px * v.br + Py * v.bi;
-  const double i1 = we * v.ai + Px * v.bi - Py * v.br;
+  const double r1 = fma(Py, v.bi, fma(Px, v.br, we * v.ar));
+  const double i1 = fma(-Py, v.br, fma(Px, v.bi, we * v.ai));
   // s = -1: (w+e) c + (P_x + i P_y) d
-  const double r2 = we * v.cr + Px * v.dr - Py * v.di;
-  const double i2 = we * v.ci + Px * v.di + Py * v.dr;
-  return (r1 * r1 + i1 * i1 + r2 * r2 + i2 * i2) * n2;
+  const double r2 = fma(-Py, v.di, fma(Px, v.dr, we * v.cr));
+  const double i2 = fma(Py, v.dr, fma(Px, v.di, we * v.ci));
+  const double m1 = fma(v.bi, v.bi, fma(v.br, v.br, fma(v.ai, v.ai, v.ar * v.ar)));
+  const double m2 = fma(v.di, v.di, fma(v.dr, v.dr, fma(v.ci, v.ci, v.cr * v.cr)));
+  return (fma(i1, i1, r1 * r1) / m1 + fma(i2, i2, r2 * r2) / m2) * n2;
 }
 
-__device__ __forceinline__ int find_pulse(const PulseDev* __restrict__ desc, int n, int tile) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (desc[mid].tile_off <= tile) lo = mid; else hi = mid - 1;
-  }
-  return lo;
+// Fixed-order sum over the 64 lanes of a wave (butterfly); every lane gets the same value.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
 }
 
 // Fixed-order tree sum of one value per lane over a 256-lane workgroup.
@@ -141,26 +215,39 @@ __device__ __forceinline__ double block_sum256(double v, double* red) {
   red[threadIdx.x] = v;
   __syncthreads();
 #pragma unroll
-  for (int w = kThreads / 2; w > 0; w >>= 1) {
+  for (int w = 128; w > 0; w >>= 1) {
     if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
   return red[0];
 }
 
-// Largest |A| of each pulse's table (bounds the step angle so the series degree can be chosen).
-__global__ void __launch_bounds__(256) k_amax(const PulseDev* __restrict__ desc, const double* __restrict__ A,
-                                              const double* __restrict__ Aedge, double* __restrict__ amax) {
+__device__ __forceinline__ double grid_max_abs(double lo, int n, double dp) {
+  // largest |p| over the cell-centred points lo + (i + 1/2) dp, i = 0..n-1 (dp = 0: a sheet)
+  return fmax(fabs(lo + 0.5 * dp), fabs(lo + (n - 0.5) * dp));
+}
+
+// Per pulse: bound on x = (omega dt)^2 over every mode and step,
+//   x <= dt^2 [ max_n ((max|p_x| + |A_x,n|)^2 + (max|p_y| + |A_y,n|)^2) + 1 + max p_z^2 ],
+// and the series variant it selects (sel.x) with the number of angle halvings (sel.y).  Per
+// pulse, so all modes of a pulse use the same arithmetic whatever the launch shape.
+__global__ void __launch_bounds__(256) k_series_select(const PulseDev* __restrict__ desc, const double* __restrict__ A,
+                                                       const double* __restrict__ Aedge, int2* __restrict__ sel) {
   const PulseDev d = desc[blockIdx.x];
+  const double pxm = grid_max_abs(d.lo[0], d.n[0], d.dp[0]);
+  const double pym = grid_max_abs(d.lo[1], d.n[1], d.dp[1]);
+  const double pzm = grid_max_abs(d.lo[2], d.n[2], d.dp[2]);
   const double2* tab = reinterpret_cast<const double2*>(A) + d.tab_off;
   double m = 0.0;
   for (int64_t n = threadIdx.x; n < d.nt; n += blockDim.x) {
     const double2 a = tab[n];
-    m = fmax(m, sqrt(a.x * a.x + a.y * a.y));
+    const double u = pxm + fabs(a.x), w = pym + fabs(a.y);
+    m = fmax(m, u * u + w * w);
   }
   if (threadIdx.x < 2) {
     const double2 a = reinterpret_cast<const double2*>(Aedge)[2 * blockIdx.x + threadIdx.x];
-    m = fmax(m, sqrt(a.x * a.x + a.y * a.y));
+    const double u = pxm + fabs(a.x), w = pym + fabs(a.y);
+    m = fmax(m, u * u + w * w);
   }
   __shared__ double red[256];
   red[threadIdx.x] = m;
@@ -169,169 +256,270 @@ __global__ void __launch_bounds__(256) k_amax(const PulseDev* __restrict__ desc,
     if (int(threadIdx.x) < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) amax[blockIdx.x] = red[0];
-}
-
-template <int MODE>  // 0: degree 6, 1: degree 7, 2: degree 7 with angle halving
-__device__ __forceinline__ void run_chunk(State& v, const double2* buf, int len, double pxdt, double pydt, double qz,
-                                          double qz2, int h, double inv4h) {
-  if (len == kChunk) {
-#pragma unroll 4
-    for (int k = 0; k < kChunk; ++k) {
-      if (MODE == 0) step<6>(v, buf[k], pxdt, pydt, qz, qz2);
-      else if (MODE == 1) step<7>(v, buf[k], pxdt, pydt, qz, qz2);
-      else step_halving(v, buf[k], pxdt, pydt, qz, qz2, h, inv4h);
+  if (threadIdx.x == 0) {
+    const double xb = (red[0] + 1.0 + pzm * pzm) * d.dt * d.dt * (1.0 + 1e-6);
+    int mode = kHalvingMode, h = 0;
+    for (int k = kNumTan - 1; k >= 0; --k)
+      if (xb <= kTanXmax[k]) mode = k;
+    if (mode == kHalvingMode) {
+      double x = xb;
+      while (x > kCosSinXmax) {
+        x *= 0.25;
+        ++h;
+      }
     }
-  } else {
-    for (int k = 0; k < len; ++k) {
-      if (MODE == 0) step<6>(v, buf[k], pxdt, pydt, qz, qz2);
-      else if (MODE == 1) step<7>(v, buf[k], pxdt, pydt, qz, qz2);
-      else step_halving(v, buf[k], pxdt, pydt, qz, qz2, h, inv4h);
-    }
+    sel[blockIdx.x] = make_int2(mode, h);
   }
 }
 
-template <int MODE>
-__device__ void evolve_tile(State& v, const double2* __restrict__ tab, int nt, double dt, double pxdt, double pydt,
-                            double qz, double qz2, int h, double inv4h, double2 (*lds)[kChunk]) {
+template <int MODE>  // MODE < kHalvingMode: T series of degree kTanDegree[MODE]; else C, S with angle halving
+__device__ __forceinline__ void one_step(State& v, double2 rec, double pxdt, double pydt, double qz, double qz2, int h,
+                                         double inv4h) {
+  if constexpr (MODE < kHalvingMode) step_tan<kTanDegree[MODE]>(v, rec, pxdt, pydt, qz, qz2);
+  else step_halving(v, rec, pxdt, pydt, qz, qz2, h, inv4h);
+}
+
+struct EvolveArgs {
+  const PulseDev* desc;
+  int n_pulses;
+  const double* A;
+  const double* Aedge;
+  const int2* sel;
+  double* f;
+  double* units;
+};
+
+// Evolves the item of THREADS * MPL modes of pulse pi starting at mode `first`, writes f and the
+// 64-mode unit sums.  Every lane of the workgroup must call it (it contains barriers).
+template <int MODE, int THREADS, int MPL>
+__device__ __forceinline__ void process_item(const EvolveArgs& a, int pi, int first, int h, double2 (*lds)[kChunk]) {
+  constexpr int kPre = kChunk / THREADS;  // table records each lane stages per chunk
+  const PulseDev& d = a.desc[pi];
+  const int nt = d.nt;
+  const double dt = d.dt;
+  const int nx = d.n[0], ny = d.n[1];
+  const int64_t nmodes = int64_t(nx) * ny * d.n[2];
+  const double inv4h = ldexp(1.0, -2 * h);
+  const double2* tab = reinterpret_cast<const double2*>(a.A) + d.tab_off;
+  const double2* edge = reinterpret_cast<const double2*>(a.Aedge) + 2 * pi;
+  const double2 ain = edge[0];
+
+  State v[MPL];
+  double pxdt[MPL], pydt[MPL], qz[MPL], qz2[MPL];
+#pragma unroll
+  for (int j = 0; j < MPL; ++j) {
+    const int64_t m = int64_t(first) + j * THREADS + threadIdx.x;
+    const int64_t mm = m < nmodes ? m : 0;
+    const int ix = int(mm % nx), iy = int((mm / nx) % ny), iz = int(mm / (int64_t(nx) * ny));
+    const double px = __dadd_rn(d.lo[0], __dmul_rn(double(ix) + 0.5, d.dp[0]));
+    const double py = __dadd_rn(d.lo[1], __dmul_rn(double(iy) + 0.5, d.dp[1]));
+    const double pz = __dadd_rn(d.lo[2], __dmul_rn(double(iz) + 0.5, d.dp[2]));
+    const double e = sqrt(fma(pz, pz, 1.0));
+    init_state(v[j], px - ain.x, py - ain.y, e);
+    pxdt[j] = px * dt;
+    pydt[j] = py * dt;
+    qz[j] = e * dt;
+    qz2[j] = qz[j] * qz[j];
+  }
+
   const int nchunks = (nt + kChunk - 1) / kChunk;
-  {
-    const int n = threadIdx.x;
-    double2 a = n < nt ? tab[n] : make_double2(0.0, 0.0);
-    lds[0][threadIdx.x] = make_double2(-a.x * dt, -a.y * dt);
+#pragma unroll
+  for (int r = 0; r < kPre; ++r) {
+    const int n = r * THREADS + threadIdx.x;
+    const double2 t = n < nt ? tab[n] : make_double2(0.0, 0.0);
+    lds[0][n] = make_double2(-t.x * dt, -t.y * dt);
   }
   __syncthreads();
   for (int c = 0; c < nchunks; ++c) {
-    const int nn = (c + 1) * kChunk + threadIdx.x;
-    double2 a = (c + 1 < nchunks && nn < nt) ? tab[nn] : make_double2(0.0, 0.0);
+    double2 pre[kPre];
+#pragma unroll
+    for (int r = 0; r < kPre; ++r) {
+      const int n = (c + 1) * kChunk + r * THREADS + threadIdx.x;
+      pre[r] = (c + 1 < nchunks && n < nt) ? tab[n] : make_double2(0.0, 0.0);
+    }
+    const double2* buf = lds[c & 1];
     const int len = min(kChunk, nt - c * kChunk);
-    run_chunk<MODE>(v, lds[c & 1], len, pxdt, pydt, qz, qz2, h, inv4h);
-    lds[(c + 1) & 1][threadIdx.x] = make_double2(-a.x * dt, -a.y * dt);
+    if (len == kChunk) {
+#pragma unroll(MPL == 1 ? 4 : 2)
+      for (int k = 0; k < kChunk; ++k) {
+        const double2 rec = buf[k];
+#pragma unroll
+        for (int j = 0; j < MPL; ++j) one_step<MODE>(v[j], rec, pxdt[j], pydt[j], qz[j], qz2[j], h, inv4h);
+      }
+    } else {
+      for (int k = 0; k < len; ++k) {
+        const double2 rec = buf[k];
+#pragma unroll
+        for (int j = 0; j < MPL; ++j) one_step<MODE>(v[j], rec, pxdt[j], pydt[j], qz[j], qz2[j], h, inv4h);
+      }
+    }
+    if constexpr (MODE < kHalvingMode) {
+#pragma unroll
+      for (int j = 0; j < MPL; ++j) renormalise(v[j]);
+    }
+#pragma unroll
+    for (int r = 0; r < kPre; ++r)
+      lds[(c + 1) & 1][r * THREADS + threadIdx.x] = make_double2(-pre[r].x * dt, -pre[r].y * dt);
     __syncthreads();
   }
-}
 
-// Bound on x = (omega dt)^2 over a whole pulse (grid corners and the largest |A|), which selects the
-// series: 0 = degree 6, 1 = degree 7, 2 = degree 7 with h angle halvings.  Per pulse, so every
-// mode of a pulse uses the same arithmetic whatever the tiling.
-__device__ __forceinline__ int series_mode(const PulseDev& d, double amax, int* h, double* inv4h) {
-  const double pxm = fmax(fabs(d.lo[0]), fabs(d.lo[0] + d.n[0] * d.dp[0]));
-  const double pym = fmax(fabs(d.lo[1]), fabs(d.lo[1] + d.n[1] * d.dp[1]));
-  const double pzm = fmax(fabs(d.lo[2]), fabs(d.lo[2] + d.n[2] * d.dp[2]));
-  const double pr = sqrt(pxm * pxm + pym * pym) + amax;
-  const double xb = (pr * pr + 1.0 + pzm * pzm) * d.dt * d.dt * (1.0 + 1e-6);
-  *h = 0;
-  *inv4h = 1.0;
-  if (xb <= kXmax6) return 0;
-  if (xb <= kXmax7) return 1;
-  while (xb * *inv4h > kXmax7) {
-    ++*h;
-    *inv4h *= 0.25;
+  const double2 aout = edge[1];
+#pragma unroll
+  for (int j = 0; j < MPL; ++j) {
+    const int64_t m = int64_t(first) + j * THREADS + threadIdx.x;
+    const bool active = m < nmodes;
+    double fv = 0.0;
+    if (active) {
+      const int64_t mm = m;
+      const int ix = int(mm % nx), iy = int((mm / nx) % ny), iz = int(mm / (int64_t(nx) * ny));
+      const double px = __dadd_rn(d.lo[0], __dmul_rn(double(ix) + 0.5, d.dp[0]));
+      const double py = __dadd_rn(d.lo[1], __dmul_rn(double(iy) + 0.5, d.dp[1]));
+      const double pz = __dadd_rn(d.lo[2], __dmul_rn(double(iz) + 0.5, d.dp[2]));
+      fv = project(v[j], px - aout.x, py - aout.y, sqrt(fma(pz, pz, 1.0)));
+      if (a.f) a.f[d.mode_off + m] = fv;
+    }
+    if (a.units) {
+      const double s = wave_sum(fv);
+      const int64_t base = int64_t(first) + j * THREADS + (threadIdx.x & ~63);
+      if ((threadIdx.x & 63) == 0 && base < nmodes) a.units[d.unit_off + base / kUnit] = s;
+    }
   }
-  return 2;
 }
 
-// One launch per series variant; a workgroup whose pulse needs another variant exits at once.
-template <int MODE>
-__global__ void __launch_bounds__(kThreads) k_evolve(const PulseDev* __restrict__ desc, int n_pulses,
-                                                     const double* __restrict__ A, const double* __restrict__ Aedge,
-                                                     const double* __restrict__ amax, double* __restrict__ f,
-                                                     double* __restrict__ tile_sums) {
+template <int THREADS, int MPL>
+__device__ __forceinline__ void dispatch_item(const EvolveArgs& a, int pi, int first, double2 (*lds)[kChunk]) {
+  const int2 sl = a.sel[pi];
+  switch (sl.x) {
+    case 0: process_item<0, THREADS, MPL>(a, pi, first, 0, lds); break;
+    case 1: process_item<1, THREADS, MPL>(a, pi, first, 0, lds); break;
+    case 2: process_item<2, THREADS, MPL>(a, pi, first, 0, lds); break;
+    case 3: process_item<3, THREADS, MPL>(a, pi, first, 0, lds); break;
+    default: process_item<kHalvingMode, THREADS, MPL>(a, pi, first, sl.y, lds); break;
+  }
+}
+
+__device__ __forceinline__ int find_pulse_item(const PulseDev* __restrict__ desc, int n, int item) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (desc[mid].item_off <= item) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// One workgroup per 256-mode item.
+__global__ void __launch_bounds__(kItem) k_evolve(EvolveArgs a) {
   __shared__ double2 lds[2][kChunk];
-  __shared__ double red[kThreads];
-  const int tile = blockIdx.x;
-  const int pi = find_pulse(desc, n_pulses, tile);
-  const PulseDev& dref = desc[pi];
-  int h;
-  double inv4h;
-  if (series_mode(dref, amax[pi], &h, &inv4h) != MODE) return;
-  const int64_t mode_off = dref.mode_off, tab_off = dref.tab_off;
-  const int nt = dref.nt;
-  const double dt = dref.dt;
-  const int nx = dref.n[0], ny = dref.n[1], nz = dref.n[2];
-  const int64_t nmodes = int64_t(nx) * ny * nz;
-  const int64_t m = int64_t(tile - dref.tile_off) * kThreads + threadIdx.x;
-  const bool active = m < nmodes;
-  const int64_t mm = active ? m : 0;
-  const int ix = int(mm % nx), iy = int((mm / nx) % ny), iz = int(mm / (int64_t(nx) * ny));
-  const double px = __dadd_rn(dref.lo[0], __dmul_rn(double(ix) + 0.5, dref.dp[0]));
-  const double py = __dadd_rn(dref.lo[1], __dmul_rn(double(iy) + 0.5, dref.dp[1]));
-  const double pz = __dadd_rn(dref.lo[2], __dmul_rn(double(iz) + 0.5, dref.dp[2]));
-  const double e = sqrt(fma(pz, pz, 1.0));
+  const int item = blockIdx.x;
+  const int pi = find_pulse_item(a.desc, a.n_pulses, item);
+  dispatch_item<kItem, 1>(a, pi, (item - a.desc[pi].item_off) * kItem, lds);
+}
 
-  const double2* edge = reinterpret_cast<const double2*>(Aedge) + 2 * pi;
-  const double2 ain = edge[0], aout = edge[1];
-  State v;
-  init_state(v, px - ain.x, py - ain.y, e);
+__global__ void k_reset_counter(int* counter) { *counter = 0; }
 
-  const double pxdt = px * dt, pydt = py * dt, qz = e * dt, qz2 = qz * qz;
-  const double2* tab = reinterpret_cast<const double2*>(A) + tab_off;
-  evolve_tile<MODE>(v, tab, nt, dt, pxdt, pydt, qz, qz2, h, inv4h, lds);
-
-  const double fv = active ? project(v, px - aout.x, py - aout.y, e) : 0.0;
-  if (f && active) f[mode_off + m] = fv;
-  if (tile_sums) {
-    const double s = block_sum256(fv, red);
-    if (threadIdx.x == 0) tile_sums[tile] = s;
+// Persistent workgroups: pull {pulse, first mode} items in queue order until the queue is empty.
+// Every workgroup reaches the exit: the counter only grows, and each pull returns a new index.
+// Register budget: four waves per SIMD with one mode per lane, three with two.
+template <int THREADS, int MPL>
+__global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(MPL == 1 ? 4 : 3)))
+k_evolve_persistent(EvolveArgs a, const int2* __restrict__ queue, int n_items, int* __restrict__ counter) {
+  __shared__ double2 lds[2][kChunk];
+  __shared__ int s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int item = s_item;
+    __syncthreads();
+    if (item >= n_items) break;
+    const int2 q = queue[item];
+    dispatch_item<THREADS, MPL>(a, q.x, q.y, lds);
   }
 }
 
-// Tile sums from a stored f array, in the same tree order as the fused reduction.
-__global__ void __launch_bounds__(kThreads) k_tile_sums(const PulseDev* __restrict__ desc, int n_pulses,
-                                                        const double* __restrict__ f, double* __restrict__ tile_sums) {
-  __shared__ double red[kThreads];
-  const int tile = blockIdx.x;
-  const int pi = find_pulse(desc, n_pulses, tile);
+// Unit sums from a stored f array, in the same butterfly order as the fused reduction.
+__global__ void __launch_bounds__(256) k_unit_sums(const PulseDev* __restrict__ desc, int n_pulses,
+                                                   const double* __restrict__ f, double* __restrict__ units) {
+  const int item = blockIdx.x;
+  const int pi = find_pulse_item(desc, n_pulses, item);
   const PulseDev& d = desc[pi];
   const int64_t nmodes = int64_t(d.n[0]) * d.n[1] * d.n[2];
-  const int64_t m = int64_t(tile - d.tile_off) * kThreads + threadIdx.x;
+  const int64_t m = int64_t(item - d.item_off) * kItem + threadIdx.x;
   const double v = m < nmodes ? f[d.mode_off + m] : 0.0;
-  const double s = block_sum256(v, red);
-  if (threadIdx.x == 0) tile_sums[tile] = s;
+  const double s = wave_sum(v);
+  const int64_t base = m - (threadIdx.x & 63);
+  if ((threadIdx.x & 63) == 0 && base < nmodes) units[d.unit_off + base / kUnit] = s;
 }
 
-// J per pulse: fixed-order tree over the pulse's tile sums, times the cell volume.
-__global__ void __launch_bounds__(kThreads) k_yield(const PulseDev* __restrict__ desc,
-                                                    const double* __restrict__ tile_sums, double* __restrict__ J) {
-  __shared__ double red[kThreads];
+// J per pulse: each lane sums units t, t + 256, ... in order, then a fixed tree; times the cell volume.
+__global__ void __launch_bounds__(256) k_yield(const PulseDev* __restrict__ desc, const double* __restrict__ units,
+                                               double* __restrict__ J) {
+  __shared__ double red[256];
   const PulseDev& d = desc[blockIdx.x];
   double v = 0.0;
-  for (int t = threadIdx.x; t < d.ntiles; t += kThreads) v += tile_sums[d.tile_off + t];
+  for (int t = threadIdx.x; t < d.nunits; t += 256) v += units[d.unit_off + t];
   const double s = block_sum256(v, red);
   if (threadIdx.x == 0) J[blockIdx.x] = s * d.dv;
 }
 
+template <int THREADS, int MPL>
+void launch_persistent_t(EvolveArgs a, const int2* q, int n_items, int nwg, int* counter, hipStream_t s) {
+  hipLaunchKernelGGL((k_evolve_persistent<THREADS, MPL>), dim3(nwg), dim3(THREADS), 0, s, a, q, n_items, counter);
+}
+
 }  // namespace
 
-po_status launch_evolve(const Batch& b, const PulseDev* d_desc, const double* d_A, const double* d_A_edge,
-                        double* d_f, double* d_tile_sums, hipStream_t s) {
-  Scratch am;
-  PO_TRY(am.alloc(sizeof(double) * b.n_pulses, s));
-  double* d_amax = static_cast<double*>(am.ptr);
-  hipLaunchKernelGGL(k_amax, dim3(b.n_pulses), dim3(256), 0, s, d_desc, d_A, d_A_edge, d_amax);
-  PO_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_evolve<0>, dim3(b.total_tiles), dim3(kThreads), 0, s, d_desc, b.n_pulses, d_A, d_A_edge,
-                     d_amax, d_f, d_tile_sums);
-  PO_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_evolve<1>, dim3(b.total_tiles), dim3(kThreads), 0, s, d_desc, b.n_pulses, d_A, d_A_edge,
-                     d_amax, d_f, d_tile_sums);
-  PO_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_evolve<2>, dim3(b.total_tiles), dim3(kThreads), 0, s, d_desc, b.n_pulses, d_A, d_A_edge,
-                     d_amax, d_f, d_tile_sums);
+po_status launch_series_select(const Batch& b, const PulseDev* d_desc, const double* d_A, const double* d_A_edge,
+                               int2* d_sel, hipStream_t s) {
+  hipLaunchKernelGGL(k_series_select, dim3(b.n_pulses), dim3(256), 0, s, d_desc, d_A, d_A_edge, d_sel);
   PO_HIP(hipGetLastError());
   return PO_OK;
 }
 
-po_status launch_tile_sums_from_f(const Batch& b, const PulseDev* d_desc, const double* d_f, double* d_tile_sums,
-                                  hipStream_t s) {
-  hipLaunchKernelGGL(k_tile_sums, dim3(b.total_tiles), dim3(kThreads), 0, s, d_desc, b.n_pulses, d_f, d_tile_sums);
+po_status launch_evolve_grid(const Batch& b, const PulseDev* d_desc, const double* d_A, const double* d_A_edge,
+                             const int2* d_sel, double* d_f, double* d_units, hipStream_t s) {
+  EvolveArgs a{d_desc, b.n_pulses, d_A, d_A_edge, d_sel, d_f, d_units};
+  hipLaunchKernelGGL(k_evolve, dim3(b.total_items), dim3(kItem), 0, s, a);
   PO_HIP(hipGetLastError());
   return PO_OK;
 }
 
-po_status launch_yield_from_tiles(const Batch& b, const PulseDev* d_desc, const double* d_tile_sums, double* d_J,
+int evolve_workgroups_per_cu(const EvolveConfig& cfg) {
+  // waves resident per SIMD at the kernel's register use (4 with one mode per lane, 3 with two),
+  // four SIMDs per CU, THREADS / 64 waves per workgroup
+  const int waves_per_simd = cfg.mpl == 1 ? 4 : 3;
+  return waves_per_simd * 4 / (cfg.threads / 64);
+}
+
+po_status launch_evolve_persistent(const EvolveConfig& cfg, int n_pulses, const PulseDev* d_desc, const double* d_A,
+                                   const double* d_A_edge, const int2* d_sel, const int2* d_queue, int n_items,
+                                   int n_workgroups, int* d_counter, double* d_f, double* d_units, hipStream_t s) {
+  EvolveArgs a{d_desc, n_pulses, d_A, d_A_edge, d_sel, d_f, d_units};
+  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, d_counter);
+  PO_HIP(hipGetLastError());
+  const int key = cfg.threads * 10 + cfg.mpl;
+  switch (key) {
+    case 641: launch_persistent_t<64, 1>(a, d_queue, n_items, n_workgroups, d_counter, s); break;
+    case 642: launch_persistent_t<64, 2>(a, d_queue, n_items, n_workgroups, d_counter, s); break;
+    case 1281: launch_persistent_t<128, 1>(a, d_queue, n_items, n_workgroups, d_counter, s); break;
+    case 1282: launch_persistent_t<128, 2>(a, d_queue, n_items, n_workgroups, d_counter, s); break;
+    case 2561: launch_persistent_t<256, 1>(a, d_queue, n_items, n_workgroups, d_counter, s); break;
+    case 2562: launch_persistent_t<256, 2>(a, d_queue, n_items, n_workgroups, d_counter, s); break;
+    default: return set_error(PO_ERR_INVALID, "unsupported evolution config threads=%d mpl=%d", cfg.threads, cfg.mpl);
+  }
+  PO_HIP(hipGetLastError());
+  return PO_OK;
+}
+
+po_status launch_unit_sums_from_f(const Batch& b, const PulseDev* d_desc, const double* d_f, double* d_units,
                                   hipStream_t s) {
-  hipLaunchKernelGGL(k_yield, dim3(b.n_pulses), dim3(kThreads), 0, s, d_desc, d_tile_sums, d_J);
+  hipLaunchKernelGGL(k_unit_sums, dim3(b.total_items), dim3(256), 0, s, d_desc, b.n_pulses, d_f, d_units);
+  PO_HIP(hipGetLastError());
+  return PO_OK;
+}
+
+po_status launch_yield_from_units(const Batch& b, const PulseDev* d_desc, const double* d_units, double* d_J,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(k_yield, dim3(b.n_pulses), dim3(256), 0, s, d_desc, d_units, d_J);
   PO_HIP(hipGetLastError());
   return PO_OK;
 }
