@@ -24,31 +24,31 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 128 FLOP/clk x 2.4 GHz
-# Series variants of the evolution kernel: tan(sqrt x)/sqrt x of degree n for (omega dt)^2 <= x_n.
-TAN_DEGREES = (6, 8, 10, 13, 19)
-TAN_XMAX = (0.0099, 0.0337, 0.0735, 0.1558, 0.3552)
+# FP64 operations of one mode-step per series variant of the evolution kernel (an FMA counts 2).
+# tan(theta)/theta series of degree n: q (2 adds), x = |q|^2 (2 FMA), the series (n FMA), T q
+# (3 mul), and 1 - i T Q on two 2x2 blocks (8 real components x 3 FMA) = 57 + 2n.
+# cos/sin of degree 7 (large steps): q, x, two series (14 FMA), S q, and C - i S Q on two blocks
+# (8 x (1 mul + 3 FMA)) = 93, plus 6 per angle halving (not counted: a lower bound).
+FLOP_PER_MODE_STEP = {"tan6": 69, "tan8": 73, "tan10": 77, "tan13": 83, "cossin7_halving": 93}
+HERE_PROFILES = os.path.join(ROOT, "profiles")
+# launch shape of the plans used by the surrogate sections (fixed, so no autotuning is timed)
+PLAN = dict(threads=256, modes_per_lane=1, persistent=1)
 
 
-def flop_per_mode_step(degree):
-    """FP64 operations of one mode-step of the tangent-form step (an FMA counts 2): q (2 adds),
-    x = |q|^2 (2 FMA), the series of degree n (n FMA), T q (3 mul), and 1 - i T Q applied to two
-    2x2 blocks (8 real components x 3 FMA)."""
-    return 2 + 4 + 2 * degree + 3 + 48
-
-
-def series_degree(A, edge, spec, grid, torch):
-    """Series degree the evolution kernel selects for this table (the kernel's own bound), or None
-    when the large-step path applies."""
-    amax = float(torch.max(torch.sqrt((A ** 2).sum(-1))).item())
-    amax = max(amax, float(torch.max(torch.sqrt((edge ** 2).sum(-1))).item()))
-    pm = [max(abs(grid["lo"][d]), abs(grid["hi"][d])) for d in range(3)]
-    dt = spec["T"] / spec["nt"]
-    pr = math.hypot(pm[0], pm[1]) + amax
-    xb = (pr * pr + 1.0 + pm[2] ** 2) * dt * dt * (1.0 + 1e-6)
-    for n, x in zip(TAN_DEGREES, TAN_XMAX):
-        if xb <= x:
-            return n
-    return None
+def hbm_traffic_record():
+    """HBM bytes per evolution call from the committed counter summary, if it was taken on the
+    evolution kernel source as it is now (else None)."""
+    import hashlib
+    path = os.path.join(HERE_PROFILES, "k_evolve_hbm_traffic_de_generation.json")
+    src = os.path.join(ROOT, "paper_1704_08919_amd", "csrc", "evolve.hip")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+        with open(src, "rb") as fh:
+            sha = hashlib.sha256(fh.read()).hexdigest()
+    except OSError:
+        return None
+    return rec if rec.get("evolve_source_sha256") == sha else None
 
 
 def cpu_baseline(w, sample_modes):
@@ -69,6 +69,14 @@ def cpu_baseline(w, sample_modes):
     return {"value": ms / dt, "unit": "mode-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"pulse 0 of {w['name']}: synthesis + first {sample_modes} of {W.n_modes(grid)} modes, "
                       f"all {spec['nt']} steps ({ms:.3e} mode-steps, {dt:.1f} s, double build, OpenMP)"}
+
+
+def guarded(fn, *a):
+    """Optional sections report their failure instead of losing the whole line."""
+    try:
+        return fn(*a)
+    except Exception as e:  # noqa: BLE001
+        return {"error": f"{type(e).__name__}: {e}"}
 
 
 def uneven_batch(api, W, torch, uniform_rate, reps=3):
@@ -98,6 +106,54 @@ def uneven_batch(api, W, torch, uniform_rate, reps=3):
             "timing": "HIP events on torch's current stream around graph replays"}
 
 
+def surrogate_training(api, W, S, torch, n=100000, n_train=90000, epochs=20, seed=11):
+    """Surrogate data and training: n (coefficients, J) pairs from the plain evaluator (T = 400,
+    nt = 4096, 64x64x16 modes), network 32 -> 3 x 256 GELU -> 1 trained with Adam lr 1e-3, batch
+    1024; held-out error in decades of J."""
+    import numpy as np
+    spec, grid = W.surrogate_data_spec()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    X, J = S.generate_dataset(spec, grid, n, seed=seed, batch=1024, plan_config=PLAN)
+    gen_s = time.perf_counter() - t0
+    net = api.MLP(32, 256, 3, max_batch=1024, seed=seed + 1)
+    t1 = time.perf_counter()
+    mean, std, loss = S.train(net, X, J, n_train, epochs=epochs, batch=1024, seed=seed + 2)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    steps = epochs * (n_train // 1024)
+    pred = S.predict(net, X[n_train:], n - n_train).cpu().numpy().astype(np.float64) * std + mean
+    truth = np.log10(np.maximum(J[n_train:, 0].cpu().numpy(), 1e-300))
+    rmse = float(np.sqrt(np.mean((pred - truth) ** 2)))
+    r2 = float(1.0 - np.mean((pred - truth) ** 2) / np.var(truth))
+    net.close()
+    flop_step = 3 * 2 * 1024 * (32 * 256 + 2 * 256 * 256 + 256)  # forward + backward GEMM work
+    return {"workload": f"{n} pulses, T=400, nt=4096, 64x64x16 modes", "generate_s": gen_s,
+            "generate_mode_steps_per_s": n * 4096 * 65536 / gen_s, "train_s": train_s, "train_steps": steps,
+            "train_steps_per_s": steps / train_s, "train_tflops_bf16": flop_step * steps / train_s / 1e12,
+            "final_train_loss": loss, "heldout": n - n_train, "heldout_rmse_log10J": rmse, "heldout_r2": r2,
+            "log10J_mean": mean, "log10J_std": std}
+
+
+def surrogate_de(api, W, S, torch, pop=512, generations=200, seed=0):
+    """Surrogate-screened DE against plain DE and random screening, same seed and initial
+    population, evaluator of the surrogate-data workload (T = 400, nt = 4096, 64x64x16 modes)."""
+    spec, grid = W.surrogate_data_spec()
+    plain = S.run_de(spec, grid, pop, generations, seed, mode="plain", plan_config=PLAN)
+    target = 0.99 * plain["best_J"]
+    out = {"workload": f"pop {pop}, T=400, nt=4096, 64x64x16 modes, top 10% evaluated, retrain every 20",
+           "plain": {k: plain[k] for k in ("generations", "wall_s", "plain_evaluations", "best_J")},
+           "target_J": target, "plain_time_to_target_s": S.time_to_reach(plain["history"], target)}
+    for mode in ("surrogate", "random"):
+        r = S.run_de(spec, grid, pop, 10 * generations, seed, mode=mode, time_limit=plain["wall_s"], target=target,
+                     plan_config=PLAN)
+        tt = S.time_to_reach(r["history"], target)
+        out[mode] = {k: r[k] for k in ("generations", "wall_s", "plain_evaluations", "best_J", "train_s")}
+        out[mode]["time_to_target_s"] = tt
+        out[mode]["speedup_vs_plain_wall"] = plain["wall_s"] / tt if tt else None
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +163,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-modes", type=int, default=65536)
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch plan measurement")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate training and DE comparison")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 512 MiB device copy first (reference for HBM counter scaling)")
     args = ap.parse_args()
@@ -134,32 +191,33 @@ def main():
     D = 4 * spec["n_s"]
     prm = api.de_params(N, D, spec["n_s"], F=w["F"], CR=w["CR"], seed=args.seed + 1)
     pop = torch.as_tensor(w["coeff"].reshape(N, D), dtype=torch.float64, device="cuda").contiguous()
-    A, edge, _, _ = api.synth(w["specs"], pop)
-    degree = series_degree(A, edge, spec, grid, torch)
-    assert degree is not None, "workload left the tangent-series range"
-    del A, edge
     fit, _ = api.evaluate(w["specs"], w["grids"], pop)
     trial = torch.empty_like(pop)
     tfit = torch.empty_like(fit)
     for g in range(args.warmup):
         api.po_de_generation(prm, g, spec, grid, pop, fit, trial, tfit)
     torch.cuda.synchronize()
-    api.po_timer_read()
     api.po_timer_enable(True)
+    api.po_timer_read()
+    api.po_timer_mode_steps()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for g in range(args.warmup, args.warmup + args.steps):
         api.po_de_generation(prm, g, spec, grid, pop, fit, trial, tfit)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    api.po_timer_enable(False)
     evolve_ms, calls = api.po_timer_read()
+    by_series = api.po_timer_mode_steps()
+    api.po_timer_enable(False)
     elapsed = t1 - t0
     mode_steps = W.mode_steps(w["specs"], w["grids"])
     value = mode_steps * args.steps / elapsed
     ev_s = evolve_ms / 1e3 / max(calls, 1)
-    fps = flop_per_mode_step(degree)
-    achieved = fps * mode_steps / ev_s / 1e12
+    counted = sum(by_series.values())
+    assert counted == mode_steps * args.steps, (counted, mode_steps * args.steps)
+    flops = sum(FLOP_PER_MODE_STEP[k] * v for k, v in by_series.items())
+    achieved = flops / (evolve_ms / 1e3) / 1e12
+    traffic = hbm_traffic_record()
     best = float(fit.max().item())
     out = {
         "metric": "mode-steps/s (FP64)",
@@ -182,12 +240,17 @@ def main():
         "evolve_mode_steps_per_s": mode_steps / ev_s,
         "best_J": best,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "k_evolve (per-mode evolution + projection)", "flop_per_mode_step": fps,
-                     "series_degree": degree},
+                     "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": traffic["bytes_per_call"] if traffic else None,
+                     "kernel": "k_evolve (per-mode evolution + projection)",
+                     "flop_per_mode_step_avg": flops / counted, "mode_steps_by_series": by_series},
     }
     if not args.no_uneven:
-        out["uneven_batch"] = uneven_batch(api, W, torch, mode_steps / ev_s)
+        out["uneven_batch"] = guarded(uneven_batch, api, W, torch, mode_steps / ev_s)
+    if not args.no_surrogate:
+        from paper_1704_08919_amd import surrogate as S
+        out["surrogate_training"] = guarded(surrogate_training, api, W, S, torch)
+        out["surrogate_de"] = guarded(surrogate_de, api, W, S, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_modes)
     print(json.dumps(out), flush=True)

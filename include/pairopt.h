@@ -186,6 +186,19 @@ po_status po_de_propose(const po_de_params* prm, int64_t generation, const doubl
 po_status po_de_select(const po_de_params* prm, double* d_pop, double* d_fit, const double* d_trial,
                        const double* d_trial_fit, const uint8_t* d_mask, void* stream);
 
+/* Compaction helpers for screened generations (only some trials evaluated):
+ * po_mask_indices: d_idx[0..count) = positions of the non-zero entries of d_mask [n] uint8, in
+ *   increasing order; d_count [1] int32 or NULL.  1 <= n <= 8192.
+ * po_gather_rows: d_dst[i][:] = d_src[d_idx[i]][:] for i < n_idx (double rows of `cols`); a row
+ *   index outside [0, rows) yields a row of NaN.
+ * po_scatter_values: d_dst[:] = fill, then d_dst[d_idx[i]] = d_vals[i] for i < n_idx; indices
+ *   outside [0, n_dst) are skipped, repeated indices leave one of their values. */
+po_status po_mask_indices(const uint8_t* d_mask, int32_t n, int32_t* d_idx, int32_t* d_count, void* stream);
+po_status po_gather_rows(const double* d_src, int32_t rows, int32_t cols, const int32_t* d_idx, int32_t n_idx,
+                         double* d_dst, void* stream);
+po_status po_scatter_values(const double* d_vals, const int32_t* d_idx, int32_t n_idx, double fill, double* d_dst,
+                            int32_t n_dst, void* stream);
+
 /* One generation on a population of pulses that share one spec and one grid (dim must equal
  * 4 spec->n_s): propose -> evaluate every trial (synthesis, evolution, yield) -> select.
  *  d_pop [N][D], d_fit [N]     in/out population and fitness (J).
@@ -232,6 +245,44 @@ po_status po_plan_evaluate(struct po_plan* plan, const double* d_coeff, double* 
 void po_plan_destroy(struct po_plan* plan);
 
 /* ---------------------------------------------------------------------------------------
+ * Surrogate network (an addition to the paper's method): an MLP n_in -> depth x (width, GELU)
+ * -> 1 that maps a pulse's coefficient vector to the standardised log10 of its pair yield, used
+ * to pre-screen differential-evolution trial vectors.  BF16 weights and activations feed the
+ * matrix cores (16x16x32 bf16 MFMA) with FP32 accumulation; FP32 master weights; Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8); loss = mean squared error.  GELU is the erf form.
+ * Parameter vector (float): per hidden layer W [k_in][width] (row-major) then b [width]; then
+ * the output weights [width] and bias [1].  Requires n_in and width multiples of 32; every
+ * batch a multiple of 32 up to max_batch.  Inputs are the coefficients as doubles (rounded to
+ * bf16 inside).  A network's calls must not overlap; it is bound to the device current at
+ * creation.  Initial weights: uniform(-1/sqrt(k_in), 1/sqrt(k_in)) from Philox4x32-10(seed).
+ * --------------------------------------------------------------------------------------- */
+struct po_mlp;
+po_status po_mlp_create(int32_t n_in, int32_t width, int32_t depth, int32_t max_batch, uint64_t seed,
+                        void* stream, struct po_mlp** out);
+int64_t po_mlp_param_count(const struct po_mlp* net);
+/* d_params [param_count] float (device). set also resets the Adam state. */
+po_status po_mlp_get_params(const struct po_mlp* net, float* d_params, void* stream);
+po_status po_mlp_set_params(struct po_mlp* net, const float* d_params, void* stream);
+/* d_x [batch][n_in] double -> d_y [batch] float. */
+po_status po_mlp_forward(struct po_mlp* net, const double* d_x, int32_t batch, float* d_y, void* stream);
+/* Loss (d_loss [1] float or NULL) and gradient (d_grad [param_count] float or NULL; kept inside
+ * the network either way) for targets d_target [batch] float. */
+po_status po_mlp_loss_grad(struct po_mlp* net, const double* d_x, const float* d_target, int32_t batch,
+                           float* d_loss, float* d_grad, void* stream);
+/* One Adam step with d_grad (NULL = the network's last gradient). */
+po_status po_mlp_adam_step(struct po_mlp* net, const float* d_grad, float lr, void* stream);
+/* po_mlp_loss_grad followed by po_mlp_adam_step. */
+po_status po_mlp_train_step(struct po_mlp* net, const double* d_x, const float* d_target, int32_t batch,
+                            float lr, float* d_loss, void* stream);
+void po_mlp_destroy(struct po_mlp* net);
+/* d_mask[i] = 1 for the k largest scores (ties: lower index first; NaN ranks last), else 0.
+ * 1 <= n <= 8192. */
+po_status po_topk_mask(const float* d_score, int32_t n, int32_t k, uint8_t* d_mask, void* stream);
+/* d_out[i] = (log10(max(d_J[i], floor)) - mean) * inv_std, as float (surrogate targets). */
+po_status po_log10_standardize(const double* d_J, int32_t n, double floor_value, double mean, double inv_std,
+                               float* d_out, void* stream);
+
+/* ---------------------------------------------------------------------------------------
  * Kernel timers (diagnostics, not part of the method).  While enabled, every po_evolve_modes /
  * po_evaluate / po_de_generation call records a pair of HIP events on its stream around the
  * launches of the per-mode evolution kernel.  po_timer_read waits for the recorded events,
@@ -240,6 +291,10 @@ void po_plan_destroy(struct po_plan* plan);
  * --------------------------------------------------------------------------------------- */
 po_status po_timer_enable(int on);
 po_status po_timer_read(double* ms_total, int64_t* calls);
+/* Mode-steps evolved since the last read while timers were enabled, per series variant of the
+ * evolution kernel: counts[0..3] = tan(theta)/theta series of degree 6, 8, 10, 13; counts[4] =
+ * cos/sin series of degree 7 with angle halving.  Synchronises the device; clears the counts. */
+po_status po_timer_mode_steps(uint64_t* counts, int32_t n);
 
 #ifdef __cplusplus
 }

@@ -64,8 +64,23 @@ SIGNATURES = {
     "po_plan_get_config": ([_P, ctypes.POINTER(PlanConfig)], ctypes.c_int),
     "po_plan_evaluate": ([_P, _P, _P, _P, _P], ctypes.c_int),
     "po_plan_destroy": ([_P], None),
+    "po_mlp_create": ([_I32, _I32, _I32, _I32, ctypes.c_uint64, _P, ctypes.POINTER(_P)], ctypes.c_int),
+    "po_mlp_param_count": ([_P], ctypes.c_int64),
+    "po_mlp_get_params": ([_P, _P, _P], ctypes.c_int),
+    "po_mlp_set_params": ([_P, _P, _P], ctypes.c_int),
+    "po_mlp_forward": ([_P, _P, _I32, _P, _P], ctypes.c_int),
+    "po_mlp_loss_grad": ([_P, _P, _P, _I32, _P, _P, _P], ctypes.c_int),
+    "po_mlp_adam_step": ([_P, _P, ctypes.c_float, _P], ctypes.c_int),
+    "po_mlp_train_step": ([_P, _P, _P, _I32, ctypes.c_float, _P, _P], ctypes.c_int),
+    "po_mlp_destroy": ([_P], None),
+    "po_topk_mask": ([_P, _I32, _I32, _P, _P], ctypes.c_int),
+    "po_log10_standardize": ([_P, _I32, ctypes.c_double, ctypes.c_double, ctypes.c_double, _P, _P], ctypes.c_int),
+    "po_mask_indices": ([_P, _I32, _P, _P, _P], ctypes.c_int),
+    "po_gather_rows": ([_P, _I32, _I32, _P, _I32, _P, _P], ctypes.c_int),
+    "po_scatter_values": ([_P, _P, _I32, ctypes.c_double, _P, _I32, _P], ctypes.c_int),
     "po_timer_enable": ([ctypes.c_int], ctypes.c_int),
     "po_timer_read": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "po_timer_mode_steps": ([ctypes.POINTER(ctypes.c_uint64), _I32], ctypes.c_int),
 }
 
 _lib = None

@@ -149,6 +149,105 @@ def po_timer_read():
     return ms.value, n.value
 
 
+class MLP:
+    """po_mlp_*: the surrogate network (BF16 MFMA, FP32 accumulation and master weights, Adam)."""
+
+    def __init__(self, n_in=32, width=256, depth=3, max_batch=1024, seed=0, stream=None):
+        h = ctypes.c_void_p()
+        check(load().po_mlp_create(int(n_in), int(width), int(depth), int(max_batch), int(seed) & (2 ** 64 - 1),
+                                   _stream(stream), ctypes.byref(h)))
+        self.handle = h
+        self.n_in, self.width, self.depth, self.max_batch = n_in, width, depth, max_batch
+        self.n_params = int(load().po_mlp_param_count(h))
+
+    def get_params(self, stream=None):
+        p = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        check(load().po_mlp_get_params(self.handle, _ptr(p, torch.float32), _stream(stream)))
+        return p
+
+    def set_params(self, params, stream=None):
+        check(load().po_mlp_set_params(self.handle, _ptr(params, torch.float32), _stream(stream)))
+
+    def forward(self, x, y=None, stream=None):
+        B = x.shape[0]
+        y = torch.empty(B, dtype=torch.float32, device="cuda") if y is None else y
+        check(load().po_mlp_forward(self.handle, _ptr(x), int(B), _ptr(y, torch.float32), _stream(stream)))
+        return y
+
+    def loss_grad(self, x, target, want_grad=True, stream=None):
+        B = x.shape[0]
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        g = torch.empty(self.n_params, dtype=torch.float32, device="cuda") if want_grad else None
+        check(load().po_mlp_loss_grad(self.handle, _ptr(x), _ptr(target, torch.float32), int(B),
+                                      _ptr(loss, torch.float32), _ptr(g, torch.float32), _stream(stream)))
+        return loss, g
+
+    def adam_step(self, grad=None, lr=1e-3, stream=None):
+        check(load().po_mlp_adam_step(self.handle, _ptr(grad, torch.float32), float(lr), _stream(stream)))
+
+    def train_step(self, x, target, lr=1e-3, loss=None, stream=None):
+        check(load().po_mlp_train_step(self.handle, _ptr(x), _ptr(target, torch.float32), int(x.shape[0]), float(lr),
+                                       _ptr(loss, torch.float32), _stream(stream)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().po_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def po_topk_mask(score, k, mask=None, stream=None):
+    n = score.shape[0]
+    mask = torch.empty(n, dtype=torch.uint8, device="cuda") if mask is None else mask
+    check(load().po_topk_mask(_ptr(score, torch.float32), int(n), int(k), _ptr(mask, torch.uint8), _stream(stream)))
+    return mask
+
+
+def po_mask_indices(mask, idx=None, count=None, stream=None):
+    n = mask.shape[0]
+    idx = torch.empty(n, dtype=torch.int32, device="cuda") if idx is None else idx
+    check(load().po_mask_indices(_ptr(mask, torch.uint8), int(n), _ptr(idx, torch.int32), _ptr(count, torch.int32),
+                                 _stream(stream)))
+    return idx
+
+
+def po_gather_rows(src, idx, n_idx, dst=None, stream=None):
+    rows, cols = src.shape
+    dst = torch.empty((n_idx, cols), dtype=torch.float64, device="cuda") if dst is None else dst
+    check(load().po_gather_rows(_ptr(src), int(rows), int(cols), _ptr(idx, torch.int32), int(n_idx), _ptr(dst),
+                                _stream(stream)))
+    return dst
+
+
+def po_scatter_values(vals, idx, n_idx, dst, fill=float("-inf"), stream=None):
+    check(load().po_scatter_values(_ptr(vals), _ptr(idx, torch.int32), int(n_idx), float(fill), _ptr(dst),
+                                   int(dst.shape[0]), _stream(stream)))
+    return dst
+
+
+def po_log10_standardize(J, mean, inv_std, floor=1e-300, out=None, stream=None):
+    n = J.shape[0]
+    out = torch.empty(n, dtype=torch.float32, device="cuda") if out is None else out
+    check(load().po_log10_standardize(_ptr(J), int(n), float(floor), float(mean), float(inv_std),
+                                      _ptr(out, torch.float32), _stream(stream)))
+    return out
+
+
+SERIES_VARIANTS = ("tan6", "tan8", "tan10", "tan13", "cossin7_halving")
+
+
+def po_timer_mode_steps():
+    """Mode-steps evolved per series variant since the last read (dict); clears the counts."""
+    arr = (ctypes.c_uint64 * len(SERIES_VARIANTS))()
+    check(load().po_timer_mode_steps(arr, len(SERIES_VARIANTS)))
+    return {k: int(v) for k, v in zip(SERIES_VARIANTS, arr)}
+
+
 # ------------------------------------------------------------------------ conveniences
 def table_rows(specs):
     return sum(int(s["nt"]) for s in specs)

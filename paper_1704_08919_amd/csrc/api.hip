@@ -204,6 +204,7 @@ po_status synth_impl(int32_t n, const po_pulse_spec* specs, const double* d_coef
 std::mutex g_timer_mu;
 bool g_timer_on = false;
 std::vector<std::pair<hipEvent_t, hipEvent_t>> g_timer_events;
+unsigned long long* g_counts = nullptr;  // device: mode-steps per series variant (diagnostics)
 
 po_status evolve_impl(const Batch& b, const PulseDev* d_desc, const double* d_A, const double* d_A_edge, double* d_f,
                       double* d_J, hipStream_t s) {
@@ -219,7 +220,10 @@ po_status evolve_impl(const Batch& b, const PulseDev* d_desc, const double* d_A,
   const bool timed = timer_start(s, &e0);
   PO_TRY(launch_series_select(b, d_desc, d_A, d_A_edge, d_sel, s));
   PO_TRY(launch_evolve_grid(b, d_desc, d_A, d_A_edge, d_sel, d_f, d_units, s));
-  if (timed) timer_stop(s, e0);
+  if (timed) {
+    timer_stop(s, e0);
+    PO_TRY(timer_count(b.n_pulses, d_desc, d_sel, s));
+  }
   if (d_J) PO_TRY(launch_yield_from_units(b, d_desc, d_units, d_J, s));
   return PO_OK;
 }
@@ -237,6 +241,16 @@ bool timer_start(hipStream_t s, hipEvent_t* e0) {
     return false;
   }
   return true;
+}
+
+po_status timer_count(int n_pulses, const PulseDev* d_desc, const int2* d_sel, hipStream_t s) {
+  unsigned long long* c;
+  {
+    std::lock_guard<std::mutex> lk(g_timer_mu);
+    if (!g_timer_on || !g_counts) return PO_OK;
+    c = g_counts;
+  }
+  return launch_count_mode_steps(n_pulses, d_desc, d_sel, c, s);
 }
 
 void timer_stop(hipStream_t s, hipEvent_t e0) {
@@ -354,7 +368,28 @@ po_status po_evaluate(int32_t n, const po_pulse_spec* specs, const po_grid* grid
 
 po_status po_timer_enable(int on) {
   std::lock_guard<std::mutex> lk(g_timer_mu);
+  if (on && !g_counts) {
+    void* p = nullptr;
+    PO_HIP(hipMalloc(&p, sizeof(unsigned long long) * kSeriesVariants));
+    PO_HIP(hipMemset(p, 0, sizeof(unsigned long long) * kSeriesVariants));
+    g_counts = static_cast<unsigned long long*>(p);
+  }
   g_timer_on = on != 0;
+  return PO_OK;
+}
+
+po_status po_timer_mode_steps(uint64_t* counts, int32_t n) {
+  if (!counts || n < 1) return set_error(PO_ERR_INVALID, "counts must hold at least one entry");
+  unsigned long long h[kSeriesVariants] = {0, 0, 0, 0, 0};
+  {
+    std::lock_guard<std::mutex> lk(g_timer_mu);
+    if (g_counts) {
+      PO_HIP(hipDeviceSynchronize());
+      PO_HIP(hipMemcpy(h, g_counts, sizeof h, hipMemcpyDeviceToHost));
+      PO_HIP(hipMemset(g_counts, 0, sizeof h));
+    }
+  }
+  for (int i = 0; i < n; ++i) counts[i] = i < kSeriesVariants ? uint64_t(h[i]) : 0;
   return PO_OK;
 }
 

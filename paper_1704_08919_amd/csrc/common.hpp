@@ -109,9 +109,14 @@ po_status launch_yield_from_units(const Batch& b, const PulseDev* d_desc, const 
 // Plans (plan.hip): evolution of caller tables with a plan's launch shape.
 po_status plan_evolve(const po_plan* plan, int32_t n, const po_pulse_spec* specs, const po_grid* grids,
                       const double* d_A, const double* d_edge, double* d_f, double* d_J, hipStream_t s);
-// Kernel timers (api.hip): start returns true (and records *e0) when timers are enabled.
+// Kernel timers (api.hip): start returns true (and records *e0) when timers are enabled;
+// timer_count enqueues the per-variant mode-step count of a selection (no-op when disabled).
+constexpr int kSeriesVariants = 5;
 bool timer_start(hipStream_t s, hipEvent_t* e0);
 void timer_stop(hipStream_t s, hipEvent_t e0);
+po_status timer_count(int n_pulses, const PulseDev* d_desc, const int2* d_sel, hipStream_t s);
+po_status launch_count_mode_steps(int n_pulses, const PulseDev* d_desc, const int2* d_sel,
+                                  unsigned long long* d_counts, hipStream_t s);
 
 po_status launch_de_propose(const po_de_params& p, int64_t gen, const double* d_pop, double* d_trial,
                             int32_t* d_idx, hipStream_t s);

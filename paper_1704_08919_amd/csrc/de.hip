@@ -120,6 +120,41 @@ __global__ void __launch_bounds__(128) k_de_select(po_de_params prm, double* __r
   }
 }
 
+// Indices of the set entries of a 0/1 mask, in increasing order (single workgroup, n <= 8192).
+__global__ void __launch_bounds__(1024) k_mask_indices(const uint8_t* __restrict__ mask, int n, int32_t* __restrict__ idx,
+                                                       int32_t* __restrict__ count) {
+  __shared__ int32_t part[1024];
+  const int per = (n + 1023) / 1024;
+  const int lo = threadIdx.x * per, hi = min(n, lo + per);
+  int c = 0;
+  for (int i = lo; i < hi; ++i) c += mask[i] != 0;
+  part[threadIdx.x] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int t = 0; t < 1024; ++t) {
+      const int v = part[t];
+      part[t] = run;
+      run += v;
+    }
+    if (count) *count = run;
+  }
+  __syncthreads();
+  int o = part[threadIdx.x];
+  for (int i = lo; i < hi; ++i)
+    if (mask[i]) idx[o++] = i;
+}
+
+// Rows whose index is out of [0, rows) read as NaN (no access outside the source).
+__global__ void k_gather_rows(const double* __restrict__ src, int rows, int cols, const int32_t* __restrict__ idx,
+                              int n_idx, double* __restrict__ dst) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= int64_t(n_idx) * cols) return;
+  const int r = int(e / cols), c = int(e % cols);
+  const int q = idx[r];
+  dst[e] = (q >= 0 && q < rows) ? src[int64_t(q) * cols + c] : __longlong_as_double(0x7ff8000000000000LL);
+}
+
 }  // namespace
 
 po_status launch_de_propose(const po_de_params& p, int64_t gen, const double* d_pop, double* d_trial, int32_t* d_idx,
@@ -138,3 +173,64 @@ po_status launch_de_select(const po_de_params& p, double* d_pop, double* d_fit, 
 }
 
 }  // namespace po
+
+using namespace po;
+
+namespace {
+__global__ void k_fill(double* __restrict__ dst, int n, double v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = v;
+}
+// Indices out of [0, n_dst) are skipped (no access outside the destination).
+__global__ void k_scatter(const double* __restrict__ vals, const int32_t* __restrict__ idx, int n_idx,
+                          double* __restrict__ dst, int n_dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_idx && idx[i] >= 0 && idx[i] < n_dst) dst[idx[i]] = vals[i];
+}
+}  // namespace
+
+extern "C" {
+
+po_status po_mask_indices(const uint8_t* d_mask, int32_t n, int32_t* d_idx, int32_t* d_count, void* stream) {
+  if (n < 1 || n > 8192) return set_error(PO_ERR_INVALID, "n must be in [1, 8192]");
+  PO_TRY(check_device_range(d_mask, size_t(n), 1, "d_mask"));
+  PO_TRY(check_device_range(d_idx, sizeof(int32_t) * n, 4, "d_idx"));
+  if (d_count) PO_TRY(check_device_range(d_count, sizeof(int32_t), 4, "d_count"));
+  hipLaunchKernelGGL(k_mask_indices, dim3(1), dim3(1024), 0, static_cast<hipStream_t>(stream), d_mask, n, d_idx,
+                     d_count);
+  PO_HIP(hipGetLastError());
+  return PO_OK;
+}
+
+po_status po_gather_rows(const double* d_src, int32_t rows, int32_t cols, const int32_t* d_idx, int32_t n_idx,
+                         double* d_dst, void* stream) {
+  if (rows < 1 || cols < 1 || n_idx < 1) return set_error(PO_ERR_INVALID, "rows, cols and n_idx must be >= 1");
+  PO_TRY(check_device_range(d_src, sizeof(double) * size_t(rows) * cols, 8, "d_src"));
+  PO_TRY(check_device_range(d_idx, sizeof(int32_t) * n_idx, 4, "d_idx"));
+  PO_TRY(check_device_range(d_dst, sizeof(double) * size_t(n_idx) * cols, 8, "d_dst"));
+  const int64_t n = int64_t(n_idx) * cols;
+  hipLaunchKernelGGL(k_gather_rows, dim3(int((n + 255) / 256)), dim3(256), 0, static_cast<hipStream_t>(stream), d_src,
+                     rows, cols, d_idx, n_idx, d_dst);
+  PO_HIP(hipGetLastError());
+  return PO_OK;
+}
+
+po_status po_scatter_values(const double* d_vals, const int32_t* d_idx, int32_t n_idx, double fill, double* d_dst,
+                            int32_t n_dst, void* stream) {
+  if (n_idx < 0 || n_dst < 1) return set_error(PO_ERR_INVALID, "need n_idx >= 0 and n_dst >= 1");
+  PO_TRY(check_device_range(d_dst, sizeof(double) * n_dst, 8, "d_dst"));
+  if (n_idx > 0) {
+    PO_TRY(check_device_range(d_vals, sizeof(double) * n_idx, 8, "d_vals"));
+    PO_TRY(check_device_range(d_idx, sizeof(int32_t) * n_idx, 4, "d_idx"));
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_fill, dim3((n_dst + 255) / 256), dim3(256), 0, s, d_dst, n_dst, fill);
+  PO_HIP(hipGetLastError());
+  if (n_idx > 0) {
+    hipLaunchKernelGGL(k_scatter, dim3((n_idx + 255) / 256), dim3(256), 0, s, d_vals, d_idx, n_idx, d_dst, n_dst);
+    PO_HIP(hipGetLastError());
+  }
+  return PO_OK;
+}
+
+}  // extern "C"

@@ -407,10 +407,19 @@ __device__ __forceinline__ int find_pulse_item(const PulseDev* __restrict__ desc
   return lo;
 }
 
+// Workgroup IDs are dispatched round-robin over the 8 XCDs (each with its own L2), so block b runs
+// on XCD b % 8.  Give each XCD a contiguous range of items -- whole stretches of one pulse -- so a
+// pulse's table is fetched from HBM by one L2 rather than by all eight.  A bijection on [0, n).
+__device__ __forceinline__ int xcd_item(int b, int n) {
+  constexpr int kXcd = 8;
+  const int x = b % kXcd, q = n / kXcd, r = n % kXcd;
+  return x * q + min(x, r) + b / kXcd;
+}
+
 // One workgroup per 256-mode item.
 __global__ void __launch_bounds__(kItem) k_evolve(EvolveArgs a) {
   __shared__ double2 lds[2][kChunk];
-  const int item = blockIdx.x;
+  const int item = xcd_item(blockIdx.x, gridDim.x);
   const int pi = find_pulse_item(a.desc, a.n_pulses, item);
   dispatch_item<kItem, 1>(a, pi, (item - a.desc[pi].item_off) * kItem, lds);
 }
@@ -461,6 +470,18 @@ __global__ void __launch_bounds__(256) k_yield(const PulseDev* __restrict__ desc
   if (threadIdx.x == 0) J[blockIdx.x] = s * d.dv;
 }
 
+// Diagnostics: adds modes x nt of every pulse to the count of the series variant it selected.
+__global__ void __launch_bounds__(256) k_count_mode_steps(const PulseDev* __restrict__ desc, int n,
+                                                          const int2* __restrict__ sel,
+                                                          unsigned long long* __restrict__ counts) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const PulseDev& d = desc[i];
+    const unsigned long long ms =
+        (unsigned long long)d.nt * (unsigned long long)d.n[0] * (unsigned long long)d.n[1] * (unsigned long long)d.n[2];
+    atomicAdd(&counts[min(max(sel[i].x, 0), kNumModes - 1)], ms);
+  }
+}
+
 template <int THREADS, int MPL>
 void launch_persistent_t(EvolveArgs a, const int2* q, int n_items, int nwg, int* counter, hipStream_t s) {
   hipLaunchKernelGGL((k_evolve_persistent<THREADS, MPL>), dim3(nwg), dim3(THREADS), 0, s, a, q, n_items, counter);
@@ -506,6 +527,13 @@ po_status launch_evolve_persistent(const EvolveConfig& cfg, int n_pulses, const 
     case 2562: launch_persistent_t<256, 2>(a, d_queue, n_items, n_workgroups, d_counter, s); break;
     default: return set_error(PO_ERR_INVALID, "unsupported evolution config threads=%d mpl=%d", cfg.threads, cfg.mpl);
   }
+  PO_HIP(hipGetLastError());
+  return PO_OK;
+}
+
+po_status launch_count_mode_steps(int n_pulses, const PulseDev* d_desc, const int2* d_sel,
+                                  unsigned long long* d_counts, hipStream_t s) {
+  hipLaunchKernelGGL(k_count_mode_steps, dim3(1), dim3(256), 0, s, d_desc, n_pulses, d_sel, d_counts);
   PO_HIP(hipGetLastError());
   return PO_OK;
 }

@@ -286,7 +286,8 @@ po_status plan_evolve(const po_plan* cp, int32_t n, const po_pulse_spec* specs, 
                       const double* d_A, const double* d_edge, double* d_f, double* d_J, hipStream_t s) {
   po_plan* p = const_cast<po_plan*>(cp);
   PO_TRY(check_plan_match(p, n, specs, grids));
-  return enqueue(p, nullptr, d_A, d_edge, d_J, d_f, s);
+  PO_TRY(enqueue(p, nullptr, d_A, d_edge, d_J, d_f, s));
+  return timer_count(p->n, p->d_desc, p->d_sel, s);
 }
 
 bool plan_matches(const po_plan* p, int32_t n, const po_pulse_spec* specs, const po_grid* grids) {
@@ -364,7 +365,10 @@ po_status po_plan_evaluate(struct po_plan* p, const double* d_coeff, double* d_J
   hipEvent_t e0 = nullptr;
   const bool timed = timer_start(s, &e0);
   PO_HIP(hipGraphLaunch(p->exec, s));
-  if (timed) timer_stop(s, e0);
+  if (timed) {
+    timer_stop(s, e0);
+    PO_TRY(timer_count(p->n, p->d_desc, p->d_sel, s));
+  }
   return PO_OK;
 }
 
