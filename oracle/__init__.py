@@ -56,6 +56,10 @@ def lib():
             "orc_qke_points_ld": (None, [c_int, c_int, c_double, c_double, c_double, c_int, c_double, _D,
                                          c_int, c_int, c_long, _D, _D, c_int]),
             "orc_qke_tabulated_ld": (None, [c_int, c_double, _D, _D, _D, c_int, c_long, _D, _D, c_int]),
+            "orc_qke_tabulated_d": (None, [c_int, c_double, _D, _D, _D, c_int, c_long, _D, _D, c_int]),
+            "orc_field_samples_ld": (None, [c_int, c_int, c_double, c_double, c_double, c_int, c_int, c_double,
+                                            _D, c_int, _D, c_int, _D, _D, _D]),
+            "orc_evolve4_points_ld": (None, [c_int, c_double, _D, _D, c_long, _D, _D, c_int]),
             "orc_philox4x32_10": (None, [_U32, _U32, _U32]),
             "orc_de_propose": (None, [c_int, c_int, c_int, c_double, c_double, c_double, c_double,
                                       ctypes.c_uint64, ctypes.c_int64, _D, _D, _I32]),
@@ -185,13 +189,38 @@ def qke_points(spec, coeff, p, nt, linear=False, nthreads=0):
     return f
 
 
-def qke_tabulated(E, Ed, A, dt, p, linear=False, nthreads=0):
+def qke_tabulated(E, Ed, A, dt, p, linear=False, nthreads=0, precision="ld"):
     """Kinetic-equation f = 1 - chi_1 for caller-supplied E, dE/dt, A at the 2 nt + 1 RK4 points."""
     E, Ed, A, p = _arr(E), _arr(Ed), _arr(A), _arr(p).reshape(-1, 3)
     nt = (E.shape[0] - 1) // 2
     f = np.zeros(p.shape[0])
-    lib().orc_qke_tabulated_ld(nt, float(dt), _d(E), _d(Ed), _d(A), int(bool(linear)), p.shape[0], _d(p), _d(f),
-                               int(nthreads))
+    fn = lib().orc_qke_tabulated_ld if precision == "ld" else lib().orc_qke_tabulated_d
+    fn(nt, float(dt), _d(E), _d(Ed), _d(A), int(bool(linear)), p.shape[0], _d(p), _d(f), int(nthreads))
+    return f
+
+
+GAUSS2 = (0.5 - 3 ** 0.5 / 6, 0.5 + 3 ** 0.5 / 6)  # Gauss-Legendre nodes on [0, 1]
+
+
+def field_samples(spec, coeff, offsets, with_end=False):
+    """Scaled E, dE/dt, A at t_i + (n + c) dt for every step n and offset c (rows n len(offsets) + r),
+    plus t_f as a last row when with_end; arrays [rows][2]."""
+    coeff, off = _arr(coeff), _arr(offsets).ravel()
+    rows = spec["nt"] * off.size + (1 if with_end else 0)
+    E, Ed, A = np.zeros((rows, 2)), np.zeros((rows, 2)), np.zeros((rows, 2))
+    lib().orc_field_samples_ld(spec["n_s"], spec["order"], spec["omega_min"], spec["omega_max"], spec["T"],
+                               spec["nt"], spec["norm"], spec["norm_value"], _d(coeff), off.size, _d(off),
+                               int(bool(with_end)), _d(E), _d(Ed), _d(A))
+    return E, Ed, A
+
+
+def evolve4_points(A_gauss, A_edge, dt, p, nthreads=0):
+    """Pair density f by the fourth-order Magnus step; A_gauss[nt][2][2] holds A at the two
+    Gauss-Legendre nodes of every step (GAUSS2), A_edge[2][2] A(t_i) and A(t_f)."""
+    A_gauss, A_edge, p = _arr(A_gauss), _arr(A_edge), _arr(p).reshape(-1, 3)
+    nt = A_gauss.size // 4
+    f = np.zeros(p.shape[0])
+    lib().orc_evolve4_points_ld(nt, float(dt), _d(A_gauss), _d(A_edge), p.shape[0], _d(p), _d(f), int(nthreads))
     return f
 
 
