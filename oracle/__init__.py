@@ -57,6 +57,7 @@ def lib():
                                          c_int, c_int, c_long, _D, _D, c_int]),
             "orc_qke_tabulated_ld": (None, [c_int, c_double, _D, _D, _D, c_int, c_long, _D, _D, c_int]),
             "orc_qke_tabulated_d": (None, [c_int, c_double, _D, _D, _D, c_int, c_long, _D, _D, c_int]),
+            "orc_qke_tabulated_q": (None, [c_int, c_double, _D, _D, _D, c_int, c_long, _D, _D, _D, c_int]),
             "orc_field_samples_ld": (None, [c_int, c_int, c_double, c_double, c_double, c_int, c_int, c_double,
                                             _D, c_int, _D, c_int, _D, _D, _D]),
             "orc_evolve4_points_ld": (None, [c_int, c_double, _D, _D, c_long, _D, _D, c_int]),
@@ -64,6 +65,10 @@ def lib():
             "orc_de_propose": (None, [c_int, c_int, c_int, c_double, c_double, c_double, c_double,
                                       ctypes.c_uint64, ctypes.c_int64, _D, _D, _I32]),
             "orc_de_select": (None, [c_int, c_int, _D, _D, _D, _D, _U8]),
+            "orc_jde_propose": (None, [c_int, c_int, c_int, c_int, c_double, c_double, c_double, c_double, c_double,
+                                       c_double, ctypes.c_uint64, ctypes.c_int64, _D, _D, _D, _D, _I32]),
+            "orc_jde_select": (None, [c_int, c_int, _D, _D, _D, _D, _D, _D, _U8]),
+            "orc_island_migrate": (None, [c_int, c_int, c_int, _D, _D, _D]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -189,11 +194,18 @@ def qke_points(spec, coeff, p, nt, linear=False, nthreads=0):
     return f
 
 
-def qke_tabulated(E, Ed, A, dt, p, linear=False, nthreads=0, precision="ld"):
-    """Kinetic-equation f = 1 - chi_1 for caller-supplied E, dE/dt, A at the 2 nt + 1 RK4 points."""
+def qke_tabulated(E, Ed, A, dt, p, linear=False, nthreads=0, precision="ld", with_fmax=False):
+    """Kinetic-equation f = 1 - chi_1 for caller-supplied E, dE/dt, A at the 2 nt + 1 RK4 points.
+    precision "ld" (long double), "d" (double) or "q" (__float128; with_fmax also returns the largest
+    |1 - chi_1(t)| of each mode over the steps)."""
     E, Ed, A, p = _arr(E), _arr(Ed), _arr(A), _arr(p).reshape(-1, 3)
     nt = (E.shape[0] - 1) // 2
     f = np.zeros(p.shape[0])
+    if precision == "q":
+        fmax = np.zeros(p.shape[0])
+        lib().orc_qke_tabulated_q(nt, float(dt), _d(E), _d(Ed), _d(A), int(bool(linear)), p.shape[0], _d(p), _d(f),
+                                  _d(fmax), int(nthreads))
+        return (f, fmax) if with_fmax else f
     fn = lib().orc_qke_tabulated_ld if precision == "ld" else lib().orc_qke_tabulated_d
     fn(nt, float(dt), _d(E), _d(Ed), _d(A), int(bool(linear)), p.shape[0], _d(p), _d(f), int(nthreads))
     return f
@@ -255,3 +267,36 @@ def de_select(pop, fit, trial, trial_fit, mask=None):
         m = mask.ctypes.data_as(_U8)
     lib().orc_de_select(N, D, _d(pop), _d(fit), _d(trial), _d(trial_fit), m)
     return pop, fit
+
+
+def jde_propose(pop, fcr, generation, islands, lo, hi, seed, n_s=0, tau1=0.1, tau2=0.1, Flo=0.1, Fhi=1.0):
+    """Self-adaptive DE (jDE) trials on islands; returns (trial, trial_fcr, idx[N][4])."""
+    pop, fcr = _arr(pop), _arr(fcr)
+    N, D = pop.shape
+    trial, tfcr = np.zeros_like(pop), np.zeros_like(fcr)
+    idx = np.zeros((N, 4), dtype=np.int32)
+    lib().orc_jde_propose(N, D, int(n_s), int(islands), float(tau1), float(tau2), float(Flo), float(Fhi), float(lo),
+                          float(hi), int(seed), int(generation), _d(pop), _d(fcr), _d(trial), _d(tfcr),
+                          idx.ctypes.data_as(_I32))
+    return trial, tfcr, idx
+
+
+def jde_select(pop, fit, fcr, trial, trial_fit, trial_fcr, mask=None):
+    """jDE selection for maximisation; returns new (pop, fit, fcr)."""
+    pop, fit, fcr = _arr(pop).copy(), _arr(fit).copy(), _arr(fcr).copy()
+    trial, trial_fit, trial_fcr = _arr(trial), _arr(trial_fit), _arr(trial_fcr)
+    N, D = pop.shape
+    m = None
+    if mask is not None:
+        mask = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
+        m = mask.ctypes.data_as(_U8)
+    lib().orc_jde_select(N, D, _d(pop), _d(fit), _d(fcr), _d(trial), _d(trial_fit), _d(trial_fcr), m)
+    return pop, fit, fcr
+
+
+def island_migrate(pop, fit, fcr, islands):
+    """Ring migration (best of island k replaces the worst of island k+1); returns new (pop, fit, fcr)."""
+    pop, fit, fcr = _arr(pop).copy(), _arr(fit).copy(), _arr(fcr).copy()
+    N, D = pop.shape
+    lib().orc_island_migrate(N, D, int(islands), _d(pop), _d(fit), _d(fcr))
+    return pop, fit, fcr

@@ -20,7 +20,7 @@ def build(force: bool = True) -> str:
     if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
         return LIB
     tmp = LIB + ".tmp"
-    subprocess.run(["g++", *FLAGS, SRC, "-o", tmp], check=True)
+    subprocess.run(["g++", *FLAGS, SRC, "-o", tmp, "-lquadmath"], check=True)
     os.replace(tmp, LIB)
     return LIB
 

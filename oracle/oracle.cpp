@@ -40,12 +40,18 @@
 #include <vector>
 
 #include <omp.h>
+#include <quadmath.h>
 
 namespace {
 
 inline int nthreads_or_default(int n) { return n > 0 ? n : omp_get_max_threads(); }
 
 template <class R> inline R pi_() { return R(3.141592653589793238462643383279502884L); }
+
+// Square root for every real type used here, including __float128 (quadmath).
+inline double sqrt_r(double x) { return std::sqrt(x); }
+inline long double sqrt_r(long double x) { return std::sqrt(x); }
+inline __float128 sqrt_r(__float128 x) { return sqrtq(x); }
 
 // ---------------------------------------------------------------------------------------
 // B-splines (Sec. III): order k means degree k-1; clamped knots with multiplicity k at
@@ -111,8 +117,12 @@ Pulse<R> make_pulse(int ns, int order, double wmin, double wmax, double T, int n
   for (int l = 0; l < 2; ++l) { P.Ej[l].assign(P.nmodes, 0); P.Phj[l].assign(P.nmodes, 0); }
   for (int j = 0; j < P.nmodes; ++j) {
     P.Om[j] = R(P.nmin + j) * P.dw;
+    // the lines sample the band [omega_min, omega_max] including both ends: the basis is
+    // evaluated at Omega_j clamped into the band, so rounding of (N_min + j) Delta omega cannot
+    // move an end line off its end knot
+    const R wb = std::min(std::max(P.Om[j], P.wmin), P.wmax);
     for (int i = 0; i < ns; ++i) {
-      const R b = bspline<R>(i, order, t, P.Om[j]);
+      const R b = bspline<R>(i, order, t, wb);
       for (int l = 0; l < 2; ++l) {
         const R aE = R(coeff[(l * 2 + 0) * ns + i]);
         const R aP = pi_<R>() * (R(coeff[(l * 2 + 1) * ns + i]) + R(1));
@@ -425,17 +435,17 @@ void qke_rhs(const QkeTable<R>& tb, bool linear, int h, const R p[3], const R ch
   const R* A = &tb.A[2 * h];
   const R Px = p[0] - A[0], Py = p[1] - A[1], pz = p[2];
   const R w2 = R(1) + Px * Px + Py * Py + pz * pz;
-  const R w = std::sqrt(w2);
-  const R eperp = std::sqrt(R(1) + pz * pz);
+  const R w = sqrt_r(w2);
+  const R eperp = sqrt_r(R(1) + pz * pz);
   R Q, Rr;
   if (linear) {
-    Q = E[0] * std::sqrt(R(1) + Py * Py + pz * pz) / w2;
+    Q = E[0] * sqrt_r(R(1) + Py * Py + pz * pz) / w2;
     Rr = 0;
   } else {
     const R EE = E[0] * E[0] + E[1] * E[1];
     const R EP = E[0] * Px + E[1] * Py;
     const R X = w2 * EE - EP * EP;
-    Q = std::sqrt(std::max(X, R(0))) / w2;
+    Q = (X > 0) ? sqrt_r(X) / w2 : R(0);
     Rr = (X > 0) ? eperp * w * (E[0] * Ed[1] - E[1] * Ed[0]) / X : R(0);
   }
   // N(t,P), skew-symmetric (Eq. matrix)
@@ -448,10 +458,11 @@ void qke_rhs(const QkeTable<R>& tb, bool linear, int h, const R p[3], const R ch
 }
 
 template <class R>
-R qke_mode(const QkeTable<R>& tb, bool linear, int nt, R dt, const double p[3]) {
+R qke_mode(const QkeTable<R>& tb, bool linear, int nt, R dt, const double p[3], double* fmax = nullptr) {
   const R pr[3] = {R(p[0]), R(p[1]), R(p[2])};
   R chi[6] = {1, 0, 0, 0, 0, 0};
   R k1[6], k2[6], k3[6], k4[6], tmp[6];
+  double peak = 0;
   for (int n = 0; n < nt; ++n) {
     qke_rhs<R>(tb, linear, 2 * n, pr, chi, k1);
     for (int i = 0; i < 6; ++i) tmp[i] = chi[i] + dt / R(2) * k1[i];
@@ -461,7 +472,9 @@ R qke_mode(const QkeTable<R>& tb, bool linear, int nt, R dt, const double p[3]) 
     for (int i = 0; i < 6; ++i) tmp[i] = chi[i] + dt * k3[i];
     qke_rhs<R>(tb, linear, 2 * n + 2, pr, tmp, k4);
     for (int i = 0; i < 6; ++i) chi[i] += dt / R(6) * (k1[i] + R(2) * k2[i] + R(2) * k3[i] + k4[i]);
+    if (fmax) peak = std::max(peak, std::fabs(double(R(1) - chi[0])));
   }
+  if (fmax) *fmax = peak;
   return R(1) - chi[0];
 }
 
@@ -727,6 +740,22 @@ void orc_qke_tabulated_ld(int nt, double dt, const double* E, const double* Ed, 
   for (long m = 0; m < nm; ++m) f[m] = double(qke_mode<R>(tb, linear != 0, nt, R(dt), p + 3 * m));
 }
 
+// Same kinetic equation in quadruple precision (__float128): the parity reference.  f = 1 - chi_1
+// cancels to far below the pair density reached during the pulse, so a long-double evaluation
+// carries an absolute error ~ 2^-64 sqrt(nt); in quadruple precision that error is ~ 1e-30.
+// fmax[nm] (optional) receives the largest |1 - chi_1(t)| over the steps, which sets the FP64
+// rounding floor of f.
+void orc_qke_tabulated_q(int nt, double dt, const double* E, const double* Ed, const double* A, int linear,
+                         long nm, const double* p, double* f, double* fmax, int nthreads) {
+  using R = __float128;
+  QkeTable<R> tb;
+  const int nh = 2 * nt + 1;
+  tb.E.assign(E, E + 2 * nh); tb.Ed.assign(Ed, Ed + 2 * nh); tb.A.assign(A, A + 2 * nh);
+  const int nth = nthreads_or_default(nthreads);
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nth)
+  for (long m = 0; m < nm; ++m) f[m] = double(qke_mode<R>(tb, linear != 0, nt, R(dt), p + 3 * m, fmax ? fmax + m : nullptr));
+}
+
 // Same kinetic equation computed in double (used to size the rounding floor of the parity bar).
 void orc_qke_tabulated_d(int nt, double dt, const double* E, const double* Ed, const double* A, int linear,
                          long nm, const double* p, double* f, int nthreads) {
@@ -844,6 +873,114 @@ void orc_de_select(int N, int D, double* pop, double* fit, const double* trial, 
     if (trial_fit[i] >= fit[i]) {
       for (int j = 0; j < D; ++j) pop[(size_t)i * D + j] = trial[(size_t)i * D + j];
       fit[i] = trial_fit[i];
+    }
+  }
+}
+
+// Self-adaptive DE, jDE (Brest, Greiner, Boskovic, Mernik & Zumer, IEEE Trans. Evol. Comput. 10
+// (2006) 646; the self-adaptive variant named in Sec. IV B), on a population split into equal
+// islands (the island model of Sec. IV B).  Every individual carries its own (F, CR) in
+// fcr[N][2].  For individual i of island k (islands of S = N / islands consecutive members):
+//   * a, b, c: distinct members of island k other than i, drawn as in orc_de_propose but over
+//     the S - 1 other members (local indices, ascending skip of the exclusions);
+//   * with probability tau1, F' = Flo + u (Fhi - Flo), else F' = F_i; with probability tau2,
+//     CR' = u, else CR' = CR_i;
+//   * the trial is DE/rand/1/bin with F', CR' and the bound handling of orc_de_propose.
+// Random words as orc_de_propose; the extra block 1 + 2 ceil(D/4) gives (u_F?, u_F, u_CR?, u_CR).
+void orc_jde_propose(int N, int D, int n_s, int islands, double tau1, double tau2, double Flo, double Fhi,
+                     double lo, double hi, uint64_t seed, int64_t gen, const double* pop, const double* fcr,
+                     double* trial, double* tfcr, int32_t* idx) {
+  const int nb = (D + 3) / 4;
+  const int S = N / islands;
+  for (int i = 0; i < N; ++i) {
+    const int base = (i / S) * S, li = i - base;
+    const uint32_t w[4] = {de_word(seed, gen, i, 0, 0), de_word(seed, gen, i, 0, 1), de_word(seed, gen, i, 0, 2),
+                           de_word(seed, gen, i, 0, 3)};
+    std::vector<int> excl = {li};
+    int pick[3];
+    for (int r = 0; r < 3; ++r) {
+      int x = (int)uniform_index(w[r], (uint32_t)(S - 1 - r));
+      std::vector<int> e = excl;
+      std::sort(e.begin(), e.end());
+      for (int ex : e) if (x >= ex) ++x;
+      excl.push_back(x);
+      pick[r] = base + x;
+    }
+    const int Rj = (int)uniform_index(w[3], (uint32_t)D);
+    if (idx) { idx[4 * i] = pick[0]; idx[4 * i + 1] = pick[1]; idx[4 * i + 2] = pick[2]; idx[4 * i + 3] = Rj; }
+    const int pb = 1 + 2 * nb;
+    double F = fcr[2 * i], CR = fcr[2 * i + 1];
+    if (uniform_open01(de_word(seed, gen, i, pb, 0)) < tau1) {
+      const double span = Fhi - Flo;
+      const double step = uniform_open01(de_word(seed, gen, i, pb, 1)) * span;
+      F = Flo + step;
+    }
+    if (uniform_open01(de_word(seed, gen, i, pb, 2)) < tau2) CR = uniform_open01(de_word(seed, gen, i, pb, 3));
+    tfcr[2 * i] = F;
+    tfcr[2 * i + 1] = CR;
+    const double* a = pop + (size_t)pick[0] * D;
+    const double* b = pop + (size_t)pick[1] * D;
+    const double* c = pop + (size_t)pick[2] * D;
+    const double* x = pop + (size_t)i * D;
+    for (int j = 0; j < D; ++j) {
+      const double r = uniform_open01(de_word(seed, gen, i, 1 + j / 4, j % 4));
+      double y;
+      if (r <= CR || j == Rj) {
+        const double diff = b[j] - c[j];
+        const double step = F * diff;
+        y = a[j] + step;
+      } else {
+        y = x[j];
+      }
+      const bool phase = (n_s > 0) && ((j / n_s) % 2 == 1);
+      if (y < lo || y > hi) {
+        if (phase) {
+          const double wd = hi - lo;
+          const double k = std::floor((y - lo) / wd);
+          y = y - wd * k;
+        } else {
+          const double r2 = uniform_open01(de_word(seed, gen, i, 1 + nb + j / 4, j % 4));
+          y = lo + (hi - lo) * r2;
+        }
+      }
+      trial[(size_t)i * D + j] = y;
+    }
+  }
+}
+
+// jDE selection (maximisation): individual i takes the trial and its (F, CR) iff mask[i] != 0
+// (or mask is null) and trial_fit[i] >= fit[i].
+void orc_jde_select(int N, int D, double* pop, double* fit, double* fcr, const double* trial, const double* trial_fit,
+                    const double* tfcr, const uint8_t* mask) {
+  for (int i = 0; i < N; ++i) {
+    if (mask && !mask[i]) continue;
+    if (trial_fit[i] >= fit[i]) {
+      for (int j = 0; j < D; ++j) pop[(size_t)i * D + j] = trial[(size_t)i * D + j];
+      fit[i] = trial_fit[i];
+      fcr[2 * i] = tfcr[2 * i];
+      fcr[2 * i + 1] = tfcr[2 * i + 1];
+    }
+  }
+}
+
+// Ring migration between islands (Sec. IV B): from the state before the call, the best member
+// of island k (largest fit, lowest index on ties) replaces the worst member of island
+// (k + 1) mod islands (smallest fit, lowest index on ties) when it is strictly better; genes, fit
+// and (F, CR) move together.  All islands migrate at once.
+void orc_island_migrate(int N, int D, int islands, double* pop, double* fit, double* fcr) {
+  const int S = N / islands;
+  std::vector<double> p0(pop, pop + (size_t)N * D), f0(fit, fit + N), c0(fcr, fcr + 2 * (size_t)N);
+  for (int k = 0; k < islands; ++k) {
+    int best = k * S;
+    for (int i = k * S; i < (k + 1) * S; ++i) if (f0[i] > f0[best]) best = i;
+    const int k2 = (k + 1) % islands;
+    int worst = k2 * S;
+    for (int i = k2 * S; i < (k2 + 1) * S; ++i) if (f0[i] < f0[worst]) worst = i;
+    if (f0[best] > f0[worst]) {
+      for (int j = 0; j < D; ++j) pop[(size_t)worst * D + j] = p0[(size_t)best * D + j];
+      fit[worst] = f0[best];
+      fcr[2 * worst] = c0[2 * best];
+      fcr[2 * worst + 1] = c0[2 * best + 1];
     }
   }
 }

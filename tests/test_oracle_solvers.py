@@ -176,3 +176,16 @@ def test_magnus4_same_limit_as_second_order(orc):
     np.testing.assert_allclose(r4[2], rich, rtol=1e-6)
     # the fourth-order error drops ~16x per halving of dt (10x asserted)
     assert np.all(np.abs(r4[1] - rich) < 0.1 * np.abs(r4[0] - rich))
+
+
+def test_kinetic_equation_quad_build(orc):
+    # the quadruple-precision build agrees with the long-double one to the latter's rounding, and
+    # reports the transient density max_t |1 - chi_1(t)| >= |f(t_f)|
+    p = np.array([[0.1, 0.2, 0.0], [-0.5, 0.3, 0.4], [1.2, -0.7, 0.1]])
+    T, nt = 120.0, 1024
+    th = -T / 2 + np.arange(2 * nt + 1) * (T / nt) / 2
+    E, Ed, A = _circular_tables(th, T, 0.8, 0.35)
+    ld = orc.qke_tabulated(E, Ed, A, T / nt, p)
+    q, fm = orc.qke_tabulated(E, Ed, A, T / nt, p, precision="q", with_fmax=True)
+    assert np.all(np.abs(q - ld) <= 1e-16)
+    assert np.all(fm >= np.abs(q)) and np.all(fm > 0)
