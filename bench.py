@@ -158,6 +158,77 @@ def surrogate_de(api, W, S, torch, pop=512, generations=200, seed=0):
     return out
 
 
+def solver_comparison(api, W, torch, n_p=512, nts=(5000, 10000, 20000, 50000, 100000, 200000, 500000, 1000000),
+                      nt_exact=2_000_000, target=1e-3):
+    """The paper's accuracy-versus-time comparison (Sec. V C) on the circular multimode pulse of its
+    2-D study: error eps = int |f - f_exact| / int f_exact over the momentum sheet against the GPU
+    time per momentum point, for the second-order Dirac step, the fourth-order Magnus step and
+    the kinetic equation with RK4; f_exact = fourth-order step at nt_exact.  Only the solver
+    call is timed (tables are built beforehand)."""
+    w = W.circular_pulse(0, nt=nts[0], n_p=n_p)
+    spec0, coeff, grid = w["specs"][0], w["coeff"], w["grids"][0]
+    M = W.n_modes(grid)
+    f = torch.empty(M, dtype=torch.float64, device="cuda")
+
+    def prepare(method, nt):
+        s = [dict(spec0, nt=nt)]
+        if method == "dirac2":
+            A, edge, _, _ = api.synth(s, coeff)
+            return lambda: api.po_evolve_modes(s, [grid], A, edge, f=f)
+        if method == "magnus4":
+            _, _, Ag, edge, _ = api.field_samples(s, coeff, api.GAUSS2)
+            return lambda: api.po_evolve_modes_m4(s, [grid], Ag, edge, f=f)
+        E, Ed, A, _, _ = api.field_samples(s, coeff, api.QKE_OFFSETS, with_end=True)
+        return lambda: api.po_qke_modes(s, [grid], E, Ed, A, f=f)
+
+    def timed(method, nt):
+        call = prepare(method, nt)
+        torch.cuda.synchronize()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        call()
+        t1.record()
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1)
+
+    for method in ("dirac2", "magnus4", "qke"):  # load code objects before timing
+        timed(method, 1000)
+    ms_exact = timed("magnus4", nt_exact)
+    fe = f.clone()
+    den = float(fe.sum().item())
+
+    def eps():
+        v = float((f - fe).abs().sum().item()) / den
+        return v if math.isfinite(v) else None
+
+    timed("dirac2", nt_exact)
+    check = eps()
+    rows, reach = [], {}
+    for method in ("dirac2", "magnus4", "qke"):
+        prev = None
+        for nt in nts:
+            ms = timed(method, nt)
+            e = eps()
+            us = ms * 1e3 / M
+            rows.append({"method": method, "nt": nt, "eps": e, "us_per_mode": us,
+                         "mode_steps_per_s": M * nt / (ms * 1e-3)})
+            if method not in reach and e is not None and e <= target:
+                if prev is not None and prev[1] is not None and prev[1] > target:  # log-log interpolation
+                    a = math.log(target / prev[1]) / math.log(e / prev[1])
+                    reach[method] = math.exp(math.log(prev[0]) + a * (math.log(us) - math.log(prev[0])))
+                else:
+                    reach[method] = us
+            prev = (us, e)
+    out = {"workload": w["name"], "modes": M, "nt_exact": nt_exact, "exact_ms": ms_exact,
+           "exact_check_eps_dirac2": check, "target_eps": target, "rows": rows,
+           "us_per_mode_to_target": reach}
+    if "qke" in reach and "dirac2" in reach:
+        out["qke_over_dirac2_at_target"] = reach["qke"] / reach["dirac2"]
+    if "magnus4" in reach and "dirac2" in reach:
+        out["dirac2_over_magnus4_at_target"] = reach["dirac2"] / reach["magnus4"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -169,6 +240,8 @@ def main():
     ap.add_argument("--cpu-sample-pulses", type=int, default=3)
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch plan measurement")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate training and DE comparison")
+    ap.add_argument("--no-solvers", action="store_true",
+                    help="skip the accuracy-versus-time comparison of the Dirac, Magnus and kinetic solvers")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 512 MiB device copy first (reference for HBM counter scaling)")
     args = ap.parse_args()
@@ -252,6 +325,8 @@ def main():
     }
     if not args.no_uneven:
         out["uneven_batch"] = guarded(uneven_batch, api, W, torch, mode_steps / ev_s)
+    if not args.no_solvers:
+        out["solver_comparison"] = guarded(solver_comparison, api, W, torch)
     if not args.no_surrogate:
         from paper_1704_08919_amd import surrogate as S
         out["surrogate_training"] = guarded(surrogate_training, api, W, S, torch)

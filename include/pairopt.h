@@ -151,6 +151,51 @@ po_status po_evaluate(int32_t n_pulses, const po_pulse_spec* specs, const po_gri
                       double* d_f, double* d_J, const struct po_plan* plan, void* stream);
 
 /* ---------------------------------------------------------------------------------------
+ * po_field_samples -- scaled E, dE/dt and A of synthesised pulses at chosen points inside
+ * every step (Sec. III, Eq. field, Eq. hann and Eq. vector_potential, with the scale of the
+ * spec's normalisation as in po_pulse_synth).  Row r of pulse i is the time
+ * t_i + (r / n_sub + offsets[r % n_sub]) dt for r < nt n_sub, and t_f for the extra last row
+ * when with_end != 0; pulse i owns nt_i n_sub + with_end rows, packed in pulse order.
+ *  n_sub     points per step, 1..8;  offsets  host [n_sub], each in [0, 1] (in units of dt).
+ *  d_E, d_Ed, d_A  out [rows][2] double or NULL (dE/dt is the exact derivative of the sum).
+ *  d_A_edge  out [n_pulses][2][2] double or NULL: A(t_i), A(t_f).
+ *  d_scale   out [n_pulses] double or NULL.  At least one of d_E, d_Ed, d_A, d_A_edge is needed.
+ * Offsets {0, 1/2} with with_end = 1 give the 2 nt + 1 points of po_qke_modes; offsets
+ * {1/2 - sqrt3/6, 1/2 + sqrt3/6} the Gauss-Legendre nodes of po_evolve_modes_m4.
+ * --------------------------------------------------------------------------------------- */
+po_status po_field_samples(int32_t n_pulses, const po_pulse_spec* specs, const double* d_coeff,
+                           int32_t n_sub, const double* offsets, int32_t with_end, double* d_E,
+                           double* d_Ed, double* d_A, double* d_A_edge, double* d_scale, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * po_qke_modes -- pair density from the quantum kinetic equation of Sec. II B (the
+ * six-component system Eq. qke with the matrix Eq. matrix, chi(t_i) = (1,0,0,0,0,0),
+ * f = 1 - chi_1 at t_f), integrated by classical fourth-order Runge-Kutta with nt steps.
+ *  specs     only nt and T are read.
+ *  d_E, d_Ed, d_A  [sum (2 nt + 1)][2] double: E, dE/dt and A at t_i + h dt/2, h = 0..2 nt.
+ *  linear    0: rotating field (Q = sqrt(X)/omega^2, R = e_perp omega (E x dE/dt)_z / X,
+ *            X = omega^2 |E|^2 - (E.P)^2, and Q = R = 0 where X = 0); 1: field along x only,
+ *            with the signed Q = E_x sqrt(1 + P_y^2 + p_z^2)/omega^2 and R = 0.
+ *  d_f, d_J  as for po_evolve_modes (at least one non-NULL; J uses the same fixed-order sum).
+ * f is the spin-summed density of po_evolve_modes in the limit dt -> 0.
+ * --------------------------------------------------------------------------------------- */
+po_status po_qke_modes(int32_t n_pulses, const po_pulse_spec* specs, const po_grid* grids,
+                       const double* d_E, const double* d_Ed, const double* d_A, int32_t linear,
+                       double* d_f, double* d_J, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * po_evolve_modes_m4 -- po_evolve_modes with a fourth-order step: the fourth-order Magnus
+ * integrator with two Gauss-Legendre nodes per step (Blanes, Casas, Oteo & Ros, Phys. Rep. 470
+ * (2009) 151), the higher-order Dirac scheme that Sec. V C names as future work.  Same
+ * initial state, projection, f and J as po_evolve_modes.
+ *  d_Ag      [sum nt][2 nodes][2] double, 16-byte aligned: A at t_i + (n + 1/2 -+ sqrt3/6) dt.
+ *  d_A_edge  [n_pulses][2][2] double: A(t_i), A(t_f).
+ * --------------------------------------------------------------------------------------- */
+po_status po_evolve_modes_m4(int32_t n_pulses, const po_pulse_spec* specs, const po_grid* grids,
+                             const double* d_Ag, const double* d_A_edge, double* d_f, double* d_J,
+                             void* stream);
+
+/* ---------------------------------------------------------------------------------------
  * Differential evolution, DE/rand/1/bin with greedy selection for maximisation (Sec. IV B).
  *  pop, dim  population size N >= 4 and genes per individual D >= 1.
  *  n_s       genes in odd blocks of n_s (phase coefficients) wrap periodically into [lo, hi];
@@ -185,6 +230,55 @@ po_status po_de_propose(const po_de_params* prm, int64_t generation, const doubl
  * d_trial_fit[i] >= d_fit[i] (ties move; NaN never moves).  d_mask [N] uint8 or NULL. */
 po_status po_de_select(const po_de_params* prm, double* d_pop, double* d_fit, const double* d_trial,
                        const double* d_trial_fit, const uint8_t* d_mask, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Self-adaptive DE on islands: jDE (Brest, Greiner, Boskovic, Mernik & Zumer, IEEE Trans.
+ * Evol. Comput. 10 (2006) 646), the self-adaptive variant named in Sec. IV B, with the
+ * population split into `islands` equal islands of S = pop / islands consecutive members and
+ * ring migration between them (the island model of Sec. IV B).
+ *  pop, dim, n_s, lo, hi, seed   as po_de_params; pop must be a multiple of islands with
+ *                                S >= 4; 1 <= islands <= 64.
+ *  tau1, tau2    probabilities in [0, 1] of redrawing F and CR for a trial.
+ *  F_lo, F_hi    range of a redrawn F, 0 <= F_lo <= F_hi <= 2 (jDE: 0.1, 1.0); a redrawn CR is
+ *                uniform in (0, 1).
+ * Each individual carries (F, CR) in d_fcr [N][2] double.  Random words as po_de_propose
+ * (donors drawn among the S - 1 other members of the island), plus the block
+ * 1 + 2 ceil(D/4): (u < tau1 ?, u for F, u < tau2 ?, u for CR).  With tau1 = tau2 = 0, one
+ * island and equal (F, CR) the trials are those of po_de_propose, bit for bit.
+ * --------------------------------------------------------------------------------------- */
+typedef struct {
+  int32_t pop;
+  int32_t dim;
+  int32_t n_s;
+  int32_t islands;
+  double tau1;
+  double tau2;
+  double F_lo;
+  double F_hi;
+  double lo;
+  double hi;
+  uint64_t seed;
+} po_jde_params;
+
+/* d_pop [N][D], d_fcr [N][2] -> d_trial [N][D], d_trial_fcr [N][2]; d_idx [N][4] or NULL. */
+po_status po_jde_propose(const po_jde_params* prm, int64_t generation, const double* d_pop,
+                         const double* d_fcr, double* d_trial, double* d_trial_fcr, int32_t* d_idx,
+                         void* stream);
+/* As po_de_select; a moving individual also takes the trial's (F, CR). */
+po_status po_jde_select(const po_jde_params* prm, double* d_pop, double* d_fit, double* d_fcr,
+                        const double* d_trial, const double* d_trial_fit, const double* d_trial_fcr,
+                        const uint8_t* d_mask, void* stream);
+/* Ring migration, all islands at once from the state before the call: the best member of island
+ * k (largest fit, lowest index on ties) replaces the worst member of island (k + 1) mod islands
+ * (smallest fit, lowest index on ties) when strictly better; genes, fit and (F, CR) move
+ * together.  dim <= 64. */
+po_status po_island_migrate(const po_jde_params* prm, double* d_pop, double* d_fit, double* d_fcr,
+                            void* stream);
+/* One jDE generation on the device: propose -> synthesis -> evolution -> J -> select, as
+ * po_de_generation; the caller migrates every few generations with po_island_migrate. */
+po_status po_jde_generation(const po_jde_params* prm, int64_t generation, const po_pulse_spec* spec,
+                            const po_grid* grid, double* d_pop, double* d_fit, double* d_fcr,
+                            double* d_trial, double* d_trial_fit, double* d_trial_fcr, void* stream);
 
 /* Compaction helpers for screened generations (only some trials evaluated):
  * po_mask_indices: d_idx[0..count) = positions of the non-zero entries of d_mask [n] uint8, in

@@ -38,6 +38,13 @@ class DEParams(ctypes.Structure):
                 ("CR", ctypes.c_double), ("lo", ctypes.c_double), ("hi", ctypes.c_double), ("seed", ctypes.c_uint64)]
 
 
+class JDEParams(ctypes.Structure):
+    _fields_ = [("pop", ctypes.c_int32), ("dim", ctypes.c_int32), ("n_s", ctypes.c_int32), ("islands", ctypes.c_int32),
+                ("tau1", ctypes.c_double), ("tau2", ctypes.c_double), ("F_lo", ctypes.c_double),
+                ("F_hi", ctypes.c_double), ("lo", ctypes.c_double), ("hi", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
+
+
 class PlanConfig(ctypes.Structure):
     _fields_ = [("threads", ctypes.c_int32), ("modes_per_lane", ctypes.c_int32), ("persistent", ctypes.c_int32),
                 ("workgroups", ctypes.c_int32)]
@@ -53,9 +60,20 @@ SIGNATURES = {
     "po_pulse_synth": ([_I32, ctypes.POINTER(PulseSpec), _P, _P, _P, _P, _P, _P], ctypes.c_int),
     "po_evolve_modes": ([_I32, ctypes.POINTER(PulseSpec), ctypes.POINTER(Grid), _P, _P, _P, _P, _P, _P], ctypes.c_int),
     "po_pair_yield": ([_I32, ctypes.POINTER(Grid), _P, _P, _P], ctypes.c_int),
+    "po_field_samples": ([_I32, ctypes.POINTER(PulseSpec), _P, _I32, ctypes.POINTER(ctypes.c_double), _I32, _P, _P, _P,
+                          _P, _P, _P], ctypes.c_int),
+    "po_qke_modes": ([_I32, ctypes.POINTER(PulseSpec), ctypes.POINTER(Grid), _P, _P, _P, _I32, _P, _P, _P],
+                     ctypes.c_int),
+    "po_evolve_modes_m4": ([_I32, ctypes.POINTER(PulseSpec), ctypes.POINTER(Grid), _P, _P, _P, _P, _P],
+                           ctypes.c_int),
     "po_evaluate": ([_I32, ctypes.POINTER(PulseSpec), ctypes.POINTER(Grid), _P, _P, _P, _P, _P, _P, _P, _P],
                     ctypes.c_int),
     "po_de_propose": ([ctypes.POINTER(DEParams), _I64, _P, _P, _P, _P], ctypes.c_int),
+    "po_jde_propose": ([ctypes.POINTER(JDEParams), _I64, _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "po_jde_select": ([ctypes.POINTER(JDEParams), _P, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "po_island_migrate": ([ctypes.POINTER(JDEParams), _P, _P, _P, _P], ctypes.c_int),
+    "po_jde_generation": ([ctypes.POINTER(JDEParams), _I64, ctypes.POINTER(PulseSpec), ctypes.POINTER(Grid), _P, _P,
+                           _P, _P, _P, _P, _P], ctypes.c_int),
     "po_de_select": ([ctypes.POINTER(DEParams), _P, _P, _P, _P, _P, _P], ctypes.c_int),
     "po_de_generation": ([ctypes.POINTER(DEParams), _I64, ctypes.POINTER(PulseSpec), ctypes.POINTER(Grid), _P, _P, _P,
                           _P, _P], ctypes.c_int),

@@ -12,7 +12,7 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import DEParams, Grid, PlanConfig, PulseSpec, check, load
+from ._lib import DEParams, Grid, JDEParams, PlanConfig, PulseSpec, check, load
 
 
 def _spec_array(specs):
@@ -70,6 +70,29 @@ def po_evolve_modes(specs, grids, A, A_edge, f=None, J=None, plan=None, stream=N
     check(load().po_evolve_modes(len(specs), sp, gr, _ptr(A), _ptr(A_edge), _ptr(f), _ptr(J), ph, _stream(stream)))
 
 
+GAUSS2 = (0.5 - 3 ** 0.5 / 6, 0.5 + 3 ** 0.5 / 6)  # Gauss-Legendre nodes on [0, 1] (po_evolve_modes_m4)
+QKE_OFFSETS = (0.0, 0.5)  # with with_end=True: the 2 nt + 1 points of po_qke_modes
+
+
+def po_field_samples(specs, coeff, offsets, with_end=False, E=None, Ed=None, A=None, A_edge=None, scale=None,
+                     stream=None):
+    sp = _spec_array(specs)
+    off = (ctypes.c_double * len(offsets))(*[float(c) for c in offsets])
+    check(load().po_field_samples(len(specs), sp, _ptr(coeff), len(offsets), off, int(bool(with_end)), _ptr(E),
+                                  _ptr(Ed), _ptr(A), _ptr(A_edge), _ptr(scale), _stream(stream)))
+
+
+def po_qke_modes(specs, grids, E, Ed, A, linear=False, f=None, J=None, stream=None):
+    sp, gr = _spec_array(specs), _grid_array(grids)
+    check(load().po_qke_modes(len(specs), sp, gr, _ptr(E), _ptr(Ed), _ptr(A), int(bool(linear)), _ptr(f), _ptr(J),
+                              _stream(stream)))
+
+
+def po_evolve_modes_m4(specs, grids, Ag, A_edge, f=None, J=None, stream=None):
+    sp, gr = _spec_array(specs), _grid_array(grids)
+    check(load().po_evolve_modes_m4(len(specs), sp, gr, _ptr(Ag), _ptr(A_edge), _ptr(f), _ptr(J), _stream(stream)))
+
+
 def po_pair_yield(grids, f, J, stream=None):
     gr = _grid_array(grids)
     check(load().po_pair_yield(len(grids), gr, _ptr(f), _ptr(J), _stream(stream)))
@@ -89,6 +112,32 @@ def po_de_propose(params, generation, pop, trial, idx=None, stream=None):
 def po_de_select(params, pop, fit, trial, trial_fit, mask=None, stream=None):
     check(load().po_de_select(ctypes.byref(params), _ptr(pop), _ptr(fit), _ptr(trial), _ptr(trial_fit),
                               _ptr(mask, torch.uint8), _stream(stream)))
+
+
+def jde_params(pop, dim, n_s, islands=1, tau1=0.1, tau2=0.1, F_lo=0.1, F_hi=1.0, lo=-1.0, hi=1.0, seed=0):
+    """Parameters of self-adaptive DE (jDE) on islands (po_jde_params)."""
+    return JDEParams(int(pop), int(dim), int(n_s), int(islands), float(tau1), float(tau2), float(F_lo), float(F_hi),
+                     float(lo), float(hi), int(seed) & (2 ** 64 - 1))
+
+
+def po_jde_propose(params, generation, pop, fcr, trial, trial_fcr, idx=None, stream=None):
+    check(load().po_jde_propose(ctypes.byref(params), int(generation), _ptr(pop), _ptr(fcr), _ptr(trial),
+                                _ptr(trial_fcr), _ptr(idx, torch.int32), _stream(stream)))
+
+
+def po_jde_select(params, pop, fit, fcr, trial, trial_fit, trial_fcr, mask=None, stream=None):
+    check(load().po_jde_select(ctypes.byref(params), _ptr(pop), _ptr(fit), _ptr(fcr), _ptr(trial), _ptr(trial_fit),
+                               _ptr(trial_fcr), _ptr(mask, torch.uint8), _stream(stream)))
+
+
+def po_island_migrate(params, pop, fit, fcr, stream=None):
+    check(load().po_island_migrate(ctypes.byref(params), _ptr(pop), _ptr(fit), _ptr(fcr), _stream(stream)))
+
+
+def po_jde_generation(params, generation, spec, grid, pop, fit, fcr, trial, trial_fit, trial_fcr, stream=None):
+    sp, gr = _spec_array([spec]), _grid_array([grid])
+    check(load().po_jde_generation(ctypes.byref(params), int(generation), sp, gr, _ptr(pop), _ptr(fit), _ptr(fcr),
+                                   _ptr(trial), _ptr(trial_fit), _ptr(trial_fcr), _stream(stream)))
 
 
 def po_de_generation(params, generation, spec, grid, pop, fit, trial, trial_fit, stream=None):
@@ -287,6 +336,33 @@ def evaluate(specs, grids, coeff, want_f=False, device="cuda"):
     f = torch.empty(n_modes(grids), dtype=torch.float64, device=device) if want_f else None
     po_evaluate(specs, grids, coeff, A, edge, J, f=f)
     return J, f
+
+
+def field_samples(specs, coeff, offsets, with_end=False, device="cuda"):
+    """Allocates outputs and runs po_field_samples: returns (E, Ed, A, A_edge, scale), arrays [rows][2]."""
+    rows = sum(int(s["nt"]) * len(offsets) + (1 if with_end else 0) for s in specs)
+    coeff = torch.as_tensor(coeff, dtype=torch.float64).reshape(-1).contiguous().to(device)
+    E, Ed, A = (torch.empty((rows, 2), dtype=torch.float64, device=device) for _ in range(3))
+    edge = torch.empty((len(specs), 2, 2), dtype=torch.float64, device=device)
+    scale = torch.empty(len(specs), dtype=torch.float64, device=device)
+    po_field_samples(specs, coeff, offsets, with_end, E=E, Ed=Ed, A=A, A_edge=edge, scale=scale)
+    return E, Ed, A, edge, scale
+
+
+def qke(specs, grids, E, Ed, A, linear=False, want_f=True, want_J=True, device="cuda"):
+    """Allocates outputs and runs po_qke_modes: returns (f or None, J or None)."""
+    f = torch.empty(n_modes(grids), dtype=torch.float64, device=device) if want_f else None
+    J = torch.empty(len(specs), dtype=torch.float64, device=device) if want_J else None
+    po_qke_modes(specs, grids, E, Ed, A, linear=linear, f=f, J=J)
+    return f, J
+
+
+def evolve_m4(specs, grids, Ag, A_edge, want_f=True, want_J=True, device="cuda"):
+    """Allocates outputs and runs po_evolve_modes_m4: returns (f or None, J or None)."""
+    f = torch.empty(n_modes(grids), dtype=torch.float64, device=device) if want_f else None
+    J = torch.empty(len(specs), dtype=torch.float64, device=device) if want_J else None
+    po_evolve_modes_m4(specs, grids, Ag, A_edge, f=f, J=J)
+    return f, J
 
 
 def de_params(pop, dim, n_s, F=0.8, CR=0.9, lo=-1.0, hi=1.0, seed=0):

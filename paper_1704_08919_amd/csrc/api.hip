@@ -318,6 +318,105 @@ po_status po_evolve_modes(int32_t n, const po_pulse_spec* specs, const po_grid* 
   return evolve_impl(b, static_cast<PulseDev*>(desc.ptr), d_A, d_A_edge, d_f, d_J, s);
 }
 
+po_status po_field_samples(int32_t n, const po_pulse_spec* specs, const double* d_coeff, int32_t n_sub,
+                           const double* offsets, int32_t with_end, double* d_E, double* d_Ed, double* d_A,
+                           double* d_A_edge, double* d_scale, void* stream) {
+  if (n < 1) return set_error(PO_ERR_INVALID, "n_pulses must be >= 1");
+  PO_TRY(check_specs(n, specs));
+  if (n_sub < 1 || n_sub > kMaxSub) return set_error(PO_ERR_INVALID, "n_sub must be in [1, %d]", kMaxSub);
+  if (!offsets) return set_error(PO_ERR_INVALID, "offsets is NULL");
+  for (int r = 0; r < n_sub; ++r)
+    if (!(offsets[r] >= 0.0 && offsets[r] <= 1.0)) return set_error(PO_ERR_INVALID, "offsets[%d] not in [0, 1]", r);
+  if (!d_E && !d_Ed && !d_A && !d_A_edge)
+    return set_error(PO_ERR_INVALID, "at least one of d_E, d_Ed, d_A, d_A_edge must be non-NULL");
+  std::vector<PulseDev> h(n);
+  Batch b;
+  PO_TRY(build_batch(n, specs, nullptr, h.data(), &b));
+  int64_t rows = 0;
+  for (int i = 0; i < n; ++i) {
+    h[i].tab_off = rows;
+    rows += int64_t(specs[i].nt) * n_sub + (with_end ? 1 : 0);
+  }
+  PO_TRY(check_device_range(d_coeff, sizeof(double) * b.total_coeff, 8, "d_coeff"));
+  if (d_E) PO_TRY(check_device_range(d_E, sizeof(double) * 2 * rows, 8, "d_E"));
+  if (d_Ed) PO_TRY(check_device_range(d_Ed, sizeof(double) * 2 * rows, 8, "d_Ed"));
+  if (d_A) PO_TRY(check_device_range(d_A, sizeof(double) * 2 * rows, 8, "d_A"));
+  if (d_A_edge) PO_TRY(check_device_range(d_A_edge, sizeof(double) * 4 * n, 8, "d_A_edge"));
+  if (d_scale) PO_TRY(check_device_range(d_scale, sizeof(double) * n, 8, "d_scale"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Scratch desc, spec, part, scl;
+  PO_TRY(upload(h, desc, s));
+  PO_TRY(spec.alloc(sizeof(double) * b.total_spec, s));
+  PO_TRY(part.alloc(sizeof(double) * size_t(std::max(1, b.max_stat_blocks)) * n, s));
+  PO_TRY(scl.alloc(sizeof(double) * n, s));
+  return launch_samples(b, static_cast<PulseDev*>(desc.ptr), d_coeff, static_cast<double*>(spec.ptr),
+                        static_cast<double*>(part.ptr), static_cast<double*>(scl.ptr), n_sub, offsets, with_end ? 1 : 0,
+                        d_E, d_Ed, d_A, d_A_edge, d_scale, s);
+}
+
+po_status po_qke_modes(int32_t n, const po_pulse_spec* specs, const po_grid* grids, const double* d_E,
+                       const double* d_Ed, const double* d_A, int32_t linear, double* d_f, double* d_J, void* stream) {
+  if (n < 1) return set_error(PO_ERR_INVALID, "n_pulses must be >= 1");
+  PO_TRY(check_specs(n, specs));
+  PO_TRY(check_grids(n, grids));
+  if (!d_f && !d_J) return set_error(PO_ERR_INVALID, "at least one of d_f, d_J must be non-NULL");
+  std::vector<PulseDev> h(n);
+  Batch b;
+  PO_TRY(build_batch(n, specs, grids, h.data(), &b));
+  int64_t rows = 0;
+  for (int i = 0; i < n; ++i) {
+    h[i].tab_off = rows;
+    rows += 2 * int64_t(specs[i].nt) + 1;
+  }
+  PO_TRY(check_device_range(d_E, sizeof(double) * 2 * rows, 8, "d_E"));
+  PO_TRY(check_device_range(d_Ed, sizeof(double) * 2 * rows, 8, "d_Ed"));
+  PO_TRY(check_device_range(d_A, sizeof(double) * 2 * rows, 8, "d_A"));
+  if (d_f) PO_TRY(check_device_range(d_f, sizeof(double) * b.total_modes, 8, "d_f"));
+  if (d_J) PO_TRY(check_device_range(d_J, sizeof(double) * n, 8, "d_J"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Scratch desc, units;
+  PO_TRY(upload(h, desc, s));
+  double* d_units = nullptr;
+  if (d_J) {
+    PO_TRY(units.alloc(sizeof(double) * size_t(b.total_units), s));
+    d_units = static_cast<double*>(units.ptr);
+  }
+  const PulseDev* d_desc = static_cast<PulseDev*>(desc.ptr);
+  PO_TRY(launch_qke_grid(b, d_desc, d_E, d_Ed, d_A, linear ? 1 : 0, d_f, d_units, s));
+  if (d_J) PO_TRY(launch_yield_from_units(b, d_desc, d_units, d_J, s));
+  return PO_OK;
+}
+
+po_status po_evolve_modes_m4(int32_t n, const po_pulse_spec* specs, const po_grid* grids, const double* d_Ag,
+                             const double* d_A_edge, double* d_f, double* d_J, void* stream) {
+  if (n < 1) return set_error(PO_ERR_INVALID, "n_pulses must be >= 1");
+  PO_TRY(check_specs(n, specs));
+  PO_TRY(check_grids(n, grids));
+  if (!d_f && !d_J) return set_error(PO_ERR_INVALID, "at least one of d_f, d_J must be non-NULL");
+  std::vector<PulseDev> h(n);
+  Batch b;
+  PO_TRY(build_batch(n, specs, grids, h.data(), &b));
+  PO_TRY(check_device_range(d_Ag, sizeof(double) * 4 * b.total_rows, 16, "d_Ag"));
+  PO_TRY(check_device_range(d_A_edge, sizeof(double) * 4 * n, 8, "d_A_edge"));
+  if (d_f) PO_TRY(check_device_range(d_f, sizeof(double) * b.total_modes, 8, "d_f"));
+  if (d_J) PO_TRY(check_device_range(d_J, sizeof(double) * n, 8, "d_J"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Scratch desc, units, sel;
+  PO_TRY(upload(h, desc, s));
+  double* d_units = nullptr;
+  if (d_J) {
+    PO_TRY(units.alloc(sizeof(double) * size_t(b.total_units), s));
+    d_units = static_cast<double*>(units.ptr);
+  }
+  PO_TRY(sel.alloc(sizeof(int2) * size_t(n), s));
+  const PulseDev* d_desc = static_cast<PulseDev*>(desc.ptr);
+  int2* d_sel = static_cast<int2*>(sel.ptr);
+  PO_TRY(launch_series_select4(b, d_desc, d_Ag, d_A_edge, d_sel, s));
+  PO_TRY(launch_evolve4_grid(b, d_desc, d_Ag, d_A_edge, d_sel, d_f, d_units, s));
+  if (d_J) PO_TRY(launch_yield_from_units(b, d_desc, d_units, d_J, s));
+  return PO_OK;
+}
+
 po_status po_pair_yield(int32_t n, const po_grid* grids, const double* d_f, double* d_J, void* stream) {
   if (n < 1) return set_error(PO_ERR_INVALID, "n_pulses must be >= 1");
   PO_TRY(check_grids(n, grids));
@@ -478,6 +577,87 @@ po_status po_de_generation(const po_de_params* prm, int64_t generation, const po
   PO_TRY(synth_impl(n, specs.data(), d_trial, d_A, nullptr, d_edge, nullptr, s, b, d_desc));
   PO_TRY(evolve_impl(b, d_desc, d_A, d_edge, nullptr, d_trial_fit, s));
   return launch_de_select(*prm, d_pop, d_fit, d_trial, d_trial_fit, nullptr, s);
+}
+
+static po_status check_jde(const po_jde_params* p) {
+  if (!p) return set_error(PO_ERR_INVALID, "params is NULL");
+  if (p->islands < 1 || p->islands > 64) return set_error(PO_ERR_INVALID, "islands must be in [1, 64]");
+  if (p->pop < 4 || p->pop % p->islands != 0 || p->pop / p->islands < 4)
+    return set_error(PO_ERR_INVALID, "pop must be a multiple of islands with at least 4 members per island");
+  if (p->dim < 1) return set_error(PO_ERR_INVALID, "dim must be >= 1");
+  if (p->n_s < 0) return set_error(PO_ERR_INVALID, "n_s must be >= 0");
+  if (!(p->tau1 >= 0.0 && p->tau1 <= 1.0) || !(p->tau2 >= 0.0 && p->tau2 <= 1.0))
+    return set_error(PO_ERR_INVALID, "tau1 and tau2 must be in [0, 1]");
+  if (!(p->F_lo >= 0.0 && p->F_lo <= p->F_hi && p->F_hi <= 2.0))
+    return set_error(PO_ERR_INVALID, "need 0 <= F_lo <= F_hi <= 2");
+  if (!(p->lo < p->hi) || !std::isfinite(p->lo) || !std::isfinite(p->hi))
+    return set_error(PO_ERR_INVALID, "need finite lo < hi");
+  return PO_OK;
+}
+
+static po_status check_jde_state(const po_jde_params* prm, const double* d_pop, const double* d_fit,
+                                 const double* d_fcr) {
+  const size_t nd = size_t(prm->pop) * prm->dim;
+  PO_TRY(check_device_range(d_pop, sizeof(double) * nd, 8, "d_pop"));
+  if (d_fit) PO_TRY(check_device_range(d_fit, sizeof(double) * prm->pop, 8, "d_fit"));
+  PO_TRY(check_device_range(d_fcr, sizeof(double) * 2 * prm->pop, 8, "d_fcr"));
+  return PO_OK;
+}
+
+po_status po_jde_propose(const po_jde_params* prm, int64_t generation, const double* d_pop, const double* d_fcr,
+                         double* d_trial, double* d_trial_fcr, int32_t* d_idx, void* stream) {
+  PO_TRY(check_jde(prm));
+  PO_TRY(check_jde_state(prm, d_pop, nullptr, d_fcr));
+  PO_TRY(check_jde_state(prm, d_trial, nullptr, d_trial_fcr));
+  if (d_idx) PO_TRY(check_device_range(d_idx, sizeof(int32_t) * 4 * prm->pop, 4, "d_idx"));
+  return launch_jde_propose(*prm, generation, d_pop, d_fcr, d_trial, d_trial_fcr, d_idx,
+                            static_cast<hipStream_t>(stream));
+}
+
+po_status po_jde_select(const po_jde_params* prm, double* d_pop, double* d_fit, double* d_fcr, const double* d_trial,
+                        const double* d_trial_fit, const double* d_trial_fcr, const uint8_t* d_mask, void* stream) {
+  PO_TRY(check_jde(prm));
+  PO_TRY(check_jde_state(prm, d_pop, d_fit, d_fcr));
+  PO_TRY(check_jde_state(prm, d_trial, d_trial_fit, d_trial_fcr));
+  if (d_mask) PO_TRY(check_device_range(d_mask, prm->pop, 1, "d_mask"));
+  return launch_jde_select(*prm, d_pop, d_fit, d_fcr, d_trial, d_trial_fit, d_trial_fcr, d_mask,
+                           static_cast<hipStream_t>(stream));
+}
+
+po_status po_island_migrate(const po_jde_params* prm, double* d_pop, double* d_fit, double* d_fcr, void* stream) {
+  PO_TRY(check_jde(prm));
+  if (prm->dim > 64) return set_error(PO_ERR_INVALID, "migration supports dim <= 64");
+  PO_TRY(check_jde_state(prm, d_pop, d_fit, d_fcr));
+  return launch_island_migrate(*prm, d_pop, d_fit, d_fcr, static_cast<hipStream_t>(stream));
+}
+
+po_status po_jde_generation(const po_jde_params* prm, int64_t generation, const po_pulse_spec* spec, const po_grid* grid,
+                            double* d_pop, double* d_fit, double* d_fcr, double* d_trial, double* d_trial_fit,
+                            double* d_trial_fcr, void* stream) {
+  PO_TRY(check_jde(prm));
+  PO_TRY(check_specs(1, spec));
+  PO_TRY(check_grids(1, grid));
+  if (prm->dim != 4 * spec->n_s) return set_error(PO_ERR_INVALID, "dim must equal 4 n_s");
+  PO_TRY(check_jde_state(prm, d_pop, d_fit, d_fcr));
+  PO_TRY(check_jde_state(prm, d_trial, d_trial_fit, d_trial_fcr));
+  const int32_t n = prm->pop;
+  std::vector<po_pulse_spec> specs(n, *spec);
+  std::vector<po_grid> grids(n, *grid);
+  std::vector<PulseDev> h(n);
+  Batch b;
+  PO_TRY(build_batch(n, specs.data(), grids.data(), h.data(), &b));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Scratch desc, tab, edge;
+  PO_TRY(upload(h, desc, s));
+  PO_TRY(tab.alloc(sizeof(double) * 2 * b.total_rows, s));
+  PO_TRY(edge.alloc(sizeof(double) * 4 * n, s));
+  const PulseDev* d_desc = static_cast<PulseDev*>(desc.ptr);
+  double* d_A = static_cast<double*>(tab.ptr);
+  double* d_edge = static_cast<double*>(edge.ptr);
+  PO_TRY(launch_jde_propose(*prm, generation, d_pop, d_fcr, d_trial, d_trial_fcr, nullptr, s));
+  PO_TRY(synth_impl(n, specs.data(), d_trial, d_A, nullptr, d_edge, nullptr, s, b, d_desc));
+  PO_TRY(evolve_impl(b, d_desc, d_A, d_edge, nullptr, d_trial_fit, s));
+  return launch_jde_select(*prm, d_pop, d_fit, d_fcr, d_trial, d_trial_fit, d_trial_fcr, nullptr, s);
 }
 
 }  // extern "C"

@@ -35,6 +35,7 @@ constexpr int kUnit = 64;         // momentum modes per reduction unit, one wave
 constexpr int kItem = 256;        // modes per workgroup in the default (non-plan) evolution launch
 constexpr int kMaxLines = 8192;   // spectral lines per pulse
 constexpr int kMaxNs = 64;        // B-spline coefficients per spectral function
+constexpr int kMaxSub = 8;        // sample points per step of po_field_samples
 
 struct PulseDev {
   int64_t tab_off;    // first table row (rows of 2 doubles)
@@ -83,6 +84,11 @@ struct Scratch {
 po_status launch_synth(const Batch& b, const PulseDev* d_desc, const double* d_coeff, double* d_spec,
                        double* d_part, double* d_scale_ws, double* d_A, double* d_E, double* d_A_edge,
                        double* d_scale_out, hipStream_t s);
+// Scaled field samples at t_i + (n + offsets[r]) dt (rows per pulse nt n_sub + with_end, from
+// desc.tab_off); any of d_E, d_Ed, d_A, d_A_edge may be NULL.
+po_status launch_samples(const Batch& b, const PulseDev* d_desc, const double* d_coeff, double* d_spec, double* d_part,
+                         double* d_scale_ws, int n_sub, const double* offsets, int with_end, double* d_E,
+                         double* d_Ed, double* d_A, double* d_A_edge, double* d_scale_out, hipStream_t s);
 // Launch shape of the evolution kernel.  threads: lanes per workgroup (64, 128, 256);
 // mpl: modes per lane (1, 2); persistent: workgroups pull items from a device queue.
 struct EvolveConfig {
@@ -102,6 +108,15 @@ po_status launch_evolve_persistent(const EvolveConfig& cfg, int n_pulses, const 
                                    const double* d_A_edge, const int2* d_sel, const int2* d_queue, int n_items,
                                    int n_workgroups, int* d_counter, double* d_f, double* d_units, hipStream_t s);
 int evolve_workgroups_per_cu(const EvolveConfig& cfg);
+// Fourth-order (Magnus) evolution: series selection over both nodes of every step and one
+// workgroup per 256 modes; d_Ag is [sum nt][2 nodes][2] with desc.tab_off counted in steps.
+po_status launch_series_select4(const Batch& b, const PulseDev* d_desc, const double* d_Ag, const double* d_A_edge,
+                                int2* d_sel, hipStream_t s);
+po_status launch_evolve4_grid(const Batch& b, const PulseDev* d_desc, const double* d_Ag, const double* d_A_edge,
+                              const int2* d_sel, double* d_f, double* d_units, hipStream_t s);
+// Kinetic equation (qke.hip): tables at the 2 nt + 1 half-step points, desc.tab_off in points.
+po_status launch_qke_grid(const Batch& b, const PulseDev* d_desc, const double* d_E, const double* d_Ed,
+                          const double* d_A, int linear, double* d_f, double* d_units, hipStream_t s);
 po_status launch_unit_sums_from_f(const Batch& b, const PulseDev* d_desc, const double* d_f, double* d_units,
                                   hipStream_t s);
 po_status launch_yield_from_units(const Batch& b, const PulseDev* d_desc, const double* d_units, double* d_J,
@@ -122,5 +137,11 @@ po_status launch_de_propose(const po_de_params& p, int64_t gen, const double* d_
                             int32_t* d_idx, hipStream_t s);
 po_status launch_de_select(const po_de_params& p, double* d_pop, double* d_fit, const double* d_trial,
                            const double* d_trial_fit, const uint8_t* d_mask, hipStream_t s);
+
+po_status launch_jde_propose(const po_jde_params& p, int64_t gen, const double* d_pop, const double* d_fcr,
+                             double* d_trial, double* d_tfcr, int32_t* d_idx, hipStream_t s);
+po_status launch_jde_select(const po_jde_params& p, double* d_pop, double* d_fit, double* d_fcr, const double* d_trial,
+                            const double* d_tfit, const double* d_tfcr, const uint8_t* d_mask, hipStream_t s);
+po_status launch_island_migrate(const po_jde_params& p, double* d_pop, double* d_fit, double* d_fcr, hipStream_t s);
 
 }  // namespace po

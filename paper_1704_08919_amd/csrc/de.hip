@@ -12,6 +12,9 @@
 namespace po {
 namespace {
 
+constexpr int kMaxIslands = 64;      // islands per population (one migrating thread each)
+constexpr int kMaxMigrateDim = 64;   // genes per individual staged by the migration kernel
+
 struct U4 {
   uint32_t x, y, z, w;
 };
@@ -155,6 +158,137 @@ __global__ void k_gather_rows(const double* __restrict__ src, int rows, int cols
   dst[e] = (q >= 0 && q < rows) ? src[int64_t(q) * cols + c] : __longlong_as_double(0x7ff8000000000000LL);
 }
 
+// Self-adaptive DE (jDE: Brest, Greiner, Boskovic, Mernik & Zumer, IEEE Trans. Evol. Comput. 10
+// (2006) 646, the variant named in Sec. IV B) on islands of S = pop / islands consecutive
+// members.  Donors are drawn among the other members of the individual's island; (F, CR) are
+// redrawn with probabilities tau1, tau2 from the extra Philox block 1 + 2 ceil(D/4).
+__global__ void __launch_bounds__(128) k_jde_propose(po_jde_params prm, int64_t gen, const double* __restrict__ pop,
+                                                     const double* __restrict__ fcr, double* __restrict__ trial,
+                                                     double* __restrict__ tfcr, int32_t* __restrict__ idx) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int N = prm.pop, D = prm.dim;
+  if (i >= N) return;
+  const int S = N / prm.islands, base = (i / S) * S;
+  const uint32_t k0 = uint32_t(prm.seed), k1 = uint32_t(prm.seed >> 32);
+  const uint32_t g0 = uint32_t(uint64_t(gen)), g1 = uint32_t(uint64_t(gen) >> 32);
+  const U4 r0 = philox4x32_10(U4{uint32_t(i), 0u, g0, g1}, k0, k1);
+  int ex[4] = {i - base, 0, 0, 0};
+  int nex = 1;
+  int pick[3];
+  const uint32_t w3[3] = {r0.x, r0.y, r0.z};
+  for (int r = 0; r < 3; ++r) {
+    int x = int(index_below(w3[r], uint32_t(S - 1 - r)));
+    int srt[4];
+    for (int q = 0; q < nex; ++q) srt[q] = ex[q];
+    for (int q = 1; q < nex; ++q)
+      for (int z = q; z > 0 && srt[z - 1] > srt[z]; --z) {
+        const int t = srt[z]; srt[z] = srt[z - 1]; srt[z - 1] = t;
+      }
+    for (int q = 0; q < nex; ++q)
+      if (x >= srt[q]) ++x;
+    ex[nex++] = x;
+    pick[r] = base + x;
+  }
+  const int R = int(index_below(r0.w, uint32_t(D)));
+  if (idx) {
+    idx[4 * i + 0] = pick[0];
+    idx[4 * i + 1] = pick[1];
+    idx[4 * i + 2] = pick[2];
+    idx[4 * i + 3] = R;
+  }
+  const int nb = (D + 3) / 4;
+  const U4 rp = philox4x32_10(U4{uint32_t(i), uint32_t(1 + 2 * nb), g0, g1}, k0, k1);
+  double F = fcr[2 * i], CR = fcr[2 * i + 1];
+  if (open01(rp.x) < prm.tau1) {
+    const double span = prm.F_hi - prm.F_lo;
+    const double step = open01(rp.y) * span;
+    F = prm.F_lo + step;
+  }
+  if (open01(rp.z) < prm.tau2) CR = open01(rp.w);
+  tfcr[2 * i] = F;
+  tfcr[2 * i + 1] = CR;
+  const double* a = pop + size_t(pick[0]) * D;
+  const double* b = pop + size_t(pick[1]) * D;
+  const double* c = pop + size_t(pick[2]) * D;
+  const double* x = pop + size_t(i) * D;
+  double* y = trial + size_t(i) * D;
+  U4 cr{}, rd{};
+  for (int j = 0; j < D; ++j) {
+    if ((j & 3) == 0) {
+      cr = philox4x32_10(U4{uint32_t(i), uint32_t(1 + j / 4), g0, g1}, k0, k1);
+      rd = philox4x32_10(U4{uint32_t(i), uint32_t(1 + nb + j / 4), g0, g1}, k0, k1);
+    }
+    const double r = open01(word(cr, j & 3));
+    double v;
+    if (r <= CR || j == R) {
+      const double diff = b[j] - c[j];
+      const double st = F * diff;
+      v = a[j] + st;
+    } else {
+      v = x[j];
+    }
+    if (v < prm.lo || v > prm.hi) {
+      const bool phase = prm.n_s > 0 && ((j / prm.n_s) & 1);
+      const double w = prm.hi - prm.lo;
+      if (phase) {
+        const double k = floor((v - prm.lo) / w);
+        v = v - w * k;
+      } else {
+        v = prm.lo + w * open01(word(rd, j & 3));
+      }
+    }
+    y[j] = v;
+  }
+}
+
+__global__ void __launch_bounds__(128) k_jde_select(po_jde_params prm, double* __restrict__ pop, double* __restrict__ fit,
+                                                    double* __restrict__ fcr, const double* __restrict__ trial,
+                                                    const double* __restrict__ tfit, const double* __restrict__ tfcr,
+                                                    const uint8_t* __restrict__ mask) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= prm.pop) return;
+  if (mask && !mask[i]) return;
+  if (tfit[i] >= fit[i]) {
+    for (int j = 0; j < prm.dim; ++j) pop[size_t(i) * prm.dim + j] = trial[size_t(i) * prm.dim + j];
+    fit[i] = tfit[i];
+    fcr[2 * i] = tfcr[2 * i];
+    fcr[2 * i + 1] = tfcr[2 * i + 1];
+  }
+}
+
+// Ring migration in one workgroup: thread k finds the best member of island k and the worst of
+// island k + 1 (lowest index on ties) in the state before the call, the moving rows are staged
+// in LDS, then written.
+__global__ void __launch_bounds__(kMaxIslands) k_island_migrate(po_jde_params prm, double* __restrict__ pop,
+                                                               double* __restrict__ fit, double* __restrict__ fcr) {
+  __shared__ double stage[kMaxIslands][kMaxMigrateDim + 3];
+  __shared__ int dst[kMaxIslands];
+  const int K = prm.islands, S = prm.pop / K, D = prm.dim;
+  const int k = threadIdx.x;
+  if (k < K) {
+    int best = k * S;
+    for (int i = k * S; i < (k + 1) * S; ++i)
+      if (fit[i] > fit[best]) best = i;
+    const int k2 = (k + 1) % K;
+    int worst = k2 * S;
+    for (int i = k2 * S; i < (k2 + 1) * S; ++i)
+      if (fit[i] < fit[worst]) worst = i;
+    dst[k] = fit[best] > fit[worst] ? worst : -1;
+    for (int j = 0; j < D; ++j) stage[k][j] = pop[size_t(best) * D + j];
+    stage[k][D] = fit[best];
+    stage[k][D + 1] = fcr[2 * best];
+    stage[k][D + 2] = fcr[2 * best + 1];
+  }
+  __syncthreads();
+  if (k < K && dst[k] >= 0) {
+    const int w = dst[k];
+    for (int j = 0; j < D; ++j) pop[size_t(w) * D + j] = stage[k][j];
+    fit[w] = stage[k][D];
+    fcr[2 * w] = stage[k][D + 1];
+    fcr[2 * w + 1] = stage[k][D + 2];
+  }
+}
+
 }  // namespace
 
 po_status launch_de_propose(const po_de_params& p, int64_t gen, const double* d_pop, double* d_trial, int32_t* d_idx,
@@ -168,6 +302,28 @@ po_status launch_de_select(const po_de_params& p, double* d_pop, double* d_fit, 
                            const double* d_trial_fit, const uint8_t* d_mask, hipStream_t s) {
   hipLaunchKernelGGL(k_de_select, dim3((p.pop + 127) / 128), dim3(128), 0, s, p, d_pop, d_fit, d_trial, d_trial_fit,
                      d_mask);
+  PO_HIP(hipGetLastError());
+  return PO_OK;
+}
+
+po_status launch_jde_propose(const po_jde_params& p, int64_t gen, const double* d_pop, const double* d_fcr,
+                             double* d_trial, double* d_tfcr, int32_t* d_idx, hipStream_t s) {
+  hipLaunchKernelGGL(k_jde_propose, dim3((p.pop + 127) / 128), dim3(128), 0, s, p, gen, d_pop, d_fcr, d_trial, d_tfcr,
+                     d_idx);
+  PO_HIP(hipGetLastError());
+  return PO_OK;
+}
+
+po_status launch_jde_select(const po_jde_params& p, double* d_pop, double* d_fit, double* d_fcr, const double* d_trial,
+                            const double* d_tfit, const double* d_tfcr, const uint8_t* d_mask, hipStream_t s) {
+  hipLaunchKernelGGL(k_jde_select, dim3((p.pop + 127) / 128), dim3(128), 0, s, p, d_pop, d_fit, d_fcr, d_trial, d_tfit,
+                     d_tfcr, d_mask);
+  PO_HIP(hipGetLastError());
+  return PO_OK;
+}
+
+po_status launch_island_migrate(const po_jde_params& p, double* d_pop, double* d_fit, double* d_fcr, hipStream_t s) {
+  hipLaunchKernelGGL(k_island_migrate, dim3(1), dim3(kMaxIslands), 0, s, p, d_pop, d_fit, d_fcr);
   PO_HIP(hipGetLastError());
   return PO_OK;
 }

@@ -31,7 +31,7 @@
 // the launch shape or on scheduling.  Two launch forms share the item code: one workgroup per
 // 256-mode item, or persistent workgroups that pull items (longest pulses first) from a device
 // queue through an atomic counter.
-#include "common.hpp"
+#include "reduce.hpp"
 
 // Every fused multiply-add below is written out: automatic contraction is off, so each mode's
 // arithmetic is the same instruction sequence in every launch shape (threads, modes per lane,
@@ -76,6 +76,7 @@ constexpr double kTanXmax[kNumTan] = {0.0099, 0.0337, 0.0735, 0.1558};
 constexpr double kCosSinXmax = 0.3612;
 constexpr int kHalvingMode = kNumTan;
 constexpr int kNumModes = kNumTan + 1;
+constexpr double kSqrt3Over6 = 0.28867513459481288225;  // sqrt(3)/6, Gauss-Legendre nodes 1/2 -+ sqrt(3)/6
 
 // Horner step k of the C and S series, coefficients forced to compile-time constants.
 template <int K>
@@ -203,25 +204,6 @@ __device__ __forceinline__ double project(const State& v, double Px, double Py, 
   return (fma(i1, i1, r1 * r1) / m1 + fma(i2, i2, r2 * r2) / m2) * n2;
 }
 
-// Fixed-order sum over the 64 lanes of a wave (butterfly); every lane gets the same value.
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// Fixed-order tree sum of one value per lane over a 256-lane workgroup.
-__device__ __forceinline__ double block_sum256(double v, double* red) {
-  red[threadIdx.x] = v;
-  __syncthreads();
-#pragma unroll
-  for (int w = 128; w > 0; w >>= 1) {
-    if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  return red[0];
-}
-
 __device__ __forceinline__ double grid_max_abs(double lo, int n, double dp) {
   // largest |p| over the cell-centred points lo + (i + 1/2) dp, i = 0..n-1 (dp = 0: a sheet)
   return fmax(fabs(lo + 0.5 * dp), fabs(lo + (n - 0.5) * dp));
@@ -231,15 +213,18 @@ __device__ __forceinline__ double grid_max_abs(double lo, int n, double dp) {
 //   x <= dt^2 [ max_n ((max|p_x| + |A_x,n|)^2 + (max|p_y| + |A_y,n|)^2) + 1 + max p_z^2 ],
 // and the series variant it selects (sel.x) with the number of angle halvings (sel.y).  Per
 // pulse, so all modes of a pulse use the same arithmetic whatever the launch shape.
+// NODES = 2: the table holds A at two nodes per step (fourth-order step); with theta^2 the bound
+// above, |w_s| <= theta + (sqrt3/6) theta^2 bounds the step's rotation angle.
+template <int NODES>
 __global__ void __launch_bounds__(256) k_series_select(const PulseDev* __restrict__ desc, const double* __restrict__ A,
                                                        const double* __restrict__ Aedge, int2* __restrict__ sel) {
   const PulseDev d = desc[blockIdx.x];
   const double pxm = grid_max_abs(d.lo[0], d.n[0], d.dp[0]);
   const double pym = grid_max_abs(d.lo[1], d.n[1], d.dp[1]);
   const double pzm = grid_max_abs(d.lo[2], d.n[2], d.dp[2]);
-  const double2* tab = reinterpret_cast<const double2*>(A) + d.tab_off;
+  const double2* tab = reinterpret_cast<const double2*>(A) + NODES * d.tab_off;
   double m = 0.0;
-  for (int64_t n = threadIdx.x; n < d.nt; n += blockDim.x) {
+  for (int64_t n = threadIdx.x; n < int64_t(NODES) * d.nt; n += blockDim.x) {
     const double2 a = tab[n];
     const double u = pxm + fabs(a.x), w = pym + fabs(a.y);
     m = fmax(m, u * u + w * w);
@@ -257,7 +242,11 @@ __global__ void __launch_bounds__(256) k_series_select(const PulseDev* __restric
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const double xb = (red[0] + 1.0 + pzm * pzm) * d.dt * d.dt * (1.0 + 1e-6);
+    double xb = (red[0] + 1.0 + pzm * pzm) * d.dt * d.dt * (1.0 + 1e-6);
+    if (NODES == 2) {
+      const double th = sqrt(xb);
+      xb = (th + kSqrt3Over6 * th * th) * (th + kSqrt3Over6 * th * th) * (1.0 + 1e-6);
+    }
     int mode = kHalvingMode, h = 0;
     for (int k = kNumTan - 1; k >= 0; --k)
       if (xb <= kTanXmax[k]) mode = k;
@@ -398,24 +387,6 @@ __device__ __forceinline__ void dispatch_item(const EvolveArgs& a, int pi, int f
   }
 }
 
-__device__ __forceinline__ int find_pulse_item(const PulseDev* __restrict__ desc, int n, int item) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (desc[mid].item_off <= item) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
-// Workgroup IDs are dispatched round-robin over the 8 XCDs (each with its own L2), so block b runs
-// on XCD b % 8.  Give each XCD a contiguous range of items -- whole stretches of one pulse -- so a
-// pulse's table is fetched from HBM by one L2 rather than by all eight.  A bijection on [0, n).
-__device__ __forceinline__ int xcd_item(int b, int n) {
-  constexpr int kXcd = 8;
-  const int x = b % kXcd, q = n / kXcd, r = n % kXcd;
-  return x * q + min(x, r) + b / kXcd;
-}
-
 // One workgroup per 256-mode item.
 __global__ void __launch_bounds__(kItem) k_evolve(EvolveArgs a) {
   __shared__ double2 lds[2][kChunk];
@@ -487,11 +458,185 @@ void launch_persistent_t(EvolveArgs a, const int2* q, int n_items, int nwg, int*
   hipLaunchKernelGGL((k_evolve_persistent<THREADS, MPL>), dim3(nwg), dim3(THREADS), 0, s, a, q, n_items, counter);
 }
 
+// ---------------------------------------------------------------------------------------------
+// Fourth-order Magnus step with two Gauss-Legendre nodes t_n + (1/2 -+ sqrt3/6) dt per step
+// (Blanes, Casas, Oteo & Ros, Phys. Rep. 470 (2009) 151): the fourth-order Dirac scheme that
+// Sec. V C of the paper leaves for future work.  For the blocks h_s(t) = v_s . tau with
+// v_s = (P_x, s P_y, e_perp), [h_2, h_1] = 2i (v_2 x v_1) . tau, so the Magnus exponent of a step
+// is -i w_s . tau with
+//     w_s = dt (v_1 + v_2)/2 + (sqrt3/6) dt^2 (v_2 x v_1),
+// and the step is again U = C [1 - i T(|w_s|^2) w_s . tau], now with one w_s (and one T) per
+// block.  With a_k = (p_x - A_x(t_k)) dt, b_k likewise, e = e_perp dt, abar = (a_1 + a_2)/2 and
+// g = (sqrt3/6) (a_1 - a_2, b_1 - b_2):
+//     w_s = (abar - s e g_y,  s (bbar + s e g_x),  e + s (abar g_y - bbar g_x)).
+// The record staged per step is (-(A_1 + A_2) dt/2, (sqrt3/6)(A_2 - A_1) dt): abar and g cost one
+// add each.  The two blocks now rotate by different angles, so each is rescaled on its own.
+// ---------------------------------------------------------------------------------------------
+
+// psi <- (1 - i t . tau) psi for one block (a, b).
+__device__ __forceinline__ void rotate_block_tan(double& ar, double& ai, double& br, double& bi, double tx, double ty,
+                                                 double tz) {
+  const double nar = fma(tx, bi, fma(-ty, br, fma(tz, ai, ar)));
+  const double nai = fma(-tx, br, fma(-ty, bi, fma(-tz, ar, ai)));
+  const double nbr = fma(-tz, bi, fma(tx, ai, fma(ty, ar, br)));
+  const double nbi = fma(tz, br, fma(-tx, ar, fma(ty, ai, bi)));
+  ar = nar; ai = nai; br = nbr; bi = nbi;
+}
+
+// psi <- (C - i s . tau) psi for one block (a, b).
+__device__ __forceinline__ void rotate_block(double& ar, double& ai, double& br, double& bi, double C, double sx,
+                                             double sy, double sz) {
+  const double nar = fma(sx, bi, fma(-sy, br, fma(sz, ai, C * ar)));
+  const double nai = fma(-sx, br, fma(-sy, bi, fma(-sz, ar, C * ai)));
+  const double nbr = fma(-sz, bi, fma(C, br, fma(sx, ai, sy * ar)));
+  const double nbi = fma(sz, br, fma(C, bi, fma(-sx, ar, sy * ai)));
+  ar = nar; ai = nai; br = nbr; bi = nbi;
+}
+
+struct Magnus4 {
+  double Xp, Yp, Zp, Xm, Ym, Zm;  // w_{+1} = (Xp, Yp, Zp); w_{-1} = (Xm, -Ym, Zm)
+};
+
+__device__ __forceinline__ Magnus4 magnus4(double4 rec, double pxdt, double pydt, double e) {
+  const double ab = pxdt + rec.x, bb = pydt + rec.y;
+  const double egx = e * rec.z, egy = e * rec.w;
+  const double g = fma(ab, rec.w, -(bb * rec.z));
+  return Magnus4{ab - egy, bb + egx, e + g, ab + egy, bb - egx, e - g};
+}
+
+template <int N>
+__device__ __forceinline__ void step4_tan(State& v, double4 rec, double pxdt, double pydt, double e) {
+  const Magnus4 w = magnus4(rec, pxdt, pydt, e);
+  const double xp = fma(w.Xp, w.Xp, fma(w.Yp, w.Yp, w.Zp * w.Zp));
+  const double xm = fma(w.Xm, w.Xm, fma(w.Ym, w.Ym, w.Zm * w.Zm));
+  const double Tp = tan_ratio<N>(xp), Tm = tan_ratio<N>(xm);
+  rotate_block_tan(v.ar, v.ai, v.br, v.bi, Tp * w.Xp, Tp * w.Yp, Tp * w.Zp);
+  rotate_block_tan(v.cr, v.ci, v.dr, v.di, Tm * w.Xm, -(Tm * w.Ym), Tm * w.Zm);
+}
+
+// C = cos sqrt x, S = sin sqrt x / sqrt x from the degree-7 series at x / 4^h and h double-angle steps.
+__device__ __forceinline__ void cos_sinc_halved(double x, int h, double inv4h, double& C, double& S) {
+  double xs = x * inv4h;
+  cos_sinc<7>(xs, C, S);
+  for (int i = 0; i < h; ++i) {
+    const double c2 = fma(C, C, -(xs * S) * S);
+    S = S * C;
+    C = c2;
+    xs *= 4.0;
+  }
+}
+
+__device__ __forceinline__ void step4_halving(State& v, double4 rec, double pxdt, double pydt, double e, int h,
+                                              double inv4h) {
+  const Magnus4 w = magnus4(rec, pxdt, pydt, e);
+  const double xp = fma(w.Xp, w.Xp, fma(w.Yp, w.Yp, w.Zp * w.Zp));
+  const double xm = fma(w.Xm, w.Xm, fma(w.Ym, w.Ym, w.Zm * w.Zm));
+  double Cp, Sp, Cm, Sm;
+  cos_sinc_halved(xp, h, inv4h, Cp, Sp);
+  cos_sinc_halved(xm, h, inv4h, Cm, Sm);
+  rotate_block(v.ar, v.ai, v.br, v.bi, Cp, Sp * w.Xp, Sp * w.Yp, Sp * w.Zp);
+  rotate_block(v.cr, v.ci, v.dr, v.di, Cm, Sm * w.Xm, -(Sm * w.Ym), Sm * w.Zm);
+}
+
+// Rescales each block by its own exact power of two.
+__device__ __forceinline__ void renormalise_blocks(State& v) {
+  const double n1 = fma(v.bi, v.bi, fma(v.br, v.br, fma(v.ai, v.ai, v.ar * v.ar)));
+  const double n2 = fma(v.di, v.di, fma(v.dr, v.dr, fma(v.ci, v.ci, v.cr * v.cr)));
+  const int e1 = -(ilogb(n1) >> 1), e2 = -(ilogb(n2) >> 1);
+  v.ar = ldexp(v.ar, e1); v.ai = ldexp(v.ai, e1); v.br = ldexp(v.br, e1); v.bi = ldexp(v.bi, e1);
+  v.cr = ldexp(v.cr, e2); v.ci = ldexp(v.ci, e2); v.dr = ldexp(v.dr, e2); v.di = ldexp(v.di, e2);
+}
+
+template <int MODE>
+__device__ __forceinline__ void one_step4(State& v, double4 rec, double pxdt, double pydt, double e, int h,
+                                          double inv4h) {
+  if constexpr (MODE < kHalvingMode) step4_tan<kTanDegree[MODE]>(v, rec, pxdt, pydt, e);
+  else step4_halving(v, rec, pxdt, pydt, e, h, inv4h);
+}
+
+struct Evolve4Args {
+  const PulseDev* desc;
+  int n_pulses;
+  const double* Ag;  // [sum nt][2 nodes][2] A at the Gauss-Legendre nodes
+  const double* Aedge;
+  const int2* sel;
+  double* f;
+  double* units;
+};
+
+// One 256-mode item of pulse pi, one mode per lane; the structure of process_item.
+template <int MODE>
+__device__ __forceinline__ void process_item4(const Evolve4Args& a, int pi, int first, int h,
+                                              double4 (*lds)[kChunk]) {
+  const PulseDev& d = a.desc[pi];
+  const int nt = d.nt;
+  const double dt = d.dt;
+  const int64_t nmodes = int64_t(d.n[0]) * d.n[1] * d.n[2];
+  const double inv4h = ldexp(1.0, -2 * h);
+  const double4* tab = reinterpret_cast<const double4*>(a.Ag) + d.tab_off;
+  const double2* edge = reinterpret_cast<const double2*>(a.Aedge) + 2 * pi;
+  const double hdt = -0.5 * dt, kdt = kSqrt3Over6 * dt;
+  const int64_t m = int64_t(first) + threadIdx.x;
+  double px, py, pz;
+  mode_momentum(d, m < nmodes ? m : 0, px, py, pz);
+  const double ep = sqrt(fma(pz, pz, 1.0));
+  State v;
+  const double2 ain = edge[0];
+  init_state(v, px - ain.x, py - ain.y, ep);
+  const double pxdt = px * dt, pydt = py * dt, e = ep * dt;
+
+  const int nchunks = (nt + kChunk - 1) / kChunk;
+  {
+    const double4 t = int(threadIdx.x) < nt ? tab[threadIdx.x] : make_double4(0.0, 0.0, 0.0, 0.0);
+    lds[0][threadIdx.x] = make_double4(hdt * (t.x + t.z), hdt * (t.y + t.w), kdt * (t.z - t.x), kdt * (t.w - t.y));
+  }
+  __syncthreads();
+  for (int c = 0; c < nchunks; ++c) {
+    const int n = (c + 1) * kChunk + threadIdx.x;
+    const double4 pre = (c + 1 < nchunks && n < nt) ? tab[n] : make_double4(0.0, 0.0, 0.0, 0.0);
+    const double4* buf = lds[c & 1];
+    const int len = min(kChunk, nt - c * kChunk);
+    if (len == kChunk) {
+#pragma unroll 2
+      for (int k = 0; k < kChunk; ++k) one_step4<MODE>(v, buf[k], pxdt, pydt, e, h, inv4h);
+    } else {
+      for (int k = 0; k < len; ++k) one_step4<MODE>(v, buf[k], pxdt, pydt, e, h, inv4h);
+    }
+    if constexpr (MODE < kHalvingMode) renormalise_blocks(v);
+    lds[(c + 1) & 1][threadIdx.x] =
+        make_double4(hdt * (pre.x + pre.z), hdt * (pre.y + pre.w), kdt * (pre.z - pre.x), kdt * (pre.w - pre.y));
+    __syncthreads();
+  }
+
+  const double2 aout = edge[1];
+  double fv = 0.0;
+  if (m < nmodes) {
+    fv = project(v, px - aout.x, py - aout.y, ep);
+    if (a.f) a.f[d.mode_off + m] = fv;
+  }
+  if (a.units) write_unit(d, a.units, m, nmodes, fv);
+}
+
+__global__ void __launch_bounds__(kItem) k_evolve4(Evolve4Args a) {
+  __shared__ double4 lds[2][kChunk];
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  const int pi = find_pulse_item(a.desc, a.n_pulses, item);
+  const int first = (item - a.desc[pi].item_off) * kItem;
+  const int2 sl = a.sel[pi];
+  switch (sl.x) {
+    case 0: process_item4<0>(a, pi, first, 0, lds); break;
+    case 1: process_item4<1>(a, pi, first, 0, lds); break;
+    case 2: process_item4<2>(a, pi, first, 0, lds); break;
+    case 3: process_item4<3>(a, pi, first, 0, lds); break;
+    default: process_item4<kHalvingMode>(a, pi, first, sl.y, lds); break;
+  }
+}
+
 }  // namespace
 
 po_status launch_series_select(const Batch& b, const PulseDev* d_desc, const double* d_A, const double* d_A_edge,
                                int2* d_sel, hipStream_t s) {
-  hipLaunchKernelGGL(k_series_select, dim3(b.n_pulses), dim3(256), 0, s, d_desc, d_A, d_A_edge, d_sel);
+  hipLaunchKernelGGL(k_series_select<1>, dim3(b.n_pulses), dim3(256), 0, s, d_desc, d_A, d_A_edge, d_sel);
   PO_HIP(hipGetLastError());
   return PO_OK;
 }
@@ -548,6 +693,21 @@ po_status launch_unit_sums_from_f(const Batch& b, const PulseDev* d_desc, const 
 po_status launch_yield_from_units(const Batch& b, const PulseDev* d_desc, const double* d_units, double* d_J,
                                   hipStream_t s) {
   hipLaunchKernelGGL(k_yield, dim3(b.n_pulses), dim3(256), 0, s, d_desc, d_units, d_J);
+  PO_HIP(hipGetLastError());
+  return PO_OK;
+}
+
+po_status launch_series_select4(const Batch& b, const PulseDev* d_desc, const double* d_Ag, const double* d_A_edge,
+                                int2* d_sel, hipStream_t s) {
+  hipLaunchKernelGGL(k_series_select<2>, dim3(b.n_pulses), dim3(256), 0, s, d_desc, d_Ag, d_A_edge, d_sel);
+  PO_HIP(hipGetLastError());
+  return PO_OK;
+}
+
+po_status launch_evolve4_grid(const Batch& b, const PulseDev* d_desc, const double* d_Ag, const double* d_A_edge,
+                              const int2* d_sel, double* d_f, double* d_units, hipStream_t s) {
+  Evolve4Args a{d_desc, b.n_pulses, d_Ag, d_A_edge, d_sel, d_f, d_units};
+  hipLaunchKernelGGL(k_evolve4, dim3(b.total_items), dim3(kItem), 0, s, a);
   PO_HIP(hipGetLastError());
   return PO_OK;
 }

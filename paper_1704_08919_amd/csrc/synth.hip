@@ -51,7 +51,9 @@ __global__ void __launch_bounds__(128) k_spectra(const PulseDev* __restrict__ de
   const double* a = coeff + d.coeff_off;
   double b[2 * kMaxNs + 2];
   for (int j = threadIdx.x; j < d.nlines; j += blockDim.x) {
-    const double w = double(d.nmin + j) * d.dw;
+    // basis at the line frequency clamped into the band: the end lines sample the end knots
+    // whatever the rounding of (N_min + j) dw
+    const double w = fmin(fmax(double(d.nmin + j) * d.dw, d.wmin), d.wmax);
     bspline_all(d.order, d.ns, d.wmin, d.wmax, w, b);
     double out[4];
     for (int l = 0; l < 2; ++l) {
@@ -225,6 +227,114 @@ __global__ void __launch_bounds__(256) k_tables(const PulseDev* __restrict__ des
   }
 }
 
+// Unscaled E, dE/dt and A at t = t_i + (n + c) dt for any offset c (0 <= n <= nt).  The phase of
+// line k is pi [k (2n - nt) mod 2nt] / nt + 2 pi k c / nt: the step part is reduced exactly in
+// integers, the offset part (below 2 pi k / nt) is added in floating point.
+__device__ void field_sample(const PulseDev& d, const double4* __restrict__ sp, int64_t n, double c, bool want_E,
+                             bool want_Ed, bool want_A, double E[2], double Ed[2], double A[2]) {
+  const int64_t nt = d.nt, two_nt = 2 * nt, hm = 2 * n - nt;
+  const double inv_nt = 1.0 / double(nt), cfrac = 2.0 * c * inv_nt;
+  auto phase = [&](int64_t k, double* s, double* co) {
+    int64_t r = (k * hm) % two_nt;
+    if (r < 0) r += two_nt;
+    double u = fma(double(k), cfrac, double(r) * inv_nt);
+    if (u >= 2.0) u -= 2.0;
+    sincospi(u, s, co);
+  };
+  double ex = 0.0, ey = 0.0, dx = 0.0, dy = 0.0, ax = 0.0, ay = 0.0;
+  double sd = 0.0, cd = 1.0;
+  if (want_A) phase(1, &sd, &cd);
+  const double tmf = (double(n - nt) + c) * d.dt;  // t - t_f
+  for (int j = 0; j < d.nlines; ++j) {
+    const int64_t k = int64_t(d.nmin) + j;
+    double s, co;
+    phase(k, &s, &co);
+    const double4 q = sp[j];  // (cEx, sEx, cEy, sEy)
+    if (want_E || want_Ed) {
+      ex += q.x * co + q.y * s;
+      ey += q.z * co + q.w * s;
+    }
+    if (want_Ed) {
+      const double om = double(k) * d.dw;
+      dx += om * (q.y * co - q.x * s);
+      dy += om * (q.w * co - q.z * s);
+    }
+    if (want_A) {
+      // the line terms of field_at, at this phase
+      const double sgn = (k & 1) ? -1.0 : 1.0;
+      const double cp = co * cd - s * sd, spp = s * cd + co * sd;
+      const double cm = cd * co + sd * s, smm = sd * co - cd * s;
+      const double om = double(k) * d.dw, wp = double(k + 1) * d.dw, wm = double(1 - k) * d.dw;
+      double tx, ty;
+      if (k == 0) {
+        tx = 0.5 * tmf * q.x;
+        ty = 0.5 * tmf * q.z;
+      } else {
+        tx = 0.5 * (q.x * s - q.y * co + sgn * q.y) / om;
+        ty = 0.5 * (q.z * s - q.w * co + sgn * q.w) / om;
+      }
+      tx += 0.25 * (q.x * spp - q.y * cp - sgn * q.y) / wp;
+      ty += 0.25 * (q.z * spp - q.w * cp - sgn * q.w) / wp;
+      if (k == 1) {
+        tx += 0.25 * tmf * q.x;
+        ty += 0.25 * tmf * q.z;
+      } else {
+        tx += 0.25 * (q.x * smm + q.y * cm + sgn * q.y) / wm;
+        ty += 0.25 * (q.z * smm + q.w * cm + sgn * q.w) / wm;
+      }
+      ax -= tx;
+      ay -= ty;
+    }
+  }
+  const double arg = (double(hm) + 2.0 * c) * inv_nt;  // 2 t / T
+  const double g = cospi(0.5 * arg);                   // cos(pi t / T)
+  if (want_E) {
+    E[0] = g * g * ex;
+    E[1] = g * g * ey;
+  }
+  if (want_Ed) {
+    const double g2d = -(M_PI / d.T) * sinpi(arg);  // d cos^2(pi t/T) / dt
+    Ed[0] = g2d * ex + g * g * dx;
+    Ed[1] = g2d * ey + g * g * dy;
+  }
+  if (want_A) {
+    A[0] = ax;
+    A[1] = ay;
+  }
+}
+
+struct Offsets {
+  double c[kMaxSub];
+};
+
+// Scaled samples: row r of pulse i is t_i + (r / n_sub + c_{r % n_sub}) dt; with_end adds t_f.
+__global__ void __launch_bounds__(256) k_samples(const PulseDev* __restrict__ desc, const double* __restrict__ spec,
+                                                 const double* __restrict__ scale, int n_sub, Offsets off,
+                                                 int with_end, double* __restrict__ Eout, double* __restrict__ Edout,
+                                                 double* __restrict__ Aout, double* __restrict__ Aedge) {
+  const PulseDev d = desc[blockIdx.y];
+  const int64_t rows = int64_t(d.nt) * n_sub + (with_end ? 1 : 0);
+  const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const double4* sp = reinterpret_cast<const double4*>(spec + d.spec_off);
+  const double s = scale[blockIdx.y];
+  if (k < rows) {
+    const bool end = k == int64_t(d.nt) * n_sub;
+    const int64_t n = end ? d.nt : k / n_sub;
+    const double c = end ? 0.0 : off.c[k % n_sub];
+    double E[2], Ed[2], A[2];
+    field_sample(d, sp, n, c, Eout != nullptr, Edout != nullptr, Aout != nullptr, E, Ed, A);
+    const int64_t row = d.tab_off + k;
+    if (Eout) reinterpret_cast<double2*>(Eout)[row] = make_double2(s * E[0], s * E[1]);
+    if (Edout) reinterpret_cast<double2*>(Edout)[row] = make_double2(s * Ed[0], s * Ed[1]);
+    if (Aout) reinterpret_cast<double2*>(Aout)[row] = make_double2(s * A[0], s * A[1]);
+  }
+  if (Aedge && blockIdx.x == 0 && threadIdx.x < 2) {
+    double E[2], A[2];
+    field_at(d, sp, threadIdx.x == 0 ? 0 : 2 * int64_t(d.nt), false, true, E, A);
+    reinterpret_cast<double2*>(Aedge)[2 * blockIdx.y + threadIdx.x] = make_double2(s * A[0], s * A[1]);
+  }
+}
+
 }  // namespace
 
 po_status launch_synth(const Batch& b, const PulseDev* d_desc, const double* d_coeff, double* d_spec,
@@ -243,6 +353,29 @@ po_status launch_synth(const Batch& b, const PulseDev* d_desc, const double* d_c
   PO_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_tables, dim3((b.max_nt + 255) / 256, P), dim3(256), 0, s, d_desc, d_spec, d_scale_ws,
                      d_A, d_E, d_A_edge);
+  PO_HIP(hipGetLastError());
+  return PO_OK;
+}
+
+po_status launch_samples(const Batch& b, const PulseDev* d_desc, const double* d_coeff, double* d_spec, double* d_part,
+                         double* d_scale_ws, int n_sub, const double* offsets, int with_end, double* d_E,
+                         double* d_Ed, double* d_A, double* d_A_edge, double* d_scale_out, hipStream_t s) {
+  const int P = b.n_pulses;
+  Offsets off{};
+  for (int r = 0; r < n_sub; ++r) off.c[r] = offsets[r];
+  hipLaunchKernelGGL(k_spectra, dim3(P), dim3(128), 0, s, d_desc, d_coeff, d_spec);
+  PO_HIP(hipGetLastError());
+  if (b.max_stat_blocks > 0) {
+    hipLaunchKernelGGL(k_field_stats, dim3(b.max_stat_blocks, P), dim3(256), 0, s, d_desc, d_spec,
+                       b.max_stat_blocks, d_part);
+    PO_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_scale, dim3(P), dim3(256), 0, s, d_desc, d_part, b.max_stat_blocks, d_scale_ws,
+                     d_scale_out);
+  PO_HIP(hipGetLastError());
+  const int64_t rows = int64_t(b.max_nt) * n_sub + (with_end ? 1 : 0);
+  hipLaunchKernelGGL(k_samples, dim3(unsigned((rows + 255) / 256), P), dim3(256), 0, s, d_desc, d_spec, d_scale_ws,
+                     n_sub, off, with_end, d_E, d_Ed, d_A, d_A_edge);
   PO_HIP(hipGetLastError());
   return PO_OK;
 }

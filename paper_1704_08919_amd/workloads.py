@@ -108,3 +108,22 @@ def sample_mode_indices(seed, n_total, k):
 def mode_steps(specs, grids):
     return sum(int(s["nt"]) * n_modes(g) for s, g in zip(specs, grids))
 
+
+
+def circular_pulse(seed=0, nt=20000, n_p=512):
+    """Circularly polarised multimode pulse of the paper's 2-D study (Sec. V B, Table pulse2D,
+    case (c)): band nu in [0.02, 0.03] (omega = 2 pi nu), T = 5000 (Delta nu = 0.0002, 51 lines),
+    N_s = 10 quadratic B-splines (order k = 3), energy U = 50; equal amplitude coefficients on both
+    components, drawn uniform in [0, 1], with phases 0 (x) and pi/2 (y), i.e. phase coefficients
+    c = -1 and c = -1/2 under a^(phi) = pi (c + 1).  The optimum the paper found is not
+    available: the amplitudes are a seeded draw.  Momentum sheet p_x, p_y in [-3, 3] at p_z = 0
+    with n_p x n_p cells."""
+    spec = pulse_spec(n_s=10, order=3, omega_min=2 * np.pi * 0.02, omega_max=2 * np.pi * 0.03, T=5000.0,
+                      nt=nt, norm=NORM_ENERGY, norm_value=50.0)
+    amp = rng(seed + 104729).uniform(0.0, 1.0, size=10)
+    coeff = np.empty((1, 2, 2, 10))
+    coeff[0, :, 0, :] = amp
+    coeff[0, 0, 1, :] = -1.0
+    coeff[0, 1, 1, :] = -0.5
+    return dict(name=f"circular_pulse_T5000_{n_p}x{n_p}", specs=[spec], grids=[sheet_grid(n_p, n_p, 3.0)],
+                coeff=coeff)

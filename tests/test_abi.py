@@ -97,3 +97,39 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="not built"):
         _lib.load()
+
+
+def _grid1():
+    g = (_lib.Grid * 1)()
+    g[0].n[:] = [4, 4, 1]
+    g[0].lo[:] = [-1, -1, 0]
+    g[0].hi[:] = [1, 1, 0]
+    return g
+
+
+def test_solver_entry_points_validate_on_host(lib):
+    off = (ctypes.c_double * 2)(0.0, 0.5)
+    # sample counts, offsets and outputs
+    assert lib.po_field_samples(1, _specs(), None, 0, off, 1, None, None, None, None, None, None) == _lib.PO_ERR_INVALID
+    assert lib.po_field_samples(1, _specs(), None, 9, off, 1, None, None, None, None, None, None) == _lib.PO_ERR_INVALID
+    bad = (ctypes.c_double * 2)(0.0, 1.5)
+    assert lib.po_field_samples(1, _specs(), None, 2, bad, 1, None, None, None, None, None, None) == _lib.PO_ERR_INVALID
+    assert b"offsets" in lib.po_last_error()
+    assert lib.po_field_samples(1, _specs(), None, 2, off, 1, None, None, None, None, None, None) == _lib.PO_ERR_INVALID
+    assert b"at least one" in lib.po_last_error()
+    # tables must be given
+    assert lib.po_qke_modes(1, _specs(), _grid1(), None, None, None, 0, None, None, None) == _lib.PO_ERR_INVALID
+    assert lib.po_evolve_modes_m4(1, _specs(), _grid1(), None, None, None, None, None) == _lib.PO_ERR_INVALID
+    assert lib.po_evolve_modes_m4(0, _specs(), _grid1(), None, None, None, None, None) == _lib.PO_ERR_INVALID
+
+
+@pytest.mark.parametrize("bad", [dict(islands=0), dict(islands=65), dict(pop=30, islands=4), dict(pop=12, islands=4),
+                                 dict(tau1=1.5), dict(tau2=-0.1), dict(F_lo=0.5, F_hi=0.2), dict(F_hi=2.5),
+                                 dict(lo=1.0, hi=-1.0)])
+def test_invalid_jde_params_rejected(lib, bad):
+    p = dict(pop=32, dim=16, n_s=4, islands=4, tau1=0.1, tau2=0.1, F_lo=0.1, F_hi=1.0, lo=-1.0, hi=1.0, seed=1)
+    p.update(bad)
+    prm = _lib.JDEParams(p["pop"], p["dim"], p["n_s"], p["islands"], p["tau1"], p["tau2"], p["F_lo"], p["F_hi"],
+                         p["lo"], p["hi"], p["seed"])
+    assert lib.po_jde_propose(ctypes.byref(prm), 0, None, None, None, None, None, None) == _lib.PO_ERR_INVALID
+    assert lib.po_island_migrate(ctypes.byref(prm), None, None, None, None) == _lib.PO_ERR_INVALID
