@@ -23,6 +23,7 @@ _I = ctypes.POINTER(ctypes.c_int)
 _U32 = ctypes.POINTER(ctypes.c_uint32)
 _I32 = ctypes.POINTER(ctypes.c_int32)
 _U8 = ctypes.POINTER(ctypes.c_uint8)
+_L = ctypes.POINTER(ctypes.c_long)
 
 NORM_NONE, NORM_PEAK, NORM_ENERGY = 0, 1, 2
 
@@ -61,6 +62,9 @@ def lib():
             "orc_field_samples_ld": (None, [c_int, c_int, c_double, c_double, c_double, c_int, c_int, c_double,
                                             _D, c_int, _D, c_int, _D, _D, _D]),
             "orc_evolve4_points_ld": (None, [c_int, c_double, _D, _D, c_long, _D, _D, c_int]),
+            "orc_grad_table_fd_ld": (None, [c_int, c_double, _D, _D, _I, _D, _D, c_double, c_int, _L, _D, c_int]),
+            "orc_grad_coeff_fd_ld": (None, [c_int, c_int, c_double, c_double, c_double, c_int, c_int, c_double, _D, _I,
+                                            _D, _D, c_double, _D, _D, _D, _D, c_int]),
             "orc_philox4x32_10": (None, [_U32, _U32, _U32]),
             "orc_de_propose": (None, [c_int, c_int, c_int, c_double, c_double, c_double, c_double,
                                       ctypes.c_uint64, ctypes.c_int64, _D, _D, _I32]),
@@ -300,3 +304,26 @@ def island_migrate(pop, fit, fcr, islands):
     N, D = pop.shape
     lib().orc_island_migrate(N, D, int(islands), _d(pop), _d(fit), _d(fcr))
     return pop, fit, fcr
+
+
+def grad_table_fd(A_mid, A_edge, dt, grid, entries, h=2.0 ** -20, nthreads=0):
+    """dJ/dx by a fourth-order central difference for table entries: e < 2 nt is A_mid[e//2][e%2],
+    e = 2 nt + r is A_edge[r//2][r%2]; J in long double."""
+    A_mid, A_edge = _arr(A_mid), _arr(A_edge)
+    n, lo, hi = _grid_arrays(grid)
+    idx = np.ascontiguousarray(np.asarray(entries, dtype=np.int64))
+    out = np.zeros(idx.size)
+    lib().orc_grad_table_fd_ld(A_mid.shape[0], float(dt), _d(A_mid), _d(A_edge), n.ctypes.data_as(_I), _d(lo),
+                               _d(hi), float(h), idx.size, idx.ctypes.data_as(_L), _d(out), int(nthreads))
+    return out
+
+
+def grad_coeff_fd(spec, grid, coeff, h=2.0 ** -14, nthreads=0):
+    """(J, U, dJ/dc, dU/dc) of one synthesised pulse by fourth-order central differences."""
+    coeff = _arr(coeff).ravel()
+    n, lo, hi = _grid_arrays(grid)
+    gJ, gU, J, U = np.zeros(coeff.size), np.zeros(coeff.size), np.zeros(1), np.zeros(1)
+    lib().orc_grad_coeff_fd_ld(spec["n_s"], spec["order"], spec["omega_min"], spec["omega_max"], spec["T"], spec["nt"],
+                               spec["norm"], spec["norm_value"], _d(coeff), n.ctypes.data_as(_I), _d(lo), _d(hi),
+                               float(h), _d(gJ), _d(gU), _d(J), _d(U), int(nthreads))
+    return float(J[0]), float(U[0]), gJ, gU

@@ -22,6 +22,7 @@
 //     with classical fourth-order Runge-Kutta; a cross-check, not part of the hot path.
 //   * Fourth-order Magnus step (two Gauss-Legendre nodes), the fourth-order Dirac scheme that
 //     Sec. V C names as future work; an extension checked by its convergence order.
+//   * Gradients of J and U for the local search (Sec. IV A) by central differences.
 //   * Differential evolution DE/rand/1/bin (Sec. IV B) driven by Philox4x32-10
 //     (Salmon, Moraes, Dror, Shaw, SC'11), implemented from that paper's definition.
 //
@@ -800,6 +801,90 @@ void orc_evolve4_points_ld(int nt, double dt, const double* Ag, const double* Ae
   const int nth = nthreads_or_default(nthreads);
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nth)
   for (long m = 0; m < nm; ++m) f[m] = double(evolve4_mode<R>(nt, R(dt), Ag, Aedge, Aedge + 2, p + 3 * m));
+}
+
+// ---------------------------------------------------------------------------------------
+// Gradients by central differences (the definition of the derivative, fourth-order stencil
+// (8 [F(h) - F(-h)] - [F(2h) - F(-2h)]) / (12 h)), for the local search of Sec. IV A.
+// J is accumulated in long double from long-double f, without rounding f to double.  The steps
+// are powers of two, so x +- h and x +- 2h are exact in double for |x| < 2^33 h.
+// ---------------------------------------------------------------------------------------
+long double yield_table_ld(int nt, long double dt, const double* Amid, const double* Aedge, const int n[3],
+                           const double lo[3], const double hi[3], int nthreads) {
+  const long nm = (long)n[0] * n[1] * n[2];
+  std::vector<long double> f((size_t)nm);
+  const int nth = nthreads_or_default(nthreads);
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nth)
+  for (long m = 0; m < nm; ++m) {
+    double p[3];
+    grid_point(n, lo, hi, m, p);
+    f[m] = evolve_mode<long double>(nt, dt, Amid, Aedge, Aedge + 2, p, nullptr);
+  }
+  long double s = 0;
+  for (long m = 0; m < nm; ++m) s += f[m];
+  return s * (long double)cell_volume(n, lo, hi);
+}
+
+// dJ/dx for table entries: e < 2 nt is A_mid[e/2][e%2], e = 2 nt + r is A_edge[r/2][r%2].
+void orc_grad_table_fd_ld(int nt, double dt, const double* Amid, const double* Aedge, const int* n, const double* lo,
+                          const double* hi, double h, int nidx, const long* idx, double* out, int nthreads) {
+  std::vector<double> A(Amid, Amid + 2 * (size_t)nt), E(Aedge, Aedge + 4);
+  for (int q = 0; q < nidx; ++q) {
+    const long e = idx[q];
+    double* x = e < 2L * nt ? &A[e] : &E[e - 2L * nt];
+    const double x0 = *x;
+    long double F[4];
+    const double st[4] = {h, -h, 2 * h, -2 * h};
+    for (int k = 0; k < 4; ++k) {
+      *x = x0 + st[k];
+      F[k] = yield_table_ld(nt, (long double)dt, A.data(), E.data(), n, lo, hi, nthreads);
+    }
+    *x = x0;
+    out[q] = double((8 * (F[0] - F[1]) - (F[2] - F[3])) / (12 * (long double)h));
+  }
+}
+
+// J and U = int |E|^2 dt (midpoint rule) of a synthesised pulse and their derivatives with
+// respect to every coefficient; tables from the long-double synthesis (rounded to double).
+void orc_grad_coeff_fd_ld(int ns, int order, double wmin, double wmax, double T, int nt, int norm, double norm_value,
+                          const double* coeff, const int* n, const double* lo, const double* hi, double h, double* gJ,
+                          double* gU, double* J0, double* U0, int nthreads) {
+  const int nc = 4 * ns;
+  std::vector<double> c(coeff, coeff + nc), Amid(2 * (size_t)nt), Emid(2 * (size_t)nt), Aedge(4);
+  auto eval = [&](long double* J, long double* U) {
+    double scale;
+    synth_impl<long double>(ns, order, wmin, wmax, T, nt, norm, norm_value, c.data(), Amid.data(), Emid.data(),
+                            Aedge.data(), &scale);
+    // energy of the field: recompute E in long double at the midpoints (the double table only
+    // stores it rounded)
+    auto P = make_pulse<long double>(ns, order, wmin, wmax, T, nt, norm, norm_value, c.data());
+    set_scale<long double>(P);
+    const long double dt = P.T / (long double)nt, ti = -P.T / 2;
+    long double u = 0;
+    for (int k = 0; k < nt; ++k) {
+      long double e[2];
+      field<long double>(P, ti + ((long double)k + 0.5L) * dt, e);
+      u += P.scale * P.scale * (e[0] * e[0] + e[1] * e[1]);
+    }
+    *U = u * dt;
+    *J = yield_table_ld(nt, (long double)T / nt, Amid.data(), Aedge.data(), n, lo, hi, nthreads);
+  };
+  long double J, U;
+  eval(&J, &U);
+  if (J0) *J0 = double(J);
+  if (U0) *U0 = double(U);
+  for (int i = 0; i < nc; ++i) {
+    const double x0 = c[i];
+    long double Fj[4], Fu[4];
+    const double st[4] = {h, -h, 2 * h, -2 * h};
+    for (int k = 0; k < 4; ++k) {
+      c[i] = x0 + st[k];
+      eval(&Fj[k], &Fu[k]);
+    }
+    c[i] = x0;
+    if (gJ) gJ[i] = double((8 * (Fj[0] - Fj[1]) - (Fj[2] - Fj[3])) / (12 * (long double)h));
+    if (gU) gU[i] = double((8 * (Fu[0] - Fu[1]) - (Fu[2] - Fu[3])) / (12 * (long double)h));
+  }
 }
 
 // Philox4x32-10 block.
