@@ -158,6 +158,80 @@ def surrogate_de(api, W, S, torch, pop=512, generations=200, seed=0):
     return out
 
 
+def de_variants(api, W, torch, pop=64, generations=60, islands=4, migrate_every=5, seed=0):
+    """Plain DE/rand/1/bin (F = 0.8, CR = 0.9, one population) against self-adaptive jDE on
+    `islands` islands with ring migration every `migrate_every` generations (Sec. IV B), from the
+    same initial population, on the surrogate-data evaluator (T = 400, nt = 4096, 64x64x16
+    modes): best J per generation and generations per second, every step on the device."""
+    spec, grid = W.surrogate_data_spec()
+    D = 4 * spec["n_s"]
+    x0 = W.draw_coeff(seed, pop, spec["n_s"]).reshape(pop, D)
+    fit0, _ = api.evaluate([spec] * pop, [grid] * pop, x0)
+    out = {"workload": f"pop {pop}, T=400, nt=4096, 64x64x16 modes, {generations} generations"}
+    for name in ("plain", f"jde_islands{islands}"):
+        P = torch.as_tensor(x0, dtype=torch.float64, device="cuda")
+        fit = fit0.clone()
+        trial, tfit = torch.empty_like(P), torch.empty_like(fit)
+        best = []
+        if name == "plain":
+            prm = api.de_params(pop, D, spec["n_s"], F=0.8, CR=0.9, seed=seed + 1)
+        else:
+            prm = api.jde_params(pop, D, spec["n_s"], islands=islands, seed=seed + 1)
+            fcr = torch.tensor([[0.8, 0.9]] * pop, dtype=torch.float64, device="cuda")
+            tfcr = torch.empty_like(fcr)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for g in range(generations):
+            if name == "plain":
+                api.po_de_generation(prm, g, spec, grid, P, fit, trial, tfit)
+            else:
+                api.po_jde_generation(prm, g, spec, grid, P, fit, fcr, trial, tfit, tfcr)
+                if (g + 1) % migrate_every == 0:
+                    api.po_island_migrate(prm, P, fit, fcr)
+            best.append(float(fit.max().item()))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = {"generations_per_s": generations / dt, "best_J_first": best[0], "best_J_final": best[-1],
+                     "best_J_every_10": best[9::10]}
+    out["final_ratio_jde_over_plain"] = out[f"jde_islands{islands}"]["best_J_final"] / out["plain"]["best_J_final"]
+    return out
+
+
+def local_search(api, W, torch, starts=10, seed=0):
+    """Multistart local search of Sec. IV A (BFGS + strong Wolfe on the augmented Lagrangian of
+    the energy constraint, gradients from the discrete adjoint on the device): evaluations per
+    start, J reached, and the cost of one gradient against one evaluation of J."""
+    import numpy as np
+    from paper_1704_08919_amd import localsearch as LS
+    w = W.local_search(seed, starts=starts)
+    specs, grids, c = w["specs"], w["grids"], w["coeff"]
+    x0 = c.reshape(starts, -1)
+    out = LS.run(specs, grids, x0, w["U_const"])
+    res = out["results"]
+    # cost of a gradient relative to an evaluation of J, same batch
+    xs = np.stack([r["x"] for r in res])
+    t = {}
+    for name in ("J", "gradient"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            if name == "J":
+                api.evaluate(specs, grids, xs)
+            else:
+                api.evaluate_gradient(specs, grids, xs)
+        torch.cuda.synchronize()
+        t[name] = (time.perf_counter() - t0) / 3
+    ms = W.mode_steps(specs, grids)
+    return {"workload": w["name"], "starts": starts, "wall_s": out["wall_s"],
+            "evaluations_per_start": out["evaluations"].tolist(),
+            "J_start": out["J_start"].tolist(), "J_final": [r["J"] for r in res],
+            "constraint_violation_max": max(abs(r["U"] - w["U_const"]) / w["U_const"] for r in res),
+            "outer_iterations": [r["outer"] for r in res], "bfgs_iterations": [r["iterations"] for r in res],
+            "best_J": res[out["best"]]["J"], "J_eval_s": t["J"], "gradient_eval_s": t["gradient"],
+            "gradient_over_J_cost": t["gradient"] / t["J"],
+            "gradient_mode_steps_per_s": ms / t["gradient"]}
+
+
 def solver_comparison(api, W, torch, n_p=512, nts=(5000, 10000, 20000, 50000, 100000, 200000, 500000, 1000000),
                       nt_exact=2_000_000, target=1e-3):
     """The paper's accuracy-versus-time comparison (Sec. V C) on the circular multimode pulse of its
@@ -240,6 +314,8 @@ def main():
     ap.add_argument("--cpu-sample-pulses", type=int, default=3)
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch plan measurement")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate training and DE comparison")
+    ap.add_argument("--no-de-variants", action="store_true", help="skip the plain DE versus jDE-on-islands run")
+    ap.add_argument("--no-local-search", action="store_true", help="skip the multistart BFGS local search")
     ap.add_argument("--no-solvers", action="store_true",
                     help="skip the accuracy-versus-time comparison of the Dirac, Magnus and kinetic solvers")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -327,6 +403,10 @@ def main():
         out["uneven_batch"] = guarded(uneven_batch, api, W, torch, mode_steps / ev_s)
     if not args.no_solvers:
         out["solver_comparison"] = guarded(solver_comparison, api, W, torch)
+    if not args.no_de_variants:
+        out["de_variants"] = guarded(de_variants, api, W, torch)
+    if not args.no_local_search:
+        out["local_search"] = guarded(local_search, api, W, torch)
     if not args.no_surrogate:
         from paper_1704_08919_amd import surrogate as S
         out["surrogate_training"] = guarded(surrogate_training, api, W, S, torch)

@@ -196,6 +196,41 @@ po_status po_evolve_modes_m4(int32_t n_pulses, const po_pulse_spec* specs, const
                              void* stream);
 
 /* ---------------------------------------------------------------------------------------
+ * Gradients for the local search of Sec. IV A (the gradient of the objective with respect to
+ * the field parameters, which the BFGS iteration needs).  The paper obtains it from the adjoint
+ * of the kinetic equation; here it is the exact derivative of the discrete Dirac evaluation of
+ * J (the adjoint of its steps), so it is the gradient of exactly the J that po_evaluate returns
+ * up to rounding.
+ *
+ * po_yield_gradient -- J and dJ/dA for any tables (as po_evolve_modes):
+ *  d_J      out [n_pulses] or NULL.
+ *  d_gA     out [sum nt][2]: dJ/dA at every step midpoint.
+ *  d_gedge  out [n_pulses][2][2] or NULL: dJ/dA(t_i), dJ/dA(t_f) (initial state, projection).
+ * Work buffers of (modes / 256) x nt x 16 bytes per pulse come from the stream-ordered pool.
+ *
+ * po_synth_gradient -- chain rule through the synthesis (Sec. III) of po_pulse_synth:
+ *  d_gA, d_gedge  as produced above (d_gedge may be NULL: no end-point terms).
+ *  d_grad   out [sum 4 n_s]: dJ/dc for the coefficient layout of po_pulse_synth.
+ *  d_U      out [n_pulses] or NULL: the energy U = int |E|^2 dt of the synthesised field
+ *           (midpoint rule, Sec. III Eq. energy).
+ *  d_gU     out [sum 4 n_s] or NULL: dU/dc (zero under PO_NORM_ENERGY, which fixes U).
+ * PO_NORM_NONE differentiates the raw field (the paper's local search, with U handled by a
+ * penalty); PO_NORM_ENERGY includes the dependence of the scale on c.  PO_NORM_PEAK is not
+ * differentiable and returns PO_ERR_UNSUPPORTED.
+ *
+ * po_evaluate_gradient -- fused synthesis -> J and dJ/dA -> dJ/dc (and U, dU/dc).
+ * --------------------------------------------------------------------------------------- */
+po_status po_yield_gradient(int32_t n_pulses, const po_pulse_spec* specs, const po_grid* grids,
+                            const double* d_A, const double* d_A_edge, double* d_J, double* d_gA,
+                            double* d_gedge, void* stream);
+po_status po_synth_gradient(int32_t n_pulses, const po_pulse_spec* specs, const double* d_coeff,
+                            const double* d_gA, const double* d_gedge, double* d_grad, double* d_U,
+                            double* d_gU, void* stream);
+po_status po_evaluate_gradient(int32_t n_pulses, const po_pulse_spec* specs, const po_grid* grids,
+                               const double* d_coeff, double* d_J, double* d_grad, double* d_U,
+                               double* d_gU, void* stream);
+
+/* ---------------------------------------------------------------------------------------
  * Differential evolution, DE/rand/1/bin with greedy selection for maximisation (Sec. IV B).
  *  pop, dim  population size N >= 4 and genes per individual D >= 1.
  *  n_s       genes in odd blocks of n_s (phase coefficients) wrap periodically into [lo, hi];

@@ -64,6 +64,11 @@ SIGNATURES = {
                           _P, _P, _P], ctypes.c_int),
     "po_qke_modes": ([_I32, ctypes.POINTER(PulseSpec), ctypes.POINTER(Grid), _P, _P, _P, _I32, _P, _P, _P],
                      ctypes.c_int),
+    "po_yield_gradient": ([_I32, ctypes.POINTER(PulseSpec), ctypes.POINTER(Grid), _P, _P, _P, _P, _P, _P],
+                          ctypes.c_int),
+    "po_synth_gradient": ([_I32, ctypes.POINTER(PulseSpec), _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "po_evaluate_gradient": ([_I32, ctypes.POINTER(PulseSpec), ctypes.POINTER(Grid), _P, _P, _P, _P, _P, _P],
+                             ctypes.c_int),
     "po_evolve_modes_m4": ([_I32, ctypes.POINTER(PulseSpec), ctypes.POINTER(Grid), _P, _P, _P, _P, _P],
                            ctypes.c_int),
     "po_evaluate": ([_I32, ctypes.POINTER(PulseSpec), ctypes.POINTER(Grid), _P, _P, _P, _P, _P, _P, _P, _P],

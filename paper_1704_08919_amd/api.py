@@ -93,6 +93,24 @@ def po_evolve_modes_m4(specs, grids, Ag, A_edge, f=None, J=None, stream=None):
     check(load().po_evolve_modes_m4(len(specs), sp, gr, _ptr(Ag), _ptr(A_edge), _ptr(f), _ptr(J), _stream(stream)))
 
 
+def po_yield_gradient(specs, grids, A, A_edge, gA, J=None, gedge=None, stream=None):
+    sp, gr = _spec_array(specs), _grid_array(grids)
+    check(load().po_yield_gradient(len(specs), sp, gr, _ptr(A), _ptr(A_edge), _ptr(J), _ptr(gA), _ptr(gedge),
+                                   _stream(stream)))
+
+
+def po_synth_gradient(specs, coeff, gA, grad, gedge=None, U=None, gU=None, stream=None):
+    sp = _spec_array(specs)
+    check(load().po_synth_gradient(len(specs), sp, _ptr(coeff), _ptr(gA), _ptr(gedge), _ptr(grad), _ptr(U), _ptr(gU),
+                                   _stream(stream)))
+
+
+def po_evaluate_gradient(specs, grids, coeff, J, grad, U=None, gU=None, stream=None):
+    sp, gr = _spec_array(specs), _grid_array(grids)
+    check(load().po_evaluate_gradient(len(specs), sp, gr, _ptr(coeff), _ptr(J), _ptr(grad), _ptr(U), _ptr(gU),
+                                      _stream(stream)))
+
+
 def po_pair_yield(grids, f, J, stream=None):
     gr = _grid_array(grids)
     check(load().po_pair_yield(len(grids), gr, _ptr(f), _ptr(J), _stream(stream)))
@@ -363,6 +381,16 @@ def evolve_m4(specs, grids, Ag, A_edge, want_f=True, want_J=True, device="cuda")
     J = torch.empty(len(specs), dtype=torch.float64, device=device) if want_J else None
     po_evolve_modes_m4(specs, grids, Ag, A_edge, f=f, J=J)
     return f, J
+
+
+def evaluate_gradient(specs, grids, coeff, device="cuda"):
+    """Allocates outputs and runs po_evaluate_gradient: returns (J, dJ/dc [sum 4 n_s], U, dU/dc)."""
+    coeff = torch.as_tensor(coeff, dtype=torch.float64).reshape(-1).contiguous().to(device)
+    J = torch.empty(len(specs), dtype=torch.float64, device=device)
+    U = torch.empty(len(specs), dtype=torch.float64, device=device)
+    grad, gU = torch.empty_like(coeff), torch.empty_like(coeff)
+    po_evaluate_gradient(specs, grids, coeff, J, grad, U=U, gU=gU)
+    return J, grad, U, gU
 
 
 def de_params(pop, dim, n_s, F=0.8, CR=0.9, lo=-1.0, hi=1.0, seed=0):

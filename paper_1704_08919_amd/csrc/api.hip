@@ -135,6 +135,7 @@ po_status build_batch(int32_t n, const po_pulse_spec* specs, const po_grid* grid
       coeff += 4 * int64_t(s.n_s);
       spec += 4 * int64_t(d.nlines);
       b->max_nt = std::max(b->max_nt, s.nt);
+      b->max_lines = std::max(b->max_lines, d.nlines);
       b->max_stat_blocks = std::max(b->max_stat_blocks, d.stat_blocks);
       if (i > 0 && (s.nt != specs[0].nt || s.T != specs[0].T)) b->uniform = false;
     }
@@ -225,6 +226,39 @@ po_status evolve_impl(const Batch& b, const PulseDev* d_desc, const double* d_A,
     PO_TRY(timer_count(b.n_pulses, d_desc, d_sel, s));
   }
   if (d_J) PO_TRY(launch_yield_from_units(b, d_desc, d_units, d_J, s));
+  return PO_OK;
+}
+
+// Gradient of J with respect to the tables (forward + adjoint sweep per mode, fixed-order sums).
+po_status yield_grad_impl(const Batch& b, const std::vector<PulseDev>& h, const PulseDev* d_desc, const double* d_A,
+                          const double* d_A_edge, double* d_J, double* d_gA, double* d_gedge, hipStream_t s) {
+  std::vector<int64_t> goff(b.n_pulses);
+  int64_t tot = 0;
+  for (int i = 0; i < b.n_pulses; ++i) {
+    goff[i] = tot;
+    tot += int64_t(h[i].nitems) * h[i].nt * 2;
+  }
+  Scratch sgoff, part, epart, units, sel, ged;
+  PO_TRY(sgoff.alloc(sizeof(int64_t) * goff.size(), s));
+  PO_HIP(hipMemcpyAsync(sgoff.ptr, goff.data(), sizeof(int64_t) * goff.size(), hipMemcpyHostToDevice, s));
+  PO_TRY(part.alloc(sizeof(double) * size_t(tot), s));
+  PO_TRY(epart.alloc(sizeof(double) * 4 * size_t(b.total_items), s));
+  PO_TRY(units.alloc(sizeof(double) * size_t(b.total_units), s));
+  PO_TRY(sel.alloc(sizeof(int2) * size_t(b.n_pulses), s));
+  int2* d_sel = static_cast<int2*>(sel.ptr);
+  double* d_units = static_cast<double*>(units.ptr);
+  PO_TRY(launch_series_select(b, d_desc, d_A, d_A_edge, d_sel, s));
+  PO_TRY(launch_yield_grad(b, d_desc, d_A, d_A_edge, d_sel, static_cast<int64_t*>(sgoff.ptr),
+                           static_cast<double*>(part.ptr), static_cast<double*>(epart.ptr), d_units, d_gA, d_gedge, s));
+  if (d_J) PO_TRY(launch_yield_from_units(b, d_desc, d_units, d_J, s));
+  return PO_OK;
+}
+
+po_status check_differentiable(int32_t n, const po_pulse_spec* specs) {
+  for (int i = 0; i < n; ++i)
+    if (specs[i].norm == PO_NORM_PEAK)
+      return set_error(PO_ERR_UNSUPPORTED, "spec %d: the peak normalisation is not differentiable; use "
+                                           "PO_NORM_NONE (with an energy penalty) or PO_NORM_ENERGY", i);
   return PO_OK;
 }
 
@@ -415,6 +449,89 @@ po_status po_evolve_modes_m4(int32_t n, const po_pulse_spec* specs, const po_gri
   PO_TRY(launch_evolve4_grid(b, d_desc, d_Ag, d_A_edge, d_sel, d_f, d_units, s));
   if (d_J) PO_TRY(launch_yield_from_units(b, d_desc, d_units, d_J, s));
   return PO_OK;
+}
+
+po_status po_yield_gradient(int32_t n, const po_pulse_spec* specs, const po_grid* grids, const double* d_A,
+                            const double* d_A_edge, double* d_J, double* d_gA, double* d_gedge, void* stream) {
+  if (n < 1) return set_error(PO_ERR_INVALID, "n_pulses must be >= 1");
+  PO_TRY(check_specs(n, specs));
+  PO_TRY(check_grids(n, grids));
+  std::vector<PulseDev> h(n);
+  Batch b;
+  PO_TRY(build_batch(n, specs, grids, h.data(), &b));
+  PO_TRY(check_device_range(d_A, sizeof(double) * 2 * b.total_rows, 8, "d_A"));
+  PO_TRY(check_device_range(d_A_edge, sizeof(double) * 4 * n, 8, "d_A_edge"));
+  PO_TRY(check_device_range(d_gA, sizeof(double) * 2 * b.total_rows, 8, "d_gA"));
+  if (d_gedge) PO_TRY(check_device_range(d_gedge, sizeof(double) * 4 * n, 8, "d_gedge"));
+  if (d_J) PO_TRY(check_device_range(d_J, sizeof(double) * n, 8, "d_J"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Scratch desc;
+  PO_TRY(upload(h, desc, s));
+  return yield_grad_impl(b, h, static_cast<PulseDev*>(desc.ptr), d_A, d_A_edge, d_J, d_gA, d_gedge, s);
+}
+
+po_status po_synth_gradient(int32_t n, const po_pulse_spec* specs, const double* d_coeff, const double* d_gA,
+                            const double* d_gedge, double* d_grad, double* d_U, double* d_gU, void* stream) {
+  if (n < 1) return set_error(PO_ERR_INVALID, "n_pulses must be >= 1");
+  PO_TRY(check_specs(n, specs));
+  PO_TRY(check_differentiable(n, specs));
+  std::vector<PulseDev> h(n);
+  Batch b;
+  PO_TRY(build_batch(n, specs, nullptr, h.data(), &b));
+  PO_TRY(check_device_range(d_coeff, sizeof(double) * b.total_coeff, 8, "d_coeff"));
+  PO_TRY(check_device_range(d_gA, sizeof(double) * 2 * b.total_rows, 8, "d_gA"));
+  if (d_gedge) PO_TRY(check_device_range(d_gedge, sizeof(double) * 4 * n, 8, "d_gedge"));
+  PO_TRY(check_device_range(d_grad, sizeof(double) * b.total_coeff, 8, "d_grad"));
+  if (d_U) PO_TRY(check_device_range(d_U, sizeof(double) * n, 8, "d_U"));
+  if (d_gU) PO_TRY(check_device_range(d_gU, sizeof(double) * b.total_coeff, 8, "d_gU"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Scratch desc, A, E, edge, scl, lines;
+  PO_TRY(upload(h, desc, s));
+  const PulseDev* d_desc = static_cast<PulseDev*>(desc.ptr);
+  PO_TRY(A.alloc(sizeof(double) * 2 * b.total_rows, s));
+  PO_TRY(E.alloc(sizeof(double) * 2 * b.total_rows, s));
+  PO_TRY(edge.alloc(sizeof(double) * 4 * n, s));
+  PO_TRY(scl.alloc(sizeof(double) * n, s));
+  PO_TRY(lines.alloc(sizeof(double) * 2 * size_t(b.total_spec), s));
+  double *dA = static_cast<double*>(A.ptr), *dE = static_cast<double*>(E.ptr), *de = static_cast<double*>(edge.ptr);
+  double* dscale = static_cast<double*>(scl.ptr);
+  PO_TRY(synth_impl(n, specs, d_coeff, dA, dE, de, dscale, s, b, d_desc));
+  return launch_synth_adjoint(b, d_desc, d_coeff, d_gA, d_gedge, dA, de, dE, dscale, static_cast<double*>(lines.ptr),
+                              d_grad, d_U, d_gU, s);
+}
+
+po_status po_evaluate_gradient(int32_t n, const po_pulse_spec* specs, const po_grid* grids, const double* d_coeff,
+                               double* d_J, double* d_grad, double* d_U, double* d_gU, void* stream) {
+  if (n < 1) return set_error(PO_ERR_INVALID, "n_pulses must be >= 1");
+  PO_TRY(check_specs(n, specs));
+  PO_TRY(check_grids(n, grids));
+  PO_TRY(check_differentiable(n, specs));
+  std::vector<PulseDev> h(n);
+  Batch b;
+  PO_TRY(build_batch(n, specs, grids, h.data(), &b));
+  PO_TRY(check_device_range(d_coeff, sizeof(double) * b.total_coeff, 8, "d_coeff"));
+  PO_TRY(check_device_range(d_J, sizeof(double) * n, 8, "d_J"));
+  PO_TRY(check_device_range(d_grad, sizeof(double) * b.total_coeff, 8, "d_grad"));
+  if (d_U) PO_TRY(check_device_range(d_U, sizeof(double) * n, 8, "d_U"));
+  if (d_gU) PO_TRY(check_device_range(d_gU, sizeof(double) * b.total_coeff, 8, "d_gU"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Scratch desc, A, E, edge, scl, gA, gedge, lines;
+  PO_TRY(upload(h, desc, s));
+  const PulseDev* d_desc = static_cast<PulseDev*>(desc.ptr);
+  PO_TRY(A.alloc(sizeof(double) * 2 * b.total_rows, s));
+  PO_TRY(E.alloc(sizeof(double) * 2 * b.total_rows, s));
+  PO_TRY(edge.alloc(sizeof(double) * 4 * n, s));
+  PO_TRY(scl.alloc(sizeof(double) * n, s));
+  PO_TRY(gA.alloc(sizeof(double) * 2 * b.total_rows, s));
+  PO_TRY(gedge.alloc(sizeof(double) * 4 * n, s));
+  PO_TRY(lines.alloc(sizeof(double) * 2 * size_t(b.total_spec), s));
+  double *dA = static_cast<double*>(A.ptr), *dE = static_cast<double*>(E.ptr), *de = static_cast<double*>(edge.ptr);
+  double *dscale = static_cast<double*>(scl.ptr), *dgA = static_cast<double*>(gA.ptr);
+  double* dge = static_cast<double*>(gedge.ptr);
+  PO_TRY(synth_impl(n, specs, d_coeff, dA, dE, de, dscale, s, b, d_desc));
+  PO_TRY(yield_grad_impl(b, h, d_desc, dA, de, d_J, dgA, dge, s));
+  return launch_synth_adjoint(b, d_desc, d_coeff, dgA, dge, dA, de, dE, dscale, static_cast<double*>(lines.ptr),
+                              d_grad, d_U, d_gU, s);
 }
 
 po_status po_pair_yield(int32_t n, const po_grid* grids, const double* d_f, double* d_J, void* stream) {

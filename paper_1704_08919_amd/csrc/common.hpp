@@ -61,6 +61,7 @@ struct Batch {
   int32_t total_items = 0;     // workgroups of the default evolution launch
   int32_t max_stat_blocks = 0; // largest per-pulse block count of the field statistics pass
   int32_t max_nt = 0;
+  int32_t max_lines = 0;       // most spectral lines of any pulse
   bool uniform = true;         // all pulses share nt/grid (lets kernels skip the binary search)
 };
 
@@ -89,6 +90,17 @@ po_status launch_synth(const Batch& b, const PulseDev* d_desc, const double* d_c
 po_status launch_samples(const Batch& b, const PulseDev* d_desc, const double* d_coeff, double* d_spec, double* d_part,
                          double* d_scale_ws, int n_sub, const double* offsets, int with_end, double* d_E,
                          double* d_Ed, double* d_A, double* d_A_edge, double* d_scale_out, hipStream_t s);
+// Adjoint of the synthesis: d_lines scratch [sum lines][8]; d_A, d_A_edge, d_E the (scaled) tables of
+// the pulses and d_scale their scale; d_gA [sum nt][2] and d_gedge [n][2][2] (or NULL) the gradient of
+// J with respect to the tables.  Writes dJ/dc, the energy U and dU/dc (NULL to skip).
+po_status launch_synth_adjoint(const Batch& b, const PulseDev* d_desc, const double* d_coeff, const double* d_gA,
+                               const double* d_gedge, const double* d_A, const double* d_A_edge, const double* d_E,
+                               const double* d_scale, double* d_lines, double* d_grad, double* d_U, double* d_gU,
+                               hipStream_t s);
+// Yield gradient (grad.hip): d_part [sum items_i nt_i][2] item partials at d_goff[i]; d_epart [items][4].
+po_status launch_yield_grad(const Batch& b, const PulseDev* d_desc, const double* d_A, const double* d_A_edge,
+                            const int2* d_sel, const int64_t* d_goff, double* d_part, double* d_epart, double* d_units,
+                            double* d_gA, double* d_gedge, hipStream_t s);
 // Launch shape of the evolution kernel.  threads: lanes per workgroup (64, 128, 256);
 // mpl: modes per lane (1, 2); persistent: workgroups pull items from a device queue.
 struct EvolveConfig {

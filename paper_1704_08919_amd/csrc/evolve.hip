@@ -31,6 +31,7 @@
 // the launch shape or on scheduling.  Two launch forms share the item code: one workgroup per
 // 256-mode item, or persistent workgroups that pull items (longest pulses first) from a device
 // queue through an atomic counter.
+#include "dirac.hpp"
 #include "reduce.hpp"
 
 // Every fused multiply-add below is written out: automatic contraction is off, so each mode's
@@ -40,169 +41,6 @@
 
 namespace po {
 namespace {
-
-constexpr int kChunk = 256;   // steps staged per LDS buffer
-
-constexpr double factorial(int n) { return n <= 1 ? 1.0 : double(n) * factorial(n - 1); }
-// Maclaurin coefficients of cos(sqrt x) and sin(sqrt x)/sqrt x.
-constexpr double cos_coef(int k) { return (k % 2 ? -1.0 : 1.0) / factorial(2 * k); }
-constexpr double sinc_coef(int k) { return (k % 2 ? -1.0 : 1.0) / factorial(2 * k + 1); }
-
-// Maclaurin coefficients of tan(z) = sum_k a_k z^k from tan' = 1 + tan^2:
-// (k + 1) a_{k+1} = [k == 0] + sum_{i+j=k} a_i a_j, so tan(sqrt x)/sqrt x = sum_n a_{2n+1} x^n.
-struct TanCoef {
-  double a[48];
-};
-constexpr TanCoef tan_coefs() {
-  TanCoef t{};
-  for (int k = 0; k + 1 < 48; ++k) {
-    double s = (k == 0) ? 1.0 : 0.0;
-    for (int i = 0; i <= k; ++i) s += t.a[i] * t.a[k - i];
-    t.a[k + 1] = s / double(k + 1);
-  }
-  return t;
-}
-constexpr TanCoef kTan = tan_coefs();
-constexpr double tan_coef(int n) { return kTan.a[2 * n + 1]; }
-
-// Series variants.  T-series degrees and the largest x at which the remainder
-// sum_{k>n} a_{2k+1} x^k <= a_{2n+3} x^{n+1} / (1 - 0.4053 x) (the coefficient ratio rises to
-// 4/pi^2 = 0.40528...) is below 2^-56.  Beyond the last, C and S of degree 7 (first omitted
-// term x^8/16! < 2^-56 for x <= 0.3612; both series alternate with decreasing terms) after h
-// angle halvings.
-constexpr int kNumTan = 4;
-constexpr int kTanDegree[kNumTan] = {6, 8, 10, 13};
-constexpr double kTanXmax[kNumTan] = {0.0099, 0.0337, 0.0735, 0.1558};
-constexpr double kCosSinXmax = 0.3612;
-constexpr int kHalvingMode = kNumTan;
-constexpr int kNumModes = kNumTan + 1;
-constexpr double kSqrt3Over6 = 0.28867513459481288225;  // sqrt(3)/6, Gauss-Legendre nodes 1/2 -+ sqrt(3)/6
-
-// Horner step k of the C and S series, coefficients forced to compile-time constants.
-template <int K>
-__device__ __forceinline__ void horner_cs(double x, double& C, double& S) {
-  constexpr double cc = cos_coef(K), sc = sinc_coef(K);
-  C = fma(C, x, cc);
-  S = fma(S, x, sc);
-  if constexpr (K > 0) horner_cs<K - 1>(x, C, S);
-}
-
-template <int D>
-__device__ __forceinline__ void cos_sinc(double x, double& C, double& S) {
-  constexpr double cd = cos_coef(D), sd = sinc_coef(D);
-  C = cd;
-  S = sd;
-  horner_cs<D - 1>(x, C, S);
-}
-
-template <int K>
-__device__ __forceinline__ void horner_tan(double x, double& T) {
-  constexpr double c = tan_coef(K);
-  T = fma(T, x, c);
-  if constexpr (K > 0) horner_tan<K - 1>(x, T);
-}
-
-// T(x) = tan(sqrt x)/sqrt x, degree N.
-template <int N>
-__device__ __forceinline__ double tan_ratio(double x) {
-  constexpr double c = tan_coef(N);
-  double T = c;
-  horner_tan<N - 1>(x, T);
-  return T;
-}
-
-// (a_r, a_i, b_r, b_i) of block s = +1 and (c_r, c_i, d_r, d_i) of block s = -1.
-struct State {
-  double ar, ai, br, bi, cr, ci, dr, di;
-};
-
-// psi <- (C - i S Q_s) psi for both blocks:
-//   s = +1:  a' = (C - i sz) a + (-sy - i sx) b ;  b' = (sy - i sx) a + (C + i sz) b,  s_q = S q;
-//   s = -1:  the same with sy -> -sy.
-__device__ __forceinline__ void rotate(State& v, double C, double S, double qx, double qy, double qz) {
-  const double sx = S * qx, sy = S * qy, sz = S * qz;
-  const double ar = fma(sx, v.bi, fma(-sy, v.br, fma(sz, v.ai, C * v.ar)));
-  const double ai = fma(-sx, v.br, fma(-sy, v.bi, fma(-sz, v.ar, C * v.ai)));
-  const double br = fma(-sz, v.bi, fma(C, v.br, fma(sx, v.ai, sy * v.ar)));
-  const double bi = fma(sz, v.br, fma(C, v.bi, fma(-sx, v.ar, sy * v.ai)));
-  const double cr = fma(sx, v.di, fma(sy, v.dr, fma(sz, v.ci, C * v.cr)));
-  const double ci = fma(-sx, v.dr, fma(sy, v.di, fma(-sz, v.cr, C * v.ci)));
-  const double dr = fma(-sz, v.di, fma(C, v.dr, fma(sx, v.ci, -sy * v.cr)));
-  const double di = fma(sz, v.dr, fma(C, v.di, fma(-sx, v.cr, -sy * v.ci)));
-  v = State{ar, ai, br, bi, cr, ci, dr, di};
-}
-
-// psi <- (1 - i T Q_s) psi for both blocks: the rotation above with C -> 1 and S -> T.
-__device__ __forceinline__ void rotate_tan(State& v, double T, double qx, double qy, double qz) {
-  const double tx = T * qx, ty = T * qy, tz = T * qz;
-  const double ar = fma(tx, v.bi, fma(-ty, v.br, fma(tz, v.ai, v.ar)));
-  const double ai = fma(-tx, v.br, fma(-ty, v.bi, fma(-tz, v.ar, v.ai)));
-  const double br = fma(-tz, v.bi, fma(tx, v.ai, fma(ty, v.ar, v.br)));
-  const double bi = fma(tz, v.br, fma(-tx, v.ar, fma(ty, v.ai, v.bi)));
-  const double cr = fma(tx, v.di, fma(ty, v.dr, fma(tz, v.ci, v.cr)));
-  const double ci = fma(-tx, v.dr, fma(ty, v.di, fma(-tz, v.cr, v.ci)));
-  const double dr = fma(-tz, v.di, fma(tx, v.ci, fma(-ty, v.cr, v.dr)));
-  const double di = fma(tz, v.dr, fma(-tx, v.cr, fma(-ty, v.ci, v.di)));
-  v = State{ar, ai, br, bi, cr, ci, dr, di};
-}
-
-template <int N>
-__device__ __forceinline__ void step_tan(State& v, double2 rec, double pxdt, double pydt, double qz, double qz2) {
-  const double qx = pxdt + rec.x;  // rec = -A dt
-  const double qy = pydt + rec.y;
-  const double x = fma(qx, qx, fma(qy, qy, qz2));
-  rotate_tan(v, tan_ratio<N>(x), qx, qy, qz);
-}
-
-// Large-step path: C, S at x / 4^h, then h double-angle steps; the step stays unitary.
-__device__ __forceinline__ void step_halving(State& v, double2 rec, double pxdt, double pydt, double qz, double qz2,
-                                             int h, double inv4h) {
-  const double qx = pxdt + rec.x;
-  const double qy = pydt + rec.y;
-  const double x = fma(qx, qx, fma(qy, qy, qz2));
-  double xs = x * inv4h;
-  double C, S;
-  cos_sinc<7>(xs, C, S);  // xs <= kCosSinXmax
-  for (int i = 0; i < h; ++i) {
-    const double c2 = fma(C, C, -(xs * S) * S);  // cos 2t = cos^2 t - t^2 (sin t / t)^2
-    S = S * C;                                 // sin 2t / 2t = (sin t / t) cos t
-    C = c2;
-    xs *= 4.0;
-  }
-  rotate(v, C, S, qx, qy, qz);
-}
-
-// Rescales the state by an exact power of two (no rounding) so that |psi_{+1}|^2 is O(1).
-__device__ __forceinline__ void renormalise(State& v) {
-  const double n2 = fma(v.bi, v.bi, fma(v.br, v.br, fma(v.ai, v.ai, v.ar * v.ar)));
-  const int e = -(ilogb(n2) >> 1);
-  v.ar = ldexp(v.ar, e); v.ai = ldexp(v.ai, e); v.br = ldexp(v.br, e); v.bi = ldexp(v.bi, e);
-  v.cr = ldexp(v.cr, e); v.ci = ldexp(v.ci, e); v.dr = ldexp(v.dr, e); v.di = ldexp(v.di, e);
-}
-
-// Negative-energy eigenvector of h_s(P): (-(P_x - i s P_y), w + e) / sqrt(2 w (w + e)).
-__device__ __forceinline__ void init_state(State& v, double Px, double Py, double e) {
-  const double w = sqrt(fma(Px, Px, fma(Py, Py, e * e)));
-  const double n = 1.0 / sqrt((2.0 * w) * (w + e));
-  v.ar = -Px * n; v.ai = Py * n;  v.br = (w + e) * n; v.bi = 0.0;   // s = +1
-  v.cr = -Px * n; v.ci = -Py * n; v.dr = (w + e) * n; v.di = 0.0;   // s = -1
-}
-
-// f = sum_s |<+_s(P)|psi_s>|^2 / |psi_s|^2 with |+_s> = (w + e, P_x + i s P_y) / sqrt(2 w (w + e)).
-__device__ __forceinline__ double project(const State& v, double Px, double Py, double e) {
-  const double w = sqrt(fma(Px, Px, fma(Py, Py, e * e)));
-  const double we = w + e;
-  const double n2 = 1.0 / ((2.0 * w) * we);
-  // s = +1: (w+e) a + (P_x - i P_y) b
-  const double r1 = fma(Py, v.bi, fma(Px, v.br, we * v.ar));
-  const double i1 = fma(-Py, v.br, fma(Px, v.bi, we * v.ai));
-  // s = -1: (w+e) c + (P_x + i P_y) d
-  const double r2 = fma(-Py, v.di, fma(Px, v.dr, we * v.cr));
-  const double i2 = fma(Py, v.dr, fma(Px, v.di, we * v.ci));
-  const double m1 = fma(v.bi, v.bi, fma(v.br, v.br, fma(v.ai, v.ai, v.ar * v.ar)));
-  const double m2 = fma(v.di, v.di, fma(v.dr, v.dr, fma(v.ci, v.ci, v.cr * v.cr)));
-  return (fma(i1, i1, r1 * r1) / m1 + fma(i2, i2, r2 * r2) / m2) * n2;
-}
 
 __device__ __forceinline__ double grid_max_abs(double lo, int n, double dp) {
   // largest |p| over the cell-centred points lo + (i + 1/2) dp, i = 0..n-1 (dp = 0: a sheet)
@@ -473,26 +311,6 @@ void launch_persistent_t(EvolveArgs a, const int2* q, int n_items, int nwg, int*
 // add each.  The two blocks now rotate by different angles, so each is rescaled on its own.
 // ---------------------------------------------------------------------------------------------
 
-// psi <- (1 - i t . tau) psi for one block (a, b).
-__device__ __forceinline__ void rotate_block_tan(double& ar, double& ai, double& br, double& bi, double tx, double ty,
-                                                 double tz) {
-  const double nar = fma(tx, bi, fma(-ty, br, fma(tz, ai, ar)));
-  const double nai = fma(-tx, br, fma(-ty, bi, fma(-tz, ar, ai)));
-  const double nbr = fma(-tz, bi, fma(tx, ai, fma(ty, ar, br)));
-  const double nbi = fma(tz, br, fma(-tx, ar, fma(ty, ai, bi)));
-  ar = nar; ai = nai; br = nbr; bi = nbi;
-}
-
-// psi <- (C - i s . tau) psi for one block (a, b).
-__device__ __forceinline__ void rotate_block(double& ar, double& ai, double& br, double& bi, double C, double sx,
-                                             double sy, double sz) {
-  const double nar = fma(sx, bi, fma(-sy, br, fma(sz, ai, C * ar)));
-  const double nai = fma(-sx, br, fma(-sy, bi, fma(-sz, ar, C * ai)));
-  const double nbr = fma(-sz, bi, fma(C, br, fma(sx, ai, sy * ar)));
-  const double nbi = fma(sz, br, fma(C, bi, fma(-sx, ar, sy * ai)));
-  ar = nar; ai = nai; br = nbr; bi = nbi;
-}
-
 struct Magnus4 {
   double Xp, Yp, Zp, Xm, Ym, Zm;  // w_{+1} = (Xp, Yp, Zp); w_{-1} = (Xm, -Ym, Zm)
 };
@@ -512,18 +330,6 @@ __device__ __forceinline__ void step4_tan(State& v, double4 rec, double pxdt, do
   const double Tp = tan_ratio<N>(xp), Tm = tan_ratio<N>(xm);
   rotate_block_tan(v.ar, v.ai, v.br, v.bi, Tp * w.Xp, Tp * w.Yp, Tp * w.Zp);
   rotate_block_tan(v.cr, v.ci, v.dr, v.di, Tm * w.Xm, -(Tm * w.Ym), Tm * w.Zm);
-}
-
-// C = cos sqrt x, S = sin sqrt x / sqrt x from the degree-7 series at x / 4^h and h double-angle steps.
-__device__ __forceinline__ void cos_sinc_halved(double x, int h, double inv4h, double& C, double& S) {
-  double xs = x * inv4h;
-  cos_sinc<7>(xs, C, S);
-  for (int i = 0; i < h; ++i) {
-    const double c2 = fma(C, C, -(xs * S) * S);
-    S = S * C;
-    C = c2;
-    xs *= 4.0;
-  }
 }
 
 __device__ __forceinline__ void step4_halving(State& v, double4 rec, double pxdt, double pydt, double e, int h,

@@ -14,6 +14,19 @@
 namespace po {
 namespace {
 
+// Fixed-order tree sum of one value per thread over a 256-thread workgroup (every thread gets it).
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
 // Knot w_i of the clamped knot vector (multiplicity k at both ends, equidistant interior knots).
 __device__ __forceinline__ double knot(int i, int k, int ns, double wmin, double wmax) {
   if (i < k) return wmin;
@@ -335,6 +348,165 @@ __global__ void __launch_bounds__(256) k_samples(const PulseDev* __restrict__ de
   }
 }
 
+// ------------------------------------------------------------------------------------------
+// Adjoint of the synthesis (gradient of J and of the energy U with respect to the coefficients).
+// A_l(t) and E_l(t) are linear in the line values cE = E_j cos Phi_j, sE = E_j sin Phi_j of every
+// line: A_l(t) = -sum_j [cE_lj alpha_j(t) + sE_lj beta_j(t)] with alpha_j, beta_j the line terms
+// of field_at, E_l(t) = g(t)^2 sum_j [cE_lj cos(Om_j t) + sE_lj sin(Om_j t)].  Per line the kernel
+// forms G = sum_t gA(t) dA(t)/d(cE, sE) over the step midpoints and both ends, and
+// dU/d(cE, sE) = 2 dt sum_n E_l(t_n) g^2 (cos, sin)(Om_j t_n) over the midpoints.
+// ------------------------------------------------------------------------------------------
+
+// Unscaled line terms (alpha, beta) of line k at half-step index hh (as in field_at).
+__device__ __forceinline__ void line_terms(const PulseDev& d, int64_t k, int64_t hh, double& al, double& be,
+                                           double& co, double& si) {
+  const int64_t nt = d.nt, two_nt = 2 * nt, hm = hh - nt;
+  const double inv_nt = 1.0 / double(nt);
+  double s, c, sd, cd;
+  line_phase(k, hm, two_nt, inv_nt, &s, &c);
+  line_phase(1, hm, two_nt, inv_nt, &sd, &cd);
+  co = c;
+  si = s;
+  const double tmf = double(hh - two_nt) * (0.5 * d.dt);
+  const double sgn = (k & 1) ? -1.0 : 1.0;
+  const double cp = c * cd - s * sd, spp = s * cd + c * sd;
+  const double cm = cd * c + sd * s, smm = sd * c - cd * s;
+  const double om = double(k) * d.dw, wp = double(k + 1) * d.dw, wm = double(1 - k) * d.dw;
+  if (k == 0) {
+    al = 0.5 * tmf;
+    be = 0.0;
+  } else {
+    al = 0.5 * s / om;
+    be = 0.5 * (sgn - c) / om;
+  }
+  al += 0.25 * spp / wp;
+  be += 0.25 * (-cp - sgn) / wp;
+  if (k == 1) {
+    al += 0.25 * tmf;
+  } else {
+    al += 0.25 * smm / wm;
+    be += 0.25 * (cm + sgn) / wm;
+  }
+}
+
+// One workgroup per (line, pulse): out[line][8] = (dJ/dcE_x, dJ/dsE_x, dJ/dcE_y, dJ/dsE_y,
+// dU/dcE_x, dU/dsE_x, dU/dcE_y, dU/dsE_y) for the unscaled field, the J part contracted with gA.
+__global__ void __launch_bounds__(256) k_adjoint_lines(const PulseDev* __restrict__ desc, const double* __restrict__ gA,
+                                                       const double* __restrict__ gedge, const double* __restrict__ E,
+                                                       const double* __restrict__ scale, double* __restrict__ out) {
+  const PulseDev d = desc[blockIdx.y];
+  const int j = blockIdx.x;
+  if (j >= d.nlines) return;
+  const int64_t k = int64_t(d.nmin) + j;
+  const double inv_s = scale[blockIdx.y] != 0.0 ? 1.0 / scale[blockIdx.y] : 0.0;
+  const double2* g = reinterpret_cast<const double2*>(gA) + d.tab_off;
+  const double2* Et = reinterpret_cast<const double2*>(E) + d.tab_off;
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t n = threadIdx.x; n < int64_t(d.nt) + 2; n += blockDim.x) {
+    double2 gv;
+    int64_t hh;
+    const bool mid = n < d.nt;
+    if (mid) {
+      gv = g[n];
+      hh = 2 * n + 1;
+    } else {
+      gv = gedge ? reinterpret_cast<const double2*>(gedge)[2 * blockIdx.y + (n - d.nt)] : make_double2(0.0, 0.0);
+      hh = (n == d.nt) ? 0 : 2 * int64_t(d.nt);
+    }
+    double al, be, co, si;
+    line_terms(d, k, hh, al, be, co, si);
+    acc[0] -= gv.x * al;
+    acc[1] -= gv.x * be;
+    acc[2] -= gv.y * al;
+    acc[3] -= gv.y * be;
+    if (mid) {
+      const double gg = cospi(double(hh - d.nt) * (0.5 / double(d.nt)));
+      const double w = 2.0 * d.dt * gg * gg * inv_s;
+      const double2 ev = Et[n];
+      acc[4] += w * ev.x * co;
+      acc[5] += w * ev.x * si;
+      acc[6] += w * ev.y * co;
+      acc[7] += w * ev.y * si;
+    }
+  }
+  __shared__ double red[256];
+  for (int q = 0; q < 8; ++q) {
+    const double v = block_sum(acc[q], red);
+    if (threadIdx.x == 0) out[(d.spec_off / 4 + j) * 8 + q] = v;
+    __syncthreads();
+  }
+}
+
+// One workgroup per pulse.  Fixed-order sums of g.A over the table and of |E|^2 (the energy),
+// then one thread per coefficient (component l, kind, index i) chains the line sums through
+// cE = E cos Phi, sE = E sin Phi and the B-spline expansions of E and Phi = pi (c + 1).
+__global__ void __launch_bounds__(256) k_adjoint_coeff(const PulseDev* __restrict__ desc, const double* __restrict__ coeff,
+                                                       const double* __restrict__ lines, const double* __restrict__ gA,
+                                                       const double* __restrict__ gedge, const double* __restrict__ A,
+                                                       const double* __restrict__ Aedge, const double* __restrict__ E,
+                                                       const double* __restrict__ scale, double* __restrict__ grad,
+                                                       double* __restrict__ Uout, double* __restrict__ gU) {
+  const PulseDev d = desc[blockIdx.x];
+  __shared__ double red[256];
+  const double2* g = reinterpret_cast<const double2*>(gA) + d.tab_off;
+  const double2* At = reinterpret_cast<const double2*>(A) + d.tab_off;
+  const double2* Et = reinterpret_cast<const double2*>(E) + d.tab_off;
+  double ga = 0.0, uu = 0.0;
+  for (int64_t n = threadIdx.x; n < d.nt; n += blockDim.x) {
+    const double2 gv = g[n], av = At[n], ev = Et[n];
+    ga += gv.x * av.x + gv.y * av.y;
+    uu += ev.x * ev.x + ev.y * ev.y;
+  }
+  if (gedge && threadIdx.x < 2) {
+    const double2 gv = reinterpret_cast<const double2*>(gedge)[2 * blockIdx.x + threadIdx.x];
+    const double2 av = reinterpret_cast<const double2*>(Aedge)[2 * blockIdx.x + threadIdx.x];
+    ga += gv.x * av.x + gv.y * av.y;
+  }
+  const double gdotA = block_sum(ga, red);
+  __syncthreads();
+  const double U = block_sum(uu, red) * d.dt;  // energy of the scaled field (midpoint rule)
+  const double s = scale[blockIdx.x];
+  const bool energy = d.norm == PO_NORM_ENERGY;
+  const double Uraw = s != 0.0 ? U / (s * s) : 0.0;
+  if (threadIdx.x == 0 && Uout) Uout[blockIdx.x] = U;
+  const int t = threadIdx.x;
+  if (t >= 4 * d.ns) return;
+  const int l = t / (2 * d.ns), kind = (t / d.ns) % 2, i = t % d.ns;
+  const double* a = coeff + d.coeff_off;
+  const double* ln = lines + (d.spec_off / 4) * 8;
+  double b[2 * kMaxNs + 2];
+  double gj = 0.0, gu = 0.0;
+  for (int j = 0; j < d.nlines; ++j) {
+    const double w = fmin(fmax(double(d.nmin + j) * d.dw, d.wmin), d.wmax);
+    bspline_all(d.order, d.ns, d.wmin, d.wmax, w, b);
+    double Ev = 0.0, ph = 0.0;
+    for (int q = 0; q < d.ns; ++q) {
+      Ev += a[(l * 2 + 0) * d.ns + q] * b[q];
+      ph += M_PI * (a[(l * 2 + 1) * d.ns + q] + 1.0) * b[q];
+    }
+    double sp, cp;
+    sincos(ph, &sp, &cp);
+    const double Gc = ln[8 * j + 2 * l], Gs = ln[8 * j + 2 * l + 1];
+    const double Uc = ln[8 * j + 4 + 2 * l], Us = ln[8 * j + 4 + 2 * l + 1];
+    double dJ, dU;
+    if (kind == 0) {  // amplitude: d(cE, sE)/dE = (cos Phi, sin Phi)
+      dJ = Gc * cp + Gs * sp;
+      dU = Uc * cp + Us * sp;
+    } else {          // phase: d(cE, sE)/dPhi = (-E sin Phi, E cos Phi), dPhi/dc = pi b_i
+      dJ = M_PI * Ev * (Gs * cp - Gc * sp);
+      dU = M_PI * Ev * (Us * cp - Uc * sp);
+    }
+    gj += dJ * b[i];
+    gu += dU * b[i];
+  }
+  // A = s A_raw: NORM_NONE has s = 1; NORM_ENERGY has s = sqrt(U0 / U_raw), so
+  // dJ/dc = s dJ_raw/dc - (g.A) / (2 U_raw) dU_raw/dc and the energy stays U0.
+  double out = s * gj;
+  if (energy && Uraw > 0.0) out -= gdotA / (2.0 * Uraw) * gu;
+  grad[d.coeff_off + t] = out;
+  if (gU) gU[d.coeff_off + t] = energy ? 0.0 : gu;
+}
+
 }  // namespace
 
 po_status launch_synth(const Batch& b, const PulseDev* d_desc, const double* d_coeff, double* d_spec,
@@ -353,6 +525,19 @@ po_status launch_synth(const Batch& b, const PulseDev* d_desc, const double* d_c
   PO_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_tables, dim3((b.max_nt + 255) / 256, P), dim3(256), 0, s, d_desc, d_spec, d_scale_ws,
                      d_A, d_E, d_A_edge);
+  PO_HIP(hipGetLastError());
+  return PO_OK;
+}
+
+po_status launch_synth_adjoint(const Batch& b, const PulseDev* d_desc, const double* d_coeff, const double* d_gA,
+                               const double* d_gedge, const double* d_A, const double* d_A_edge, const double* d_E,
+                               const double* d_scale, double* d_lines, double* d_grad, double* d_U, double* d_gU,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_adjoint_lines, dim3(b.max_lines, b.n_pulses), dim3(256), 0, s, d_desc, d_gA, d_gedge, d_E,
+                     d_scale, d_lines);
+  PO_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_adjoint_coeff, dim3(b.n_pulses), dim3(256), 0, s, d_desc, d_coeff, d_lines, d_gA, d_gedge, d_A,
+                     d_A_edge, d_E, d_scale, d_grad, d_U, d_gU);
   PO_HIP(hipGetLastError());
   return PO_OK;
 }

@@ -127,3 +127,17 @@ def circular_pulse(seed=0, nt=20000, n_p=512):
     coeff[0, 1, 1, :] = -0.5
     return dict(name=f"circular_pulse_T5000_{n_p}x{n_p}", specs=[spec], grids=[sheet_grid(n_p, n_p, 3.0)],
                 coeff=coeff)
+
+
+def local_search(seed=0, starts=10, nt=4096, n=(64, 64, 16)):
+    """Multistart local search (Sec. IV A): `starts` random initial pulses, 2x(8+8) cubic
+    coefficients, band [0,1], T = 400, nt = 4096, no normalisation -- the energy
+    U = int |E|^2 dt is held at U_const = 0.1 by the augmented Lagrangian (about the energy of a
+    peak-0.1 field of this kind); 64x64x16 grid over px,py in [-2,2], pz in [-1,1].  Amplitude
+    coefficients are drawn uniform in [-0.005, 0.005] (peak |E| of order 0.1), phase coefficients
+    uniform in [-1, 1]; the search rescales the amplitudes onto the constraint before it starts."""
+    spec = pulse_spec(n_s=8, order=4, T=400.0, nt=nt, norm=NORM_NONE, norm_value=0.0)
+    coeff = draw_coeff(seed + 31337, starts, 8)
+    coeff[:, :, 0, :] *= 0.005
+    return dict(name=f"local_search_{starts}starts_{n[0]}x{n[1]}x{n[2]}_nt{nt}", specs=[spec] * starts,
+                grids=[box_grid(*n)] * starts, coeff=coeff, U_const=0.1)
