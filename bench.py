@@ -35,20 +35,30 @@ HERE_PROFILES = os.path.join(ROOT, "profiles")
 PLAN = dict(threads=256, modes_per_lane=1, persistent=1)
 
 
+EVOLVE_SOURCES = ("evolve.hip", "dirac.hpp", "reduce.hpp", "common.hpp")
+
+
+def evolve_sources_sha256():
+    """Hash of the sources the evolution kernel is compiled from."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in EVOLVE_SOURCES:
+        with open(os.path.join(ROOT, "paper_1704_08919_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def hbm_traffic_record():
     """HBM bytes per evolution call from the committed counter summary, if it was taken on the
-    evolution kernel source as it is now (else None)."""
-    import hashlib
+    evolution kernel's sources as they are now (else None)."""
     path = os.path.join(HERE_PROFILES, "k_evolve_hbm_traffic_de_generation.json")
-    src = os.path.join(ROOT, "paper_1704_08919_amd", "csrc", "evolve.hip")
     try:
         with open(path) as fh:
             rec = json.load(fh)
-        with open(src, "rb") as fh:
-            sha = hashlib.sha256(fh.read()).hexdigest()
+        sha = evolve_sources_sha256()
     except OSError:
         return None
-    return rec if rec.get("evolve_source_sha256") == sha else None
+    return rec if rec.get("evolve_sources_sha256") == sha else None
 
 
 def cpu_baseline(w, sample_modes, sample_pulses):
