@@ -492,7 +492,7 @@ po_status po_synth_gradient(int32_t n, const po_pulse_spec* specs, const double*
   PO_TRY(E.alloc(sizeof(double) * 2 * b.total_rows, s));
   PO_TRY(edge.alloc(sizeof(double) * 4 * n, s));
   PO_TRY(scl.alloc(sizeof(double) * n, s));
-  PO_TRY(lines.alloc(sizeof(double) * 2 * size_t(b.total_spec), s));
+  PO_TRY(lines.alloc(sizeof(double) * size_t(b.total_spec / 4) * 8 * kMaxNs, s));
   double *dA = static_cast<double*>(A.ptr), *dE = static_cast<double*>(E.ptr), *de = static_cast<double*>(edge.ptr);
   double* dscale = static_cast<double*>(scl.ptr);
   PO_TRY(synth_impl(n, specs, d_coeff, dA, dE, de, dscale, s, b, d_desc));
@@ -524,7 +524,7 @@ po_status po_evaluate_gradient(int32_t n, const po_pulse_spec* specs, const po_g
   PO_TRY(scl.alloc(sizeof(double) * n, s));
   PO_TRY(gA.alloc(sizeof(double) * 2 * b.total_rows, s));
   PO_TRY(gedge.alloc(sizeof(double) * 4 * n, s));
-  PO_TRY(lines.alloc(sizeof(double) * 2 * size_t(b.total_spec), s));
+  PO_TRY(lines.alloc(sizeof(double) * size_t(b.total_spec / 4) * 8 * kMaxNs, s));
   double *dA = static_cast<double*>(A.ptr), *dE = static_cast<double*>(E.ptr), *de = static_cast<double*>(edge.ptr);
   double *dscale = static_cast<double*>(scl.ptr), *dgA = static_cast<double*>(gA.ptr);
   double* dge = static_cast<double*>(gedge.ptr);

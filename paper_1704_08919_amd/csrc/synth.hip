@@ -389,11 +389,15 @@ __device__ __forceinline__ void line_terms(const PulseDev& d, int64_t k, int64_t
   }
 }
 
-// One workgroup per (line, pulse): out[line][8] = (dJ/dcE_x, dJ/dsE_x, dJ/dcE_y, dJ/dsE_y,
-// dU/dcE_x, dU/dsE_x, dU/dcE_y, dU/dsE_y) for the unscaled field, the J part contracted with gA.
-__global__ void __launch_bounds__(256) k_adjoint_lines(const PulseDev* __restrict__ desc, const double* __restrict__ gA,
-                                                       const double* __restrict__ gedge, const double* __restrict__ E,
-                                                       const double* __restrict__ scale, double* __restrict__ out) {
+// One workgroup per (line, pulse).  The eight line sums G = sum_t gA(t) dA(t)/d(cE, sE) per component
+// and dU/d(cE, sE) (unscaled field) are formed with fixed-order block sums; then thread c < 4 n_s
+// chains them through cE = E cos Phi, sE = E sin Phi and the B-spline expansions of E and
+// Phi = pi (c + 1) for coefficient c, writing out[line][c] (dJ) and out[line][4 n_s + c] (dU),
+// line slots of 8 kMaxNs doubles.
+__global__ void __launch_bounds__(256) k_adjoint_lines(const PulseDev* __restrict__ desc, const double* __restrict__ coeff,
+                                                       const double* __restrict__ gA, const double* __restrict__ gedge,
+                                                       const double* __restrict__ E, const double* __restrict__ scale,
+                                                       double* __restrict__ out) {
   const PulseDev d = desc[blockIdx.y];
   const int j = blockIdx.x;
   if (j >= d.nlines) return;
@@ -430,22 +434,44 @@ __global__ void __launch_bounds__(256) k_adjoint_lines(const PulseDev* __restric
     }
   }
   __shared__ double red[256];
-  for (int q = 0; q < 8; ++q) {
-    const double v = block_sum(acc[q], red);
-    if (threadIdx.x == 0) out[(d.spec_off / 4 + j) * 8 + q] = v;
-    __syncthreads();
+  double L[8];
+  for (int q = 0; q < 8; ++q) L[q] = block_sum(acc[q], red);
+  const int t = threadIdx.x;
+  if (t >= 4 * d.ns) return;
+  const int l = t / (2 * d.ns), kind = (t / d.ns) % 2, i = t % d.ns;
+  const double* a = coeff + d.coeff_off;
+  double b[2 * kMaxNs + 2];
+  const double w = fmin(fmax(double(k) * d.dw, d.wmin), d.wmax);
+  bspline_all(d.order, d.ns, d.wmin, d.wmax, w, b);
+  double Ev = 0.0, ph = 0.0;
+  for (int q = 0; q < d.ns; ++q) {
+    Ev += a[(l * 2 + 0) * d.ns + q] * b[q];
+    ph += M_PI * (a[(l * 2 + 1) * d.ns + q] + 1.0) * b[q];
   }
+  double sp, cp;
+  sincos(ph, &sp, &cp);
+  const double Gc = L[2 * l], Gs = L[2 * l + 1], Uc = L[4 + 2 * l], Us = L[4 + 2 * l + 1];
+  double dJ, dU;
+  if (kind == 0) {  // amplitude: d(cE, sE)/dE = (cos Phi, sin Phi)
+    dJ = Gc * cp + Gs * sp;
+    dU = Uc * cp + Us * sp;
+  } else {          // phase: d(cE, sE)/dPhi = (-E sin Phi, E cos Phi), dPhi/dc = pi b_i
+    dJ = M_PI * Ev * (Gs * cp - Gc * sp);
+    dU = M_PI * Ev * (Us * cp - Uc * sp);
+  }
+  double* o = out + (d.spec_off / 4 + j) * (8 * kMaxNs);
+  o[t] = dJ * b[i];
+  o[4 * d.ns + t] = dU * b[i];
 }
 
 // One workgroup per pulse.  Fixed-order sums of g.A over the table and of |E|^2 (the energy),
-// then one thread per coefficient (component l, kind, index i) chains the line sums through
-// cE = E cos Phi, sE = E sin Phi and the B-spline expansions of E and Phi = pi (c + 1).
-__global__ void __launch_bounds__(256) k_adjoint_coeff(const PulseDev* __restrict__ desc, const double* __restrict__ coeff,
-                                                       const double* __restrict__ lines, const double* __restrict__ gA,
-                                                       const double* __restrict__ gedge, const double* __restrict__ A,
-                                                       const double* __restrict__ Aedge, const double* __restrict__ E,
-                                                       const double* __restrict__ scale, double* __restrict__ grad,
-                                                       double* __restrict__ Uout, double* __restrict__ gU) {
+// then thread c < 4 n_s sums its line contributions in line order.
+__global__ void __launch_bounds__(256) k_adjoint_coeff(const PulseDev* __restrict__ desc, const double* __restrict__ lines,
+                                                       const double* __restrict__ gA, const double* __restrict__ gedge,
+                                                       const double* __restrict__ A, const double* __restrict__ Aedge,
+                                                       const double* __restrict__ E, const double* __restrict__ scale,
+                                                       double* __restrict__ grad, double* __restrict__ Uout,
+                                                       double* __restrict__ gU) {
   const PulseDev d = desc[blockIdx.x];
   __shared__ double red[256];
   const double2* g = reinterpret_cast<const double2*>(gA) + d.tab_off;
@@ -463,7 +489,6 @@ __global__ void __launch_bounds__(256) k_adjoint_coeff(const PulseDev* __restric
     ga += gv.x * av.x + gv.y * av.y;
   }
   const double gdotA = block_sum(ga, red);
-  __syncthreads();
   const double U = block_sum(uu, red) * d.dt;  // energy of the scaled field (midpoint rule)
   const double s = scale[blockIdx.x];
   const bool energy = d.norm == PO_NORM_ENERGY;
@@ -471,39 +496,17 @@ __global__ void __launch_bounds__(256) k_adjoint_coeff(const PulseDev* __restric
   if (threadIdx.x == 0 && Uout) Uout[blockIdx.x] = U;
   const int t = threadIdx.x;
   if (t >= 4 * d.ns) return;
-  const int l = t / (2 * d.ns), kind = (t / d.ns) % 2, i = t % d.ns;
-  const double* a = coeff + d.coeff_off;
-  const double* ln = lines + (d.spec_off / 4) * 8;
-  double b[2 * kMaxNs + 2];
+  const double* ln = lines + (d.spec_off / 4) * (8 * kMaxNs);
   double gj = 0.0, gu = 0.0;
   for (int j = 0; j < d.nlines; ++j) {
-    const double w = fmin(fmax(double(d.nmin + j) * d.dw, d.wmin), d.wmax);
-    bspline_all(d.order, d.ns, d.wmin, d.wmax, w, b);
-    double Ev = 0.0, ph = 0.0;
-    for (int q = 0; q < d.ns; ++q) {
-      Ev += a[(l * 2 + 0) * d.ns + q] * b[q];
-      ph += M_PI * (a[(l * 2 + 1) * d.ns + q] + 1.0) * b[q];
-    }
-    double sp, cp;
-    sincos(ph, &sp, &cp);
-    const double Gc = ln[8 * j + 2 * l], Gs = ln[8 * j + 2 * l + 1];
-    const double Uc = ln[8 * j + 4 + 2 * l], Us = ln[8 * j + 4 + 2 * l + 1];
-    double dJ, dU;
-    if (kind == 0) {  // amplitude: d(cE, sE)/dE = (cos Phi, sin Phi)
-      dJ = Gc * cp + Gs * sp;
-      dU = Uc * cp + Us * sp;
-    } else {          // phase: d(cE, sE)/dPhi = (-E sin Phi, E cos Phi), dPhi/dc = pi b_i
-      dJ = M_PI * Ev * (Gs * cp - Gc * sp);
-      dU = M_PI * Ev * (Us * cp - Uc * sp);
-    }
-    gj += dJ * b[i];
-    gu += dU * b[i];
+    gj += ln[int64_t(j) * (8 * kMaxNs) + t];
+    gu += ln[int64_t(j) * (8 * kMaxNs) + 4 * d.ns + t];
   }
   // A = s A_raw: NORM_NONE has s = 1; NORM_ENERGY has s = sqrt(U0 / U_raw), so
   // dJ/dc = s dJ_raw/dc - (g.A) / (2 U_raw) dU_raw/dc and the energy stays U0.
-  double out = s * gj;
-  if (energy && Uraw > 0.0) out -= gdotA / (2.0 * Uraw) * gu;
-  grad[d.coeff_off + t] = out;
+  double outv = s * gj;
+  if (energy && Uraw > 0.0) outv -= gdotA / (2.0 * Uraw) * gu;
+  grad[d.coeff_off + t] = outv;
   if (gU) gU[d.coeff_off + t] = energy ? 0.0 : gu;
 }
 
@@ -533,11 +536,11 @@ po_status launch_synth_adjoint(const Batch& b, const PulseDev* d_desc, const dou
                                const double* d_gedge, const double* d_A, const double* d_A_edge, const double* d_E,
                                const double* d_scale, double* d_lines, double* d_grad, double* d_U, double* d_gU,
                                hipStream_t s) {
-  hipLaunchKernelGGL(k_adjoint_lines, dim3(b.max_lines, b.n_pulses), dim3(256), 0, s, d_desc, d_gA, d_gedge, d_E,
-                     d_scale, d_lines);
+  hipLaunchKernelGGL(k_adjoint_lines, dim3(b.max_lines, b.n_pulses), dim3(256), 0, s, d_desc, d_coeff, d_gA, d_gedge,
+                     d_E, d_scale, d_lines);
   PO_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_adjoint_coeff, dim3(b.n_pulses), dim3(256), 0, s, d_desc, d_coeff, d_lines, d_gA, d_gedge, d_A,
-                     d_A_edge, d_E, d_scale, d_grad, d_U, d_gU);
+  hipLaunchKernelGGL(k_adjoint_coeff, dim3(b.n_pulses), dim3(256), 0, s, d_desc, d_lines, d_gA, d_gedge, d_A, d_A_edge,
+                     d_E, d_scale, d_grad, d_U, d_gU);
   PO_HIP(hipGetLastError());
   return PO_OK;
 }
