@@ -14,13 +14,19 @@
 // perturbation of the block eigenvectors, energies -+ omega):
 //     d|->  = -|+><+|dh|->/(2 omega),   d<+|psi> = <+|dh|-><-|psi>/(2 omega),   dP = -dA.
 //
-// One workgroup of 256 lanes per 256-mode item, one mode per lane.  Forward: the exact C, S form
-// (degree-7 series with the pulse's angle halvings), states unit-normalised at t_f.  Backward:
-// the table is staged through LDS chunk by chunk in reverse; each step applies U^+ to psi and chi
-// and forms the two derivative terms; their sum over the item's modes is taken per step, a fixed
-// butterfly per wave and then the four waves in order, and written as item partials
-// [item][n][2]; a second kernel sums the items of each pulse in order.  So the gradient, like J,
-// does not depend on scheduling.
+// Since f_s is the same with chi_s replaced by alpha_s chi_s, the backward sweep carries
+// chi'_s = alpha_s chi_s and each term is 2 Re <chi'_{n+1}| dU/dq_j |psi_n>, of which only
+// Re <chi'|psi> and Im <chi'|tau_k|psi> enter.
+//
+// One workgroup of 256 lanes per 256-mode item, one mode per lane.  Forward: the evolution's own
+// step (tangent form or C, S with the pulse's angle halvings), states unit-normalised per block at
+// t_f.  Backward: the table is staged through LDS chunk by chunk in reverse; each step applies U^+
+// (exact C, S form) to psi and chi' and forms the two derivative terms.  Their sum over the item's
+// modes is taken per step in a fixed order: each lane stores its terms for 8 steps in LDS, the wave
+// reads them back transposed (lane (j, p) adds the lanes p, p + 8, ..., p + 56 of step j), pairs
+// up the 8 lanes of a step (DPP), and the four waves are added in order; the results are written
+// as item partials [item][n][2], and a second kernel sums the items of each pulse in order.  So
+// the gradient, like J, does not depend on scheduling.
 #include "dirac.hpp"
 #include "reduce.hpp"
 
@@ -29,25 +35,31 @@
 namespace po {
 namespace {
 
-// Maclaurin coefficients of D(x) = (cos sqrt x - sin sqrt x / sqrt x) / x
-//   = sum_k (-1)^(k+1) 2 (k+1) x^k / (2k+3)!   (-1/3 + x/30 - x^2/840 + ...).
-constexpr double dser_coef(int k) { return (k % 2 ? 1.0 : -1.0) * 2.0 * double(k + 1) / factorial(2 * k + 3); }
-
+// C = cos sqrt x and S = sin sqrt x / sqrt x by their degree-7 series (x <= 0.3612 keeps both
+// remainders below 2^-56), and D = (C - S)/x = C1 - S1, where C = 1 + x C1 and S = 1 + x S1 are the
+// last Horner steps (no cancellation: C1 ~ -1/2, S1 ~ -1/6; remainder of D below 2^-54).
 template <int K>
-__device__ __forceinline__ void horner_d(double x, double& D) {
-  constexpr double c = dser_coef(K);
-  D = fma(D, x, c);
-  if constexpr (K > 0) horner_d<K - 1>(x, D);
+__device__ __forceinline__ void horner_cs1(double x, double& C, double& S) {
+  constexpr double cc = cos_coef(K), sc = sinc_coef(K);
+  C = fma(C, x, cc);
+  S = fma(S, x, sc);
+  if constexpr (K > 1) horner_cs1<K - 1>(x, C, S);
 }
 
-// C, S and D at x = |q|^2: degree-7 series (x / 4^h <= 0.3612 keeps every remainder below
-// 2^-56), h double-angle steps for C and S; D = (C - S)/x when halved (x > 0.36: no cancellation).
+__device__ __forceinline__ void csd_series(double x, double& C, double& S, double& D) {
+  constexpr double c7 = cos_coef(7), s7 = sinc_coef(7);
+  double C1 = c7, S1 = s7;
+  horner_cs1<6>(x, C1, S1);
+  D = C1 - S1;
+  C = fma(C1, x, 1.0);
+  S = fma(S1, x, 1.0);
+}
+
+// The same after h halvings of the angle (x / 4^h in the series range, h double-angle steps for C
+// and S); D = (C - S)/x has no cancellation there (x > 0.36).
 __device__ __forceinline__ void csd(double x, int h, double inv4h, double& C, double& S, double& D) {
   if (h == 0) {
-    cos_sinc<7>(x, C, S);
-    constexpr double d7 = dser_coef(7);
-    D = d7;
-    horner_d<6>(x, D);
+    csd_series(x, C, S, D);
   } else {
     cos_sinc_halved(x, h, inv4h, C, S);
     D = (C - S) / x;
@@ -58,31 +70,15 @@ struct Blk {
   double ar, ai, br, bi;
 };
 
-// psi <- U^+ psi = (C + i S q.tau) psi for one block, q = (qx, qy, qz) the block's vector.
-__device__ __forceinline__ void back_rotate(Blk& v, double C, double S, double qx, double qy, double qz) {
-  rotate_block(v.ar, v.ai, v.br, v.bi, C, -(S * qx), -(S * qy), -(S * qz));
+// Block s (0: s = +1, 1: s = -1) of a two-block state.
+__device__ __forceinline__ Blk block_of(const State& v, int s) {
+  return s == 0 ? Blk{v.ar, v.ai, v.br, v.bi} : Blk{v.cr, v.ci, v.dr, v.di};
 }
 
-// 2 Re[conj(alpha) <chi| dU/dq_j |psi>] for j = x, y of one block.
-__device__ __forceinline__ void block_terms(const Blk& c, const Blk& p, double ar_, double ai_, double C, double S,
-                                            double D, double qx, double qy, double qz, double& gx, double& gy) {
-  (void)C;
-  // conj(c1) p1, conj(c2) p2, conj(c1) p2, conj(c2) p1
-  const double u11r = fma(c.ar, p.ar, c.ai * p.ai), u11i = fma(c.ar, p.ai, -(c.ai * p.ar));
-  const double u22r = fma(c.br, p.br, c.bi * p.bi), u22i = fma(c.br, p.bi, -(c.bi * p.br));
-  const double u12r = fma(c.ar, p.br, c.ai * p.bi), u12i = fma(c.ar, p.bi, -(c.ai * p.br));
-  const double u21r = fma(c.br, p.ar, c.bi * p.ai), u21i = fma(c.br, p.ai, -(c.bi * p.ar));
-  const double a_r = u11r + u22r, a_i = u11i + u22i;              // <chi|psi>
-  const double tz_r = u11r - u22r, tz_i = u11i - u22i;            // <chi|tau_z|psi>
-  const double tx_r = u12r + u21r, tx_i = u12i + u21i;            // <chi|tau_x|psi>
-  const double ty_r = -(u21i - u12i), ty_i = u21r - u12r;         // i (conj(c2) p1 - conj(c1) p2)
-  const double b_r = fma(qx, tx_r, fma(qy, ty_r, qz * tz_r));     // <chi|q.tau|psi>
-  const double b_i = fma(qx, tx_i, fma(qy, ty_i, qz * tz_i));
-  const double w_r = fma(-S, a_r, D * b_i), w_i = fma(-S, a_i, -(D * b_r));  // -S a - i D b
-  const double dx_r = fma(qx, w_r, S * tx_i), dx_i = fma(qx, w_i, -(S * tx_r));
-  const double dy_r = fma(qy, w_r, S * ty_i), dy_i = fma(qy, w_i, -(S * ty_r));
-  gx = 2.0 * fma(ar_, dx_r, ai_ * dx_i);
-  gy = 2.0 * fma(ar_, dy_r, ai_ * dy_i);
+// z b for a complex scalar z and a block vector b.
+__device__ __forceinline__ Blk cscale(double zr, double zi, const Blk& b) {
+  return Blk{fma(zr, b.ar, -(zi * b.ai)), fma(zr, b.ai, zi * b.ar), fma(zr, b.br, -(zi * b.bi)),
+             fma(zr, b.bi, zi * b.br)};
 }
 
 // Unit eigenvectors of h_s(P) = P_x tau_x + s P_y tau_y + e tau_z: |+> = (w + e, P_x + i s P_y)/N,
@@ -113,6 +109,108 @@ __device__ __forceinline__ void tau_xy(const Blk& x, const Blk& y, double s, dou
   yi = s * (b_r - a_r);
 }
 
+// Re <chi| dU/dq_j |psi> for j = x, y of one block, chi = (c1, c2) already carrying the factor
+// alpha, psi = (p1, p2), q = (qx, qy, qz) the block's vector.  Only four real numbers of the
+// block products enter: a = Re <chi|psi> and the imaginary parts of t_k = <chi|tau_k|psi>;
+//   Re[q_j (-S a - i D q.t) - i S t_j] = q_j (D q.Im t - S Re a) + S Im t_j.
+__device__ __forceinline__ void block_grad(double c1r, double c1i, double c2r, double c2i, double p1r, double p1i,
+                                           double p2r, double p2i, double S, double D, double qx, double qy,
+                                           double qz, double& gx, double& gy) {
+  const double a = fma(c2i, p2i, fma(c2r, p2r, fma(c1i, p1i, c1r * p1r)));
+  const double tx = fma(-c2i, p1r, fma(c2r, p1i, fma(-c1i, p2r, c1r * p2i)));   // Im(c1* p2 + c2* p1)
+  const double ty = fma(-c1i, p2i, fma(-c1r, p2r, fma(c2i, p1i, c2r * p1r)));   // Re(c2* p1 - c1* p2)
+  const double tz = fma(c2i, p2r, fma(-c2r, p2i, fma(-c1i, p1r, c1r * p1i)));   // Im(c1* p1 - c2* p2)
+  const double b = fma(qz, tz, fma(qy, ty, qx * tx));
+  const double w = fma(D, b, -(S * a));
+  gx = fma(qx, w, S * tx);
+  gy = fma(qy, w, S * ty);
+}
+
+// One backward step n: psi <- U_n^+ psi (psi_{n+1} -> psi_n), the derivative terms with chi_{n+1},
+// then chi <- U_n^+ chi.  Returns (sum_s Re<chi|dU/dq_x|psi>, sum_s s Re<chi|dU/dq_y|psi>).
+// SERIES: the step angle is within the degree-7 range (no halving, D from its own series).
+template <bool SERIES>
+__device__ __forceinline__ double2 back_step(State& psi, State& chi, double2 r, double pxdt, double pydt, double qz,
+                                             double qz2, int h, double inv4h) {
+  const double qx = pxdt + r.x, qy = pydt + r.y;
+  const double x = fma(qx, qx, fma(qy, qy, qz2));
+  double C, S, D;
+  if constexpr (SERIES) {
+    csd_series(x, C, S, D);
+  } else {
+    csd(x, h, inv4h, C, S, D);
+  }
+  rotate(psi, C, -S, qx, qy, qz);
+  double gx0, gy0, gx1, gy1;
+  block_grad(chi.ar, chi.ai, chi.br, chi.bi, psi.ar, psi.ai, psi.br, psi.bi, S, D, qx, qy, qz, gx0, gy0);
+  block_grad(chi.cr, chi.ci, chi.dr, chi.di, psi.cr, psi.ci, psi.dr, psi.di, S, D, qx, -qy, qz, gx1, gy1);
+  rotate(chi, C, -S, qx, qy, qz);
+  return make_double2(gx0 + gx1, gy0 - gy1);
+}
+
+// Forward step of the evolution in the form the pulse's series choice selects.
+template <int MODE>
+__device__ __forceinline__ void fwd_step(State& v, double2 rec, double pxdt, double pydt, double qz, double qz2, int h,
+                                         double inv4h) {
+  if constexpr (MODE < kHalvingMode) step_tan<kTanDegree[MODE]>(v, rec, pxdt, pydt, qz, qz2);
+  else step_halving(v, rec, pxdt, pydt, qz, qz2, h, inv4h);
+}
+
+// Lane-to-lane moves inside rows of 16 (DPP): pairs (l, l^1), (l, l^2), l <-> 7 - l within 8 lanes and
+// l <-> 15 - l within 16 lanes.
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_get(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over each aligned group of L lanes (L = 8 or 16); every lane of a group gets the same value.
+template <int L>
+__device__ __forceinline__ double group_sum(double v) {
+  v += dpp_get<kDppXor1>(v);
+  v += dpp_get<kDppXor2>(v);
+  v += dpp_get<kDppHalfMirror>(v);
+  if constexpr (L == 16) v += dpp_get<kDppMirror>(v);
+  return v;
+}
+
+// Per-step sums over the 64 lanes of a wave for kGroup steps at once: each lane has written its
+// (gx, gy) of step j to buf[j][lane]; lane (j, p) (j = lane / L, p = lane % L, L = 64 / kGroup)
+// adds the lanes p, p + L, ... in order, then the L lanes of its step pair up.  Lane p = 0 of step
+// j returns the wave's sum of step j.
+constexpr int kGroup = 8;
+constexpr int kLanesPerStep = 64 / kGroup;
+
+__device__ __forceinline__ double2 group_reduce(const double2 (*buf)[64], int lane) {
+  const int j = lane / kLanesPerStep, p = lane % kLanesPerStep;
+  double2 v = buf[j][p];
+#pragma unroll
+  for (int i = 1; i < kGroup; ++i) {
+    const double2 u = buf[j][i * kLanesPerStep + p];
+    v.x += u.x;
+    v.y += u.y;
+  }
+  return make_double2(group_sum<kLanesPerStep>(v.x), group_sum<kLanesPerStep>(v.y));
+}
+
+// Reduces a group of cnt steps (rows 0..cnt-1 of buf, steps top, top - 1, ...) and stores the
+// wave's step sums in red[top - j].  The wave reads what its own lanes wrote: the fences complete
+// the stores before the loads and the loads before the next group's stores (no other wave uses buf).
+__device__ __forceinline__ void group_store(double2 (*buf)[64], double2* red, int lane, int top, int cnt) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  const double2 v = group_reduce(buf, lane);
+  const int j = lane / kLanesPerStep;
+  if (lane % kLanesPerStep == 0 && j < cnt) red[top - j] = v;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 struct GradArgs {
   const PulseDev* desc;
   int n_pulses;
@@ -127,11 +225,12 @@ struct GradArgs {
 
 constexpr int kWaves = kItem / 64;
 
-__global__ void __launch_bounds__(kItem) __attribute__((amdgpu_waves_per_eu(3))) k_yield_grad(GradArgs a) {
-  __shared__ double2 tab[kChunk];
-  __shared__ double2 red[kWaves][kChunk];
-  const int item = xcd_item(blockIdx.x, gridDim.x);
-  const int pi = find_pulse_item(a.desc, a.n_pulses, item);
+// LDS: tab[kChunk] (-A dt of the chunk), red[kWaves][kChunk] (per-wave step sums of the chunk),
+// bufs[kWaves][kGroup][64] (lane values of kGroup steps, per wave); separate arrays, so the
+// compiler sees that the table reads do not depend on the buf stores.
+template <int MODE>
+__device__ __forceinline__ void grad_item(const GradArgs& a, int item, int pi, double2* tab, double2 (*red)[kChunk],
+                                          double2 (*bufs)[kGroup][64]) {
   const PulseDev& d = a.desc[pi];
   const int nt = d.nt;
   const double dt = d.dt;
@@ -151,16 +250,10 @@ __global__ void __launch_bounds__(kItem) __attribute__((amdgpu_waves_per_eu(3)))
   const double e = sqrt(fma(pz, pz, 1.0));
   const double pxdt = px * dt, pydt = py * dt, qz = e * dt, qz2 = qz * qz;
 
-  // forward: psi_s from |-_s(P_in)>
-  Blk psi[2];
-  {
-    Blk up, dn;
-    double w;
-    eig_pm(px - ain.x, py - ain.y, e, 1.0, up, dn, w);
-    psi[0] = dn;
-    eig_pm(px - ain.x, py - ain.y, e, -1.0, up, dn, w);
-    psi[1] = dn;
-  }
+  // forward: psi_s from |-_s(P_in)>, in the evolution's own step form (the tangent form drops the
+  // common factor C of every step; the blocks are normalised at t_f)
+  State psi;
+  init_state(psi, px - ain.x, py - ain.y, e);
   const int nchunks = (nt + kChunk - 1) / kChunk;
   for (int c = 0; c < nchunks; ++c) {
     const int n0 = c * kChunk, len = min(kChunk, nt - n0);
@@ -170,22 +263,17 @@ __global__ void __launch_bounds__(kItem) __attribute__((amdgpu_waves_per_eu(3)))
       tab[threadIdx.x] = make_double2(-t.x * dt, -t.y * dt);
     }
     __syncthreads();
-#pragma unroll 1
-    for (int k = 0; k < len; ++k) {
-      const double2 r = tab[k];
-      const double qx = pxdt + r.x, qy = pydt + r.y;
-      const double x = fma(qx, qx, fma(qy, qy, qz2));
-      double C, S;
-      if (h == 0) cos_sinc<7>(x, C, S);
-      else cos_sinc_halved(x, h, inv4h, C, S);
-      rotate_block(psi[0].ar, psi[0].ai, psi[0].br, psi[0].bi, C, S * qx, S * qy, S * qz);
-      rotate_block(psi[1].ar, psi[1].ai, psi[1].br, psi[1].bi, C, S * qx, -(S * qy), S * qz);
+    if (len == kChunk) {
+#pragma unroll 4
+      for (int k = 0; k < kChunk; ++k) fwd_step<MODE>(psi, tab[k], pxdt, pydt, qz, qz2, h, inv4h);
+    } else {
+      for (int k = 0; k < len; ++k) fwd_step<MODE>(psi, tab[k], pxdt, pydt, qz, qz2, h, inv4h);
     }
+    if constexpr (MODE < kHalvingMode) renormalise(psi);
   }
 
-  // t_f: normalise, alpha_s = <+_s(P_out)|psi_s>, final-state terms
-  Blk chi[2];
-  double al_r[2], al_i[2];
+  // t_f: normalise each block, alpha_s = <+_s(P_out)|psi_s>, final-state terms; chi_s = alpha_s |+_s>
+  State chi;
   double g_out_x = 0.0, g_out_y = 0.0, f = 0.0;
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
@@ -193,28 +281,39 @@ __global__ void __launch_bounds__(kItem) __attribute__((amdgpu_waves_per_eu(3)))
     Blk up_out, dn_out;
     double w_out;
     eig_pm(px - aout.x, py - aout.y, e, sg, up_out, dn_out, w_out);
+    Blk p = block_of(psi, s);
     double nr, ni;
-    inner(psi[s], psi[s], nr, ni);
+    inner(p, p, nr, ni);
     const double inv = 1.0 / sqrt(nr);
-    psi[s] = Blk{psi[s].ar * inv, psi[s].ai * inv, psi[s].br * inv, psi[s].bi * inv};
-    inner(up_out, psi[s], al_r[s], al_i[s]);
-    if (!active) al_r[s] = al_i[s] = 0.0;
-    f += fma(al_r[s], al_r[s], al_i[s] * al_i[s]);
+    p = Blk{p.ar * inv, p.ai * inv, p.br * inv, p.bi * inv};
+    double al_r, al_i;
+    inner(up_out, p, al_r, al_i);
+    if (!active) al_r = al_i = 0.0;
+    f += fma(al_r, al_r, al_i * al_i);
     // d alpha = <+|dh|-><-|psi>/(2 w), dh = tau_x dP_x + s tau_y dP_y, dP = -dA(t_f)
     double xr, xi, yr, yi, mr, mi;
     tau_xy(up_out, dn_out, sg, xr, xi, yr, yi);
-    inner(dn_out, psi[s], mr, mi);
+    inner(dn_out, p, mr, mi);
     const double k = -1.0 / (2.0 * w_out);
     // Re[conj(alpha) (t m)]
     const double tmx_r = fma(xr, mr, -(xi * mi)), tmx_i = fma(xr, mi, xi * mr);
     const double tmy_r = fma(yr, mr, -(yi * mi)), tmy_i = fma(yr, mi, yi * mr);
-    g_out_x += 2.0 * k * fma(al_r[s], tmx_r, al_i[s] * tmx_i);
-    g_out_y += 2.0 * k * fma(al_r[s], tmy_r, al_i[s] * tmy_i);
-    chi[s] = up_out;
+    g_out_x += 2.0 * k * fma(al_r, tmx_r, al_i * tmx_i);
+    g_out_y += 2.0 * k * fma(al_r, tmy_r, al_i * tmy_i);
+    const Blk cb = cscale(al_r, al_i, up_out);
+    if (s == 0) {
+      psi.ar = p.ar; psi.ai = p.ai; psi.br = p.br; psi.bi = p.bi;
+      chi.ar = cb.ar; chi.ai = cb.ai; chi.br = cb.br; chi.bi = cb.bi;
+    } else {
+      psi.cr = p.ar; psi.ci = p.ai; psi.dr = p.br; psi.di = p.bi;
+      chi.cr = cb.ar; chi.ci = cb.ai; chi.dr = cb.br; chi.di = cb.bi;
+    }
   }
 
-  // backward over the chunks in reverse
+  // backward over the chunks in reverse, kGroup steps at a time (the last group of a chunk may be short)
+  constexpr bool kSeries = MODE < kHalvingMode;
   double* part = a.part + a.goff[pi] + int64_t(li) * nt * 2;
+  double2 (*buf)[64] = bufs[wave];
   for (int c = nchunks - 1; c >= 0; --c) {
     const int n0 = c * kChunk, len = min(kChunk, nt - n0);
     __syncthreads();
@@ -223,27 +322,20 @@ __global__ void __launch_bounds__(kItem) __attribute__((amdgpu_waves_per_eu(3)))
       tab[threadIdx.x] = make_double2(-t.x * dt, -t.y * dt);
     }
     __syncthreads();
+    // a short group first (len not a multiple of kGroup), then full groups
+    int top = len - 1;
+    const int r = len % kGroup;
+    if (r != 0) {
 #pragma unroll 1
-    for (int k = len - 1; k >= 0; --k) {
-      const double2 r = tab[k];
-      const double qx = pxdt + r.x, qy = pydt + r.y;
-      const double x = fma(qx, qx, fma(qy, qy, qz2));
-      double C, S, D;
-      csd(x, h, inv4h, C, S, D);
-      double gx = 0.0, gy = 0.0;
-    #pragma unroll
-  for (int s = 0; s < 2; ++s) {
-        const double qys = s == 0 ? qy : -qy;
-        back_rotate(psi[s], C, S, qx, qys, qz);  // psi_n
-        double bx, by;
-        block_terms(chi[s], psi[s], al_r[s], al_i[s], C, S, D, qx, qys, qz, bx, by);
-        gx += bx;
-        gy += s == 0 ? by : -by;  // dq_y/dA_y = -s dt
-        back_rotate(chi[s], C, S, qx, qys, qz);  // chi_n
-      }
-      gx = wave_sum(-dt * gx);
-      gy = wave_sum(-dt * gy);
-      if (lane == 0) red[wave][k] = make_double2(gx, gy);
+      for (int j = 0; j < r; ++j) buf[j][lane] = back_step<kSeries>(psi, chi, tab[top - j], pxdt, pydt, qz, qz2, h, inv4h);
+      group_store(buf, red[wave], lane, top, r);
+      top -= r;
+    }
+    for (; top >= 0; top -= kGroup) {
+#pragma unroll
+      for (int j = 0; j < kGroup; ++j)
+        buf[j][lane] = back_step<kSeries>(psi, chi, tab[top - j], pxdt, pydt, qz, qz2, h, inv4h);
+      group_store(buf, red[wave], lane, top, kGroup);
     }
     __syncthreads();
     if (int(threadIdx.x) < len) {
@@ -257,7 +349,7 @@ __global__ void __launch_bounds__(kItem) __attribute__((amdgpu_waves_per_eu(3)))
     }
   }
 
-  // t_i: d|-> = -|+><+|dh|->/(2 w), dP = -dA(t_i); chi holds U^+ ... |+_out> = chi_0
+  // t_i: d|-> = -|+><+|dh|->/(2 w), dP = -dA(t_i); chi holds U^+ ... alpha |+_out> = alpha chi_0
   double g_in_x = 0.0, g_in_y = 0.0;
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
@@ -267,12 +359,10 @@ __global__ void __launch_bounds__(kItem) __attribute__((amdgpu_waves_per_eu(3)))
     eig_pm(px - ain.x, py - ain.y, e, sg, up_in, dn_in, w_in);
     double xr, xi, yr, yi, cr, ci;
     tau_xy(up_in, dn_in, sg, xr, xi, yr, yi);
-    inner(chi[s], up_in, cr, ci);
+    inner(block_of(chi, s), up_in, cr, ci);
     const double k = 1.0 / (2.0 * w_in);  // (-1/(2w)) * (dP/dA = -1)
-    const double tmx_r = fma(cr, xr, -(ci * xi)), tmx_i = fma(cr, xi, ci * xr);
-    const double tmy_r = fma(cr, yr, -(ci * yi)), tmy_i = fma(cr, yi, ci * yr);
-    g_in_x += 2.0 * k * fma(al_r[s], tmx_r, al_i[s] * tmx_i);
-    g_in_y += 2.0 * k * fma(al_r[s], tmy_r, al_i[s] * tmy_i);
+    g_in_x += 2.0 * k * fma(cr, xr, -(ci * xi));
+    g_in_y += 2.0 * k * fma(cr, yr, -(ci * yi));
   }
   const double e4[4] = {g_in_x, g_in_y, g_out_x, g_out_y};
   __syncthreads();
@@ -290,7 +380,23 @@ __global__ void __launch_bounds__(kItem) __attribute__((amdgpu_waves_per_eu(3)))
   if (a.units) write_unit(d, a.units, m, nmodes, active ? f : 0.0);
 }
 
-// dJ/dA[n] = dV sum over the pulse's items (in order) of the partials; one thread per (n, component).
+__global__ void __launch_bounds__(kItem) __attribute__((amdgpu_waves_per_eu(3))) k_yield_grad(GradArgs a) {
+  __shared__ double2 tab[kChunk];
+  __shared__ double2 red[kWaves][kChunk];
+  __shared__ double2 bufs[kWaves][kGroup][64];
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  const int pi = find_pulse_item(a.desc, a.n_pulses, item);
+  switch (a.sel[pi].x) {
+    case 0: grad_item<0>(a, item, pi, tab, red, bufs); break;
+    case 1: grad_item<1>(a, item, pi, tab, red, bufs); break;
+    case 2: grad_item<2>(a, item, pi, tab, red, bufs); break;
+    case 3: grad_item<3>(a, item, pi, tab, red, bufs); break;
+    default: grad_item<kHalvingMode>(a, item, pi, tab, red, bufs); break;
+  }
+}
+
+// dJ/dA[n] = -2 dt dV sum over the pulse's items (in order) of the partials (the edge partials carry
+// their factors); one thread per (n, component).
 __global__ void __launch_bounds__(256) k_grad_reduce(const PulseDev* __restrict__ desc, const int64_t* __restrict__ goff,
                                                      const double* __restrict__ part, const double* __restrict__ epart,
                                                      double* __restrict__ gA, double* __restrict__ gedge) {
@@ -301,7 +407,7 @@ __global__ void __launch_bounds__(256) k_grad_reduce(const PulseDev* __restrict_
     const double* p = part + goff[blockIdx.y];
     double v = 0.0;
     for (int i = 0; i < d.nitems; ++i) v += p[int64_t(i) * per + e];
-    gA[2 * d.tab_off + e] = v * d.dv;
+    gA[2 * d.tab_off + e] = v * (-2.0 * d.dt) * d.dv;  // dq_x/dA_x = -dt; the factor 2 of 2 Re[...]
   }
   if (gedge && blockIdx.x == 0 && threadIdx.x < 4) {
     double v = 0.0;
