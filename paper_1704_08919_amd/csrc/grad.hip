@@ -148,6 +148,78 @@ __device__ __forceinline__ double2 back_step(State& psi, State& chi, double2 r, 
   return make_double2(gx0 + gx1, gy0 - gy1);
 }
 
+// Tangent form of the backward step (steps within the T-series range).  With U = C (1 - i T Q)
+// and S = C T, D = (C - S)/x = -C R where R = (T - 1)/x, the step applies (1 + i T Q) to psi and
+// chi' and leaves out the factors C: psi_n = sigma_n psi~_n and chi'_{n+1} = sigma_{n+1} chi~_{n+1}
+// with sigma_n = C_n sigma_{n+1}, so the term of step n is Sigma_n = sigma_n^2 = C_n^2 Sigma_{n+1}
+// times the same expression in psi~, chi~ with (S, D) -> (T, -R).  C^2 = cos^2 sqrt x comes from its
+// own series, R from the T series before its last Horner step (T = 1 + x R).
+// cos^2 sqrt x = 1 + sum_{k >= 1} (-1)^k 2^(2k-1) x^k / (2k)!, alternating with decreasing terms;
+// degree M per T variant keeps the remainder below 2^-59 up to that variant's largest x.
+constexpr double pow2i(int n) { return n == 0 ? 1.0 : 2.0 * pow2i(n - 1); }
+constexpr double cos2_coef(int k) { return k == 0 ? 1.0 : (k % 2 ? -1.0 : 1.0) * pow2i(2 * k - 1) / factorial(2 * k); }
+constexpr int kCos2Degree[kNumTan] = {5, 6, 7, 8};
+
+template <int K>
+__device__ __forceinline__ void horner_cos2(double x, double& c) {
+  constexpr double ck = cos2_coef(K);
+  c = fma(c, x, ck);
+  if constexpr (K > 0) horner_cos2<K - 1>(x, c);
+}
+
+template <int M>
+__device__ __forceinline__ double cos2_series(double x) {
+  constexpr double cm = cos2_coef(M);
+  double c = cm;
+  horner_cos2<M - 1>(x, c);
+  return c;
+}
+
+// Horner steps K..1 of the T series (the step with coefficient 1 left out).
+template <int K>
+__device__ __forceinline__ void horner_tan1(double x, double& R) {
+  constexpr double c = tan_coef(K);
+  R = fma(R, x, c);
+  if constexpr (K > 1) horner_tan1<K - 1>(x, R);
+}
+
+template <int MODE>
+__device__ __forceinline__ double2 back_step_tan(State& psi, State& chi, double2 r, double pxdt, double pydt,
+                                                 double qz, double qz2, double& sig) {
+  constexpr int N = kTanDegree[MODE], M = kCos2Degree[MODE];
+  const double qx = pxdt + r.x, qy = pydt + r.y;
+  const double x = fma(qx, qx, fma(qy, qy, qz2));
+  constexpr double cn = tan_coef(N);
+  double R = cn;
+  horner_tan1<N - 1>(x, R);
+  const double T = fma(R, x, 1.0);
+  const double c2 = cos2_series<M>(x);
+  rotate_tan(psi, -T, qx, qy, qz);
+  double gx0, gy0, gx1, gy1;
+  block_grad(chi.ar, chi.ai, chi.br, chi.bi, psi.ar, psi.ai, psi.br, psi.bi, T, -R, qx, qy, qz, gx0, gy0);
+  block_grad(chi.cr, chi.ci, chi.dr, chi.di, psi.cr, psi.ci, psi.dr, psi.di, T, -R, qx, -qy, qz, gx1, gy1);
+  rotate_tan(chi, -T, qx, qy, qz);
+  sig *= c2;
+  return make_double2(sig * (gx0 + gx1), sig * (gy0 - gy1));
+}
+
+// Folds Sigma back into the states (psi~, chi~ <- sqrt(Sigma) psi~, chi~ are then the true states) so
+// Sigma restarts at 1; once per chunk, which keeps Sigma far from underflow.
+__device__ __forceinline__ void fold_scale(State& psi, State& chi, double& sig) {
+  const double s = sqrt(sig);
+  psi.ar *= s; psi.ai *= s; psi.br *= s; psi.bi *= s; psi.cr *= s; psi.ci *= s; psi.dr *= s; psi.di *= s;
+  chi.ar *= s; chi.ai *= s; chi.br *= s; chi.bi *= s; chi.cr *= s; chi.ci *= s; chi.dr *= s; chi.di *= s;
+  sig = 1.0;
+}
+
+// One backward step in the form of the pulse's variant: tangent form (scale in sig) or exact C, S.
+template <int MODE>
+__device__ __forceinline__ double2 back_any(State& psi, State& chi, double2 r, double pxdt, double pydt, double qz,
+                                            double qz2, int h, double inv4h, double& sig) {
+  if constexpr (MODE < kHalvingMode) return back_step_tan<MODE>(psi, chi, r, pxdt, pydt, qz, qz2, sig);
+  else return back_step<false>(psi, chi, r, pxdt, pydt, qz, qz2, h, inv4h);
+}
+
 // Forward step of the evolution in the form the pulse's series choice selects.
 template <int MODE>
 __device__ __forceinline__ void fwd_step(State& v, double2 rec, double pxdt, double pydt, double qz, double qz2, int h,
@@ -311,7 +383,7 @@ __device__ __forceinline__ void grad_item(const GradArgs& a, int item, int pi, d
   }
 
   // backward over the chunks in reverse, kGroup steps at a time (the last group of a chunk may be short)
-  constexpr bool kSeries = MODE < kHalvingMode;
+  double sig = 1.0;  // Sigma of the tangent form (unused by the exact form)
   double* part = a.part + a.goff[pi] + int64_t(li) * nt * 2;
   double2 (*buf)[64] = bufs[wave];
   for (int c = nchunks - 1; c >= 0; --c) {
@@ -322,19 +394,21 @@ __device__ __forceinline__ void grad_item(const GradArgs& a, int item, int pi, d
       tab[threadIdx.x] = make_double2(-t.x * dt, -t.y * dt);
     }
     __syncthreads();
+    if constexpr (MODE < kHalvingMode) fold_scale(psi, chi, sig);
     // a short group first (len not a multiple of kGroup), then full groups
     int top = len - 1;
     const int r = len % kGroup;
     if (r != 0) {
 #pragma unroll 1
-      for (int j = 0; j < r; ++j) buf[j][lane] = back_step<kSeries>(psi, chi, tab[top - j], pxdt, pydt, qz, qz2, h, inv4h);
+      for (int j = 0; j < r; ++j)
+        buf[j][lane] = back_any<MODE>(psi, chi, tab[top - j], pxdt, pydt, qz, qz2, h, inv4h, sig);
       group_store(buf, red[wave], lane, top, r);
       top -= r;
     }
     for (; top >= 0; top -= kGroup) {
 #pragma unroll
       for (int j = 0; j < kGroup; ++j)
-        buf[j][lane] = back_step<kSeries>(psi, chi, tab[top - j], pxdt, pydt, qz, qz2, h, inv4h);
+        buf[j][lane] = back_any<MODE>(psi, chi, tab[top - j], pxdt, pydt, qz, qz2, h, inv4h, sig);
       group_store(buf, red[wave], lane, top, kGroup);
     }
     __syncthreads();
@@ -348,6 +422,8 @@ __device__ __forceinline__ void grad_item(const GradArgs& a, int item, int pi, d
       reinterpret_cast<double2*>(part)[n0 + threadIdx.x] = v;
     }
   }
+
+  if constexpr (MODE < kHalvingMode) fold_scale(psi, chi, sig);  // chi~ -> the true chi'_0
 
   // t_i: d|-> = -|+><+|dh|->/(2 w), dP = -dA(t_i); chi holds U^+ ... alpha |+_out> = alpha chi_0
   double g_in_x = 0.0, g_in_y = 0.0;

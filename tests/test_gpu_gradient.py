@@ -30,7 +30,7 @@ def assert_grad(g, gr, what):
     assert np.all(err <= tol), (what, np.nonzero(err > tol)[0][:8])
 
 
-@pytest.mark.parametrize("case", ["tan_range", "angle_halving", "two_pulses_ragged"])
+@pytest.mark.parametrize("case", ["tan_range", "angle_halving", "two_pulses_ragged", "short_tables"])
 def test_yield_gradient_matches_differences(orc, case):
     w = W.single_pulse(0)
     specs = [dict(w["specs"][0], nt=2048)]
@@ -44,6 +44,15 @@ def test_yield_gradient_matches_differences(orc, case):
         coeffs = [w["coeff"][0], W.draw_coeff(8, 1, 8)[0]]
     say(f"yield gradient case {case}")
     tabs = [orc.synth(sp, c) for sp, c in zip(specs, coeffs)]
+    if case == "short_tables":
+        # tables shorter than one reduction group (5 steps) and not a multiple of it (13 steps):
+        # stretches of the nt = 2048 table at its step, with the neighbouring rows as edges
+        full, dt = tabs[0], specs[0]["T"] / specs[0]["nt"]
+        specs, tabs = [], []
+        for n0, n in ((100, 5), (900, 13)):
+            specs.append(dict(w["specs"][0], nt=n, T=n * dt))
+            tabs.append((full[0][n0:n0 + n], None, np.stack([full[0][n0 - 1], full[0][n0 + n]]), 1.0))
+        grids = [W.sheet_grid(8, 8, 1.0), W.grid((5, 3, 2), (-0.8, -0.6, -0.5), (0.7, 0.9, 0.4))]
     A = np.concatenate([t[0] for t in tabs])
     edge = np.stack([t[2] for t in tabs])
     gA = torch.empty(A.shape, dtype=torch.float64, device="cuda")
