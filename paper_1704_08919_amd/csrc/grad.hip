@@ -21,7 +21,8 @@
 // One workgroup of 256 lanes per 256-mode item, one mode per lane.  Forward: the evolution's own
 // step (tangent form or C, S with the pulse's angle halvings), states unit-normalised per block at
 // t_f.  Backward: the table is staged through LDS chunk by chunk in reverse; each step applies U^+
-// (exact C, S form) to psi and chi' and forms the two derivative terms.  Their sum over the item's
+// to psi and chi' (tangent form with the factors C carried in a per-lane scale, or the exact C, S
+// form on the angle-halving path) and forms the two derivative terms.  Their sum over the item's
 // modes is taken per step in a fixed order: each lane stores its terms for 8 steps in LDS, the wave
 // reads them back transposed (lane (j, p) adds the lanes p, p + 8, ..., p + 56 of step j), pairs
 // up the 8 lanes of a step (DPP), and the four waves are added in order; the results are written
