@@ -29,7 +29,8 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 128 FLOP/clk x 2.4 GHz
 # (3 mul), and 1 - i T Q on two 2x2 blocks (8 real components x 3 FMA) = 57 + 2n.
 # cos/sin of degree 7 (large steps): q, x, two series (14 FMA), S q, and C - i S Q on two blocks
 # (8 x (1 mul + 3 FMA)) = 93, plus 6 per angle halving (not counted: a lower bound).
-FLOP_PER_MODE_STEP = {"tan6": 69, "tan8": 73, "tan10": 77, "tan13": 83, "cossin7_halving": 93}
+FLOP_PER_MODE_STEP = {"tan6": 69, "tan7": 71, "tan8": 73, "tan9": 75, "tan10": 77, "tan11": 79, "tan12": 81,
+                      "tan13": 83, "cossin7_halving": 93}
 HERE_PROFILES = os.path.join(ROOT, "profiles")
 # launch shape of the plans used by the surrogate sections (fixed, so no autotuning is timed)
 PLAN = dict(threads=256, modes_per_lane=1, persistent=1)

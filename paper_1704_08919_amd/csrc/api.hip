@@ -106,7 +106,7 @@ po_status build_batch(int32_t n, const po_pulse_spec* specs, const po_grid* grid
   *b = Batch{};
   b->n_pulses = n;
   int64_t tab = 0, modes = 0, coeff = 0, spec = 0;
-  int64_t units = 0, items = 0;
+  int64_t units = 0, items = 0, blocks = 0;
   for (int i = 0; i < n; ++i) {
     PulseDev d;
     std::memset(&d, 0, sizeof d);
@@ -116,6 +116,7 @@ po_status build_batch(int32_t n, const po_pulse_spec* specs, const po_grid* grid
     d.spec_off = spec;
     d.unit_off = units;
     d.item_off = int32_t(items);
+    d.blk_off = int32_t(blocks);
     if (specs) {
       const po_pulse_spec& s = specs[i];
       d.nt = s.nt;
@@ -156,6 +157,7 @@ po_status build_batch(int32_t n, const po_pulse_spec* specs, const po_grid* grid
       modes += m;
       units += d.nunits;
       items += d.nitems;
+      blocks += (m + kSelBlock - 1) / kSelBlock;
       if (i > 0 && std::memcmp(&g, &grids[0], sizeof g) != 0) b->uniform = false;
     }
     out[i] = d;
@@ -167,6 +169,7 @@ po_status build_batch(int32_t n, const po_pulse_spec* specs, const po_grid* grid
   b->total_spec = spec;
   b->total_units = units;
   b->total_items = int32_t(items);
+  b->total_blocks = int32_t(blocks);
   return PO_OK;
 }
 
@@ -215,11 +218,11 @@ po_status evolve_impl(const Batch& b, const PulseDev* d_desc, const double* d_A,
     PO_TRY(units.alloc(sizeof(double) * size_t(b.total_units), s));
     d_units = static_cast<double*>(units.ptr);
   }
-  PO_TRY(sel.alloc(sizeof(int2) * size_t(b.n_pulses), s));
+  PO_TRY(sel.alloc(sizeof(int2) * size_t(b.total_blocks), s));
   int2* d_sel = static_cast<int2*>(sel.ptr);
   hipEvent_t e0 = nullptr;
   const bool timed = timer_start(s, &e0);
-  PO_TRY(launch_series_select(b, d_desc, d_A, d_A_edge, d_sel, s));
+  PO_TRY(launch_block_select(b, d_desc, d_A, d_sel, s));
   PO_TRY(launch_evolve_grid(b, d_desc, d_A, d_A_edge, d_sel, d_f, d_units, s));
   if (timed) {
     timer_stop(s, e0);
@@ -596,7 +599,7 @@ po_status po_timer_enable(int on) {
 
 po_status po_timer_mode_steps(uint64_t* counts, int32_t n) {
   if (!counts || n < 1) return set_error(PO_ERR_INVALID, "counts must hold at least one entry");
-  unsigned long long h[kSeriesVariants] = {0, 0, 0, 0, 0};
+  unsigned long long h[kSeriesVariants] = {};
   {
     std::lock_guard<std::mutex> lk(g_timer_mu);
     if (g_counts) {

@@ -33,6 +33,7 @@ po_status check_device_range(const void* p, size_t bytes, size_t align, const ch
 // One record per pulse, uploaded to device memory for every multi-pulse launch.
 constexpr int kUnit = 64;         // momentum modes per reduction unit, one wave (fixed: sets the sum order)
 constexpr int kItem = 256;        // modes per workgroup in the default (non-plan) evolution launch
+constexpr int kSelBlock = 512;    // modes per series-selection block: a multiple of every launch's item
 constexpr int kMaxLines = 8192;   // spectral lines per pulse
 constexpr int kMaxNs = 64;        // B-spline coefficients per spectral function
 constexpr int kMaxSub = 8;        // sample points per step of po_field_samples
@@ -49,7 +50,7 @@ struct PulseDev {
   int32_t nunits;
   int32_t item_off;   // first workgroup item of this pulse in the default evolution launch
   int32_t nitems;
-  int32_t pad1;
+  int32_t blk_off;    // first series-selection block (kSelBlock modes) of this pulse in the batch
   double T, dt, dw, wmin, wmax, norm_value, dv;
   double lo[3], dp[3];  // p_d = lo_d + (i + 1/2) dp_d; dp_d = 0 for a sheet (then p_d = lo_d)
 };
@@ -59,6 +60,7 @@ struct Batch {
   int64_t total_rows = 0, total_modes = 0, total_coeff = 0, total_spec = 0;
   int64_t total_units = 0;
   int32_t total_items = 0;     // workgroups of the default evolution launch
+  int32_t total_blocks = 0;    // series-selection blocks (kSelBlock modes, per pulse)
   int32_t max_stat_blocks = 0; // largest per-pulse block count of the field statistics pass
   int32_t max_nt = 0;
   int32_t max_lines = 0;       // most spectral lines of any pulse
@@ -108,12 +110,18 @@ struct EvolveConfig {
   int mpl = 1;
   int persistent = 0;
 };
-// Per-pulse series selection: x = mode (variant), y = number of angle halvings.
-// d_sel must hold n_pulses int2; d_units n = total_units doubles (one partial sum per 64 modes).
+// Per-pulse series selection (yield gradient): x = variant of kTanDegree (or kHalvingMode), y =
+// number of angle halvings; d_sel holds n_pulses int2.
 po_status launch_series_select(const Batch& b, const PulseDev* d_desc, const double* d_A, const double* d_A_edge,
                                int2* d_sel, hipStream_t s);
+// Per-block series selection of the second-order evolution: x = variant of kFineDegree (or
+// kFineHalving), y = number of angle halvings, one int2 per kSelBlock modes of each pulse
+// (total_blocks).  The evolution launches below take this array; d_units holds total_units
+// doubles (one partial sum per 64 modes).
+po_status launch_block_select(const Batch& b, const PulseDev* d_desc, const double* d_A, int2* d_bsel,
+                              hipStream_t s);
 po_status launch_evolve_grid(const Batch& b, const PulseDev* d_desc, const double* d_A, const double* d_A_edge,
-                             const int2* d_sel, double* d_f, double* d_units, hipStream_t s);
+                             const int2* d_bsel, double* d_f, double* d_units, hipStream_t s);
 // Persistent launch: items are {pulse, first mode} pairs of cfg.threads * cfg.mpl modes each,
 // taken in queue order through the counter (reset on the stream before the launch).
 po_status launch_evolve_persistent(const EvolveConfig& cfg, int n_pulses, const PulseDev* d_desc, const double* d_A,
@@ -137,8 +145,8 @@ po_status launch_yield_from_units(const Batch& b, const PulseDev* d_desc, const 
 po_status plan_evolve(const po_plan* plan, int32_t n, const po_pulse_spec* specs, const po_grid* grids,
                       const double* d_A, const double* d_edge, double* d_f, double* d_J, hipStream_t s);
 // Kernel timers (api.hip): start returns true (and records *e0) when timers are enabled;
-// timer_count enqueues the per-variant mode-step count of a selection (no-op when disabled).
-constexpr int kSeriesVariants = 5;
+// timer_count enqueues the per-variant mode-step count of a block selection (no-op when disabled).
+constexpr int kSeriesVariants = 9;  // T series of degree 6..13, then the angle-halving path
 bool timer_start(hipStream_t s, hipEvent_t* e0);
 void timer_stop(hipStream_t s, hipEvent_t e0);
 po_status timer_count(int n_pulses, const PulseDev* d_desc, const int2* d_sel, hipStream_t s);

@@ -49,6 +49,12 @@ constexpr double kTanXmax[kNumTan] = {0.0099, 0.0337, 0.0735, 0.1558};
 constexpr double kCosSinXmax = 0.3612;
 constexpr int kHalvingMode = kNumTan;
 constexpr int kNumModes = kNumTan + 1;
+// Every degree from 6 to 13, for the per-block choice of the second-order evolution (same remainder
+// bound, largest x rounded down to four digits).  Index kFineHalving: the angle-halving path.
+constexpr int kNumFine = 8;
+constexpr int kFineDegree[kNumFine] = {6, 7, 8, 9, 10, 11, 12, 13};
+constexpr double kFineXmax[kNumFine] = {0.0099, 0.0197, 0.0337, 0.0518, 0.0735, 0.0985, 0.1261, 0.1558};
+constexpr int kFineHalving = kNumFine;
 constexpr double kSqrt3Over6 = 0.28867513459481288225;  // sqrt(3)/6, Gauss-Legendre nodes 1/2 -+ sqrt(3)/6
 
 // Horner step k of the C and S series, coefficients forced to compile-time constants.

@@ -19,8 +19,9 @@
 // For any value of T, 1 - i T Q_s is a scalar multiple of a unitary matrix (its square modulus
 // is (1 + T^2 x) 1), so rounding in T perturbs only the rotation angle.  T -- or C and S on the
 // large-step path, which halves the angle -- is a truncated Maclaurin series in x whose
-// remainder is below 2^-56 on the pulse's whole range of x; it is shared by both blocks,
-// because omega does not depend on s.
+// remainder is below 2^-56 on the whole range of x of the 512-mode block the item belongs to (a
+// box of momenta against the range of the pulse's table); it is shared by both blocks, because
+// omega does not depend on s.
 //
 // Work decomposition: a workgroup of THREADS lanes (64-wide waves) owns an item of
 // THREADS x MPL consecutive modes of one pulse, MPL modes per lane.  The pulse's table of -A dt
@@ -49,8 +50,8 @@ __device__ __forceinline__ double grid_max_abs(double lo, int n, double dp) {
 
 // Per pulse: bound on x = (omega dt)^2 over every mode and step,
 //   x <= dt^2 [ max_n ((max|p_x| + |A_x,n|)^2 + (max|p_y| + |A_y,n|)^2) + 1 + max p_z^2 ],
-// and the series variant it selects (sel.x) with the number of angle halvings (sel.y).  Per
-// pulse, so all modes of a pulse use the same arithmetic whatever the launch shape.
+// and the series variant of kTanDegree it selects (sel.x) with the number of angle halvings
+// (sel.y).  Per pulse, for the yield gradient and (NODES = 2) the fourth-order step.
 // NODES = 2: the table holds A at two nodes per step (fourth-order step); with theta^2 the bound
 // above, |w_s| <= theta + (sqrt3/6) theta^2 bounds the step's rotation angle.
 template <int NODES>
@@ -99,10 +100,67 @@ __global__ void __launch_bounds__(256) k_series_select(const PulseDev* __restric
   }
 }
 
-template <int MODE>  // MODE < kHalvingMode: T series of degree kTanDegree[MODE]; else C, S with angle halving
+// Per block of kSelBlock consecutive modes of a pulse: bound on x = (omega dt)^2 over the block's
+// modes and every step,
+//   x <= dt^2 [ max|p_x - A_x|^2 + max|p_y - A_y|^2 + 1 + max p_z^2 ],
+// each maximum over the block's box of cell-centred momenta and the range of the pulse's table,
+// and the variant of kFineDegree it selects (x) with the number of angle halvings (y).  Items of
+// every launch shape lie inside one block, so each mode's arithmetic is still the same whatever
+// the launch.  One workgroup per pulse: the table's extremes, then one thread per block.
+__global__ void __launch_bounds__(256) k_block_select(const PulseDev* __restrict__ desc, const double* __restrict__ A,
+                                                      int2* __restrict__ bsel) {
+  const PulseDev d = desc[blockIdx.x];
+  const double2* tab = reinterpret_cast<const double2*>(A) + d.tab_off;
+  double lx = INFINITY, hx = -INFINITY, ly = INFINITY, hy = -INFINITY;
+  for (int64_t n = threadIdx.x; n < d.nt; n += blockDim.x) {
+    const double2 a = tab[n];
+    lx = fmin(lx, a.x); hx = fmax(hx, a.x);
+    ly = fmin(ly, a.y); hy = fmax(hy, a.y);
+  }
+  __shared__ double red[4][256];
+  red[0][threadIdx.x] = -lx; red[1][threadIdx.x] = hx; red[2][threadIdx.x] = -ly; red[3][threadIdx.x] = hy;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w)
+      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = fmax(red[k][threadIdx.x], red[k][threadIdx.x + w]);
+    __syncthreads();
+  }
+  const double axl = -red[0][0], axh = red[1][0], ayl = -red[2][0], ayh = red[3][0];
+  const int nx = d.n[0], ny = d.n[1];
+  const int64_t nmodes = int64_t(nx) * ny * d.n[2];
+  const int nblk = int((nmodes + kSelBlock - 1) / kSelBlock);
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+    const int64_t m0 = int64_t(b) * kSelBlock, m1 = min(m0 + kSelBlock, nmodes) - 1;
+    const int64_t r0 = m0 / nx, r1 = m1 / nx;                      // rows (iy, iz)
+    const int64_t z0 = r0 / ny, z1 = r1 / ny;
+    const int ix0 = r0 == r1 ? int(m0 % nx) : 0, ix1 = r0 == r1 ? int(m1 % nx) : nx - 1;
+    const int iy0 = z0 == z1 ? int(r0 % ny) : 0, iy1 = z0 == z1 ? int(r1 % ny) : ny - 1;
+    const double pxl = d.lo[0] + (ix0 + 0.5) * d.dp[0], pxh = d.lo[0] + (ix1 + 0.5) * d.dp[0];
+    const double pyl = d.lo[1] + (iy0 + 0.5) * d.dp[1], pyh = d.lo[1] + (iy1 + 0.5) * d.dp[1];
+    const double pzl = d.lo[2] + (z0 + 0.5) * d.dp[2], pzh = d.lo[2] + (z1 + 0.5) * d.dp[2];
+    // largest |p - a| over p and a in their intervals
+    const double X = fmax(fmax(fmax(pxl, pxh) - axl, axh - fmin(pxl, pxh)), 0.0);
+    const double Y = fmax(fmax(fmax(pyl, pyh) - ayl, ayh - fmin(pyl, pyh)), 0.0);
+    const double Z = fmax(fabs(pzl), fabs(pzh));
+    const double xb = (X * X + Y * Y + 1.0 + Z * Z) * d.dt * d.dt * (1.0 + 1e-6);
+    int mode = kFineHalving, h = 0;
+    for (int k = kNumFine - 1; k >= 0; --k)
+      if (xb <= kFineXmax[k]) mode = k;
+    if (mode == kFineHalving) {
+      double x = xb;
+      while (x > kCosSinXmax) {
+        x *= 0.25;
+        ++h;
+      }
+    }
+    bsel[d.blk_off + b] = make_int2(mode, h);
+  }
+}
+
+template <int MODE>  // MODE < kFineHalving: T series of degree kFineDegree[MODE]; else C, S with angle halving
 __device__ __forceinline__ void one_step(State& v, double2 rec, double pxdt, double pydt, double qz, double qz2, int h,
                                          double inv4h) {
-  if constexpr (MODE < kHalvingMode) step_tan<kTanDegree[MODE]>(v, rec, pxdt, pydt, qz, qz2);
+  if constexpr (MODE < kFineHalving) step_tan<kFineDegree[MODE]>(v, rec, pxdt, pydt, qz, qz2);
   else step_halving(v, rec, pxdt, pydt, qz, qz2, h, inv4h);
 }
 
@@ -111,7 +169,7 @@ struct EvolveArgs {
   int n_pulses;
   const double* A;
   const double* Aedge;
-  const int2* sel;
+  const int2* sel;  // per selection block (k_block_select)
   double* f;
   double* units;
 };
@@ -180,7 +238,7 @@ __device__ __forceinline__ void process_item(const EvolveArgs& a, int pi, int fi
         for (int j = 0; j < MPL; ++j) one_step<MODE>(v[j], rec, pxdt[j], pydt[j], qz[j], qz2[j], h, inv4h);
       }
     }
-    if constexpr (MODE < kHalvingMode) {
+    if constexpr (MODE < kFineHalving) {
 #pragma unroll
       for (int j = 0; j < MPL; ++j) renormalise(v[j]);
     }
@@ -213,15 +271,20 @@ __device__ __forceinline__ void process_item(const EvolveArgs& a, int pi, int fi
   }
 }
 
+// The item's variant is that of the selection block holding it (items never straddle blocks).
 template <int THREADS, int MPL>
 __device__ __forceinline__ void dispatch_item(const EvolveArgs& a, int pi, int first, double2 (*lds)[kChunk]) {
-  const int2 sl = a.sel[pi];
+  const int2 sl = a.sel[a.desc[pi].blk_off + first / kSelBlock];
   switch (sl.x) {
     case 0: process_item<0, THREADS, MPL>(a, pi, first, 0, lds); break;
     case 1: process_item<1, THREADS, MPL>(a, pi, first, 0, lds); break;
     case 2: process_item<2, THREADS, MPL>(a, pi, first, 0, lds); break;
     case 3: process_item<3, THREADS, MPL>(a, pi, first, 0, lds); break;
-    default: process_item<kHalvingMode, THREADS, MPL>(a, pi, first, sl.y, lds); break;
+    case 4: process_item<4, THREADS, MPL>(a, pi, first, 0, lds); break;
+    case 5: process_item<5, THREADS, MPL>(a, pi, first, 0, lds); break;
+    case 6: process_item<6, THREADS, MPL>(a, pi, first, 0, lds); break;
+    case 7: process_item<7, THREADS, MPL>(a, pi, first, 0, lds); break;
+    default: process_item<kFineHalving, THREADS, MPL>(a, pi, first, sl.y, lds); break;
   }
 }
 
@@ -279,15 +342,19 @@ __global__ void __launch_bounds__(256) k_yield(const PulseDev* __restrict__ desc
   if (threadIdx.x == 0) J[blockIdx.x] = s * d.dv;
 }
 
-// Diagnostics: adds modes x nt of every pulse to the count of the series variant it selected.
+// Diagnostics: adds modes x nt of every selection block to the count of the variant it selected.
 __global__ void __launch_bounds__(256) k_count_mode_steps(const PulseDev* __restrict__ desc, int n,
-                                                          const int2* __restrict__ sel,
+                                                          const int2* __restrict__ bsel,
                                                           unsigned long long* __restrict__ counts) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+  for (int i = 0; i < n; ++i) {
     const PulseDev& d = desc[i];
-    const unsigned long long ms =
-        (unsigned long long)d.nt * (unsigned long long)d.n[0] * (unsigned long long)d.n[1] * (unsigned long long)d.n[2];
-    atomicAdd(&counts[min(max(sel[i].x, 0), kNumModes - 1)], ms);
+    const int64_t nmodes = int64_t(d.n[0]) * d.n[1] * d.n[2];
+    const int nblk = int((nmodes + kSelBlock - 1) / kSelBlock);
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+      const int64_t m = min(int64_t(kSelBlock), nmodes - int64_t(b) * kSelBlock);
+      atomicAdd(&counts[min(max(bsel[d.blk_off + b].x, 0), kSeriesVariants - 1)],
+                (unsigned long long)m * (unsigned long long)d.nt);
+    }
   }
 }
 
@@ -443,6 +510,13 @@ __global__ void __launch_bounds__(kItem) k_evolve4(Evolve4Args a) {
 po_status launch_series_select(const Batch& b, const PulseDev* d_desc, const double* d_A, const double* d_A_edge,
                                int2* d_sel, hipStream_t s) {
   hipLaunchKernelGGL(k_series_select<1>, dim3(b.n_pulses), dim3(256), 0, s, d_desc, d_A, d_A_edge, d_sel);
+  PO_HIP(hipGetLastError());
+  return PO_OK;
+}
+
+po_status launch_block_select(const Batch& b, const PulseDev* d_desc, const double* d_A, int2* d_bsel,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_block_select, dim3(b.n_pulses), dim3(256), 0, s, d_desc, d_A, d_bsel);
   PO_HIP(hipGetLastError());
   return PO_OK;
 }

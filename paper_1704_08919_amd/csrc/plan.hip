@@ -102,7 +102,7 @@ po_status enqueue(po_plan* p, const double* d_coeff, const double* d_A, const do
     d_A = p->d_A;
     d_edge = p->d_edge;
   }
-  PO_TRY(launch_series_select(p->b, p->d_desc, d_A, d_edge, p->d_sel, s));
+  PO_TRY(launch_block_select(p->b, p->d_desc, d_A, p->d_sel, s));
   double* units = d_J ? p->d_units : nullptr;
   if (p->cfg.persistent)
     PO_TRY(launch_evolve_persistent(p->cfg, p->n, p->d_desc, d_A, d_edge, p->d_sel, p->d_queue, p->n_items,
@@ -220,7 +220,7 @@ po_status plan_create(int32_t n, const po_pulse_spec* specs, const po_grid* grid
   PO_TRY(dalloc(&p->d_desc, n));
   PO_HIP(hipMemcpy(p->d_desc, p->h_desc.data(), sizeof(PulseDev) * n, hipMemcpyHostToDevice));
   PO_TRY(dalloc(&p->d_counter, 1));
-  PO_TRY(dalloc(&p->d_sel, n));
+  PO_TRY(dalloc(&p->d_sel, size_t(p->b.total_blocks)));
   PO_TRY(dalloc(&p->d_units, size_t(p->b.total_units)));
   PO_TRY(dalloc(&p->d_A, size_t(2 * p->b.total_rows)));
   PO_TRY(dalloc(&p->d_edge, size_t(4 * n)));
