@@ -137,6 +137,7 @@ po_status build_batch(int32_t n, const po_pulse_spec* specs, const po_grid* grid
       spec += 4 * int64_t(d.nlines);
       b->max_nt = std::max(b->max_nt, s.nt);
       b->max_lines = std::max(b->max_lines, d.nlines);
+      b->max_ns = std::max(b->max_ns, d.ns);
       b->max_stat_blocks = std::max(b->max_stat_blocks, d.stat_blocks);
       if (i > 0 && (s.nt != specs[0].nt || s.T != specs[0].T)) b->uniform = false;
     }
@@ -495,7 +496,7 @@ po_status po_synth_gradient(int32_t n, const po_pulse_spec* specs, const double*
   PO_TRY(E.alloc(sizeof(double) * 2 * b.total_rows, s));
   PO_TRY(edge.alloc(sizeof(double) * 4 * n, s));
   PO_TRY(scl.alloc(sizeof(double) * n, s));
-  PO_TRY(lines.alloc(sizeof(double) * size_t(b.total_spec / 4) * 8 * kMaxNs, s));
+  PO_TRY(lines.alloc(sizeof(double) * size_t(b.total_spec / 4) * 8 * size_t(b.max_ns), s));
   double *dA = static_cast<double*>(A.ptr), *dE = static_cast<double*>(E.ptr), *de = static_cast<double*>(edge.ptr);
   double* dscale = static_cast<double*>(scl.ptr);
   PO_TRY(synth_impl(n, specs, d_coeff, dA, dE, de, dscale, s, b, d_desc));
@@ -527,7 +528,7 @@ po_status po_evaluate_gradient(int32_t n, const po_pulse_spec* specs, const po_g
   PO_TRY(scl.alloc(sizeof(double) * n, s));
   PO_TRY(gA.alloc(sizeof(double) * 2 * b.total_rows, s));
   PO_TRY(gedge.alloc(sizeof(double) * 4 * n, s));
-  PO_TRY(lines.alloc(sizeof(double) * size_t(b.total_spec / 4) * 8 * kMaxNs, s));
+  PO_TRY(lines.alloc(sizeof(double) * size_t(b.total_spec / 4) * 8 * size_t(b.max_ns), s));
   double *dA = static_cast<double*>(A.ptr), *dE = static_cast<double*>(E.ptr), *de = static_cast<double*>(edge.ptr);
   double *dscale = static_cast<double*>(scl.ptr), *dgA = static_cast<double*>(gA.ptr);
   double* dge = static_cast<double*>(gedge.ptr);

@@ -64,6 +64,7 @@ struct Batch {
   int32_t max_stat_blocks = 0; // largest per-pulse block count of the field statistics pass
   int32_t max_nt = 0;
   int32_t max_lines = 0;       // most spectral lines of any pulse
+  int32_t max_ns = 0;          // most B-spline coefficients per spectral function of any pulse
   bool uniform = true;         // all pulses share nt/grid (lets kernels skip the binary search)
 };
 
@@ -92,7 +93,7 @@ po_status launch_synth(const Batch& b, const PulseDev* d_desc, const double* d_c
 po_status launch_samples(const Batch& b, const PulseDev* d_desc, const double* d_coeff, double* d_spec, double* d_part,
                          double* d_scale_ws, int n_sub, const double* offsets, int with_end, double* d_E,
                          double* d_Ed, double* d_A, double* d_A_edge, double* d_scale_out, hipStream_t s);
-// Adjoint of the synthesis: d_lines scratch [sum lines][8 kMaxNs]; d_A, d_A_edge, d_E the (scaled) tables of
+// Adjoint of the synthesis: d_lines scratch [sum lines][8 max_ns]; d_A, d_A_edge, d_E the (scaled) tables of
 // the pulses and d_scale their scale; d_gA [sum nt][2] and d_gedge [n][2][2] (or NULL) the gradient of
 // J with respect to the tables.  Writes dJ/dc, the energy U and dU/dc (NULL to skip).
 po_status launch_synth_adjoint(const Batch& b, const PulseDev* d_desc, const double* d_coeff, const double* d_gA,

@@ -393,11 +393,11 @@ __device__ __forceinline__ void line_terms(const PulseDev& d, int64_t k, int64_t
 // and dU/d(cE, sE) (unscaled field) are formed with fixed-order block sums; then thread c < 4 n_s
 // chains them through cE = E cos Phi, sE = E sin Phi and the B-spline expansions of E and
 // Phi = pi (c + 1) for coefficient c, writing out[line][c] (dJ) and out[line][4 n_s + c] (dU),
-// line slots of 8 kMaxNs doubles.
+// line slots of `stride` = 8 max n_s doubles.
 __global__ void __launch_bounds__(256) k_adjoint_lines(const PulseDev* __restrict__ desc, const double* __restrict__ coeff,
                                                        const double* __restrict__ gA, const double* __restrict__ gedge,
                                                        const double* __restrict__ E, const double* __restrict__ scale,
-                                                       double* __restrict__ out) {
+                                                       int stride, double* __restrict__ out) {
   const PulseDev d = desc[blockIdx.y];
   const int j = blockIdx.x;
   if (j >= d.nlines) return;
@@ -459,7 +459,7 @@ __global__ void __launch_bounds__(256) k_adjoint_lines(const PulseDev* __restric
     dJ = M_PI * Ev * (Gs * cp - Gc * sp);
     dU = M_PI * Ev * (Us * cp - Uc * sp);
   }
-  double* o = out + (d.spec_off / 4 + j) * (8 * kMaxNs);
+  double* o = out + (d.spec_off / 4 + j) * stride;
   o[t] = dJ * b[i];
   o[4 * d.ns + t] = dU * b[i];
 }
@@ -470,7 +470,7 @@ __global__ void __launch_bounds__(256) k_adjoint_coeff(const PulseDev* __restric
                                                        const double* __restrict__ gA, const double* __restrict__ gedge,
                                                        const double* __restrict__ A, const double* __restrict__ Aedge,
                                                        const double* __restrict__ E, const double* __restrict__ scale,
-                                                       double* __restrict__ grad, double* __restrict__ Uout,
+                                                       int stride, double* __restrict__ grad, double* __restrict__ Uout,
                                                        double* __restrict__ gU) {
   const PulseDev d = desc[blockIdx.x];
   __shared__ double red[256];
@@ -496,11 +496,11 @@ __global__ void __launch_bounds__(256) k_adjoint_coeff(const PulseDev* __restric
   if (threadIdx.x == 0 && Uout) Uout[blockIdx.x] = U;
   const int t = threadIdx.x;
   if (t >= 4 * d.ns) return;
-  const double* ln = lines + (d.spec_off / 4) * (8 * kMaxNs);
+  const double* ln = lines + (d.spec_off / 4) * stride;
   double gj = 0.0, gu = 0.0;
   for (int j = 0; j < d.nlines; ++j) {
-    gj += ln[int64_t(j) * (8 * kMaxNs) + t];
-    gu += ln[int64_t(j) * (8 * kMaxNs) + 4 * d.ns + t];
+    gj += ln[int64_t(j) * stride + t];
+    gu += ln[int64_t(j) * stride + 4 * d.ns + t];
   }
   // A = s A_raw: NORM_NONE has s = 1; NORM_ENERGY has s = sqrt(U0 / U_raw), so
   // dJ/dc = s dJ_raw/dc - (g.A) / (2 U_raw) dU_raw/dc and the energy stays U0.
@@ -537,10 +537,10 @@ po_status launch_synth_adjoint(const Batch& b, const PulseDev* d_desc, const dou
                                const double* d_scale, double* d_lines, double* d_grad, double* d_U, double* d_gU,
                                hipStream_t s) {
   hipLaunchKernelGGL(k_adjoint_lines, dim3(b.max_lines, b.n_pulses), dim3(256), 0, s, d_desc, d_coeff, d_gA, d_gedge,
-                     d_E, d_scale, d_lines);
+                     d_E, d_scale, 8 * b.max_ns, d_lines);
   PO_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_adjoint_coeff, dim3(b.n_pulses), dim3(256), 0, s, d_desc, d_lines, d_gA, d_gedge, d_A, d_A_edge,
-                     d_E, d_scale, d_grad, d_U, d_gU);
+                     d_E, d_scale, 8 * b.max_ns, d_grad, d_U, d_gU);
   PO_HIP(hipGetLastError());
   return PO_OK;
 }
