@@ -248,10 +248,10 @@ po_status yield_grad_impl(const Batch& b, const std::vector<PulseDev>& h, const 
   PO_TRY(part.alloc(sizeof(double) * size_t(tot), s));
   PO_TRY(epart.alloc(sizeof(double) * 4 * size_t(b.total_items), s));
   PO_TRY(units.alloc(sizeof(double) * size_t(b.total_units), s));
-  PO_TRY(sel.alloc(sizeof(int2) * size_t(b.n_pulses), s));
+  PO_TRY(sel.alloc(sizeof(int2) * size_t(b.total_blocks), s));
   int2* d_sel = static_cast<int2*>(sel.ptr);
   double* d_units = static_cast<double*>(units.ptr);
-  PO_TRY(launch_series_select(b, d_desc, d_A, d_A_edge, d_sel, s));
+  PO_TRY(launch_block_select(b, d_desc, d_A, d_sel, s));
   PO_TRY(launch_yield_grad(b, d_desc, d_A, d_A_edge, d_sel, static_cast<int64_t*>(sgoff.ptr),
                            static_cast<double*>(part.ptr), static_cast<double*>(epart.ptr), d_units, d_gA, d_gedge, s));
   if (d_J) PO_TRY(launch_yield_from_units(b, d_desc, d_units, d_J, s));

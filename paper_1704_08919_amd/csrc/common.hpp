@@ -111,14 +111,10 @@ struct EvolveConfig {
   int mpl = 1;
   int persistent = 0;
 };
-// Per-pulse series selection (yield gradient): x = variant of kTanDegree (or kHalvingMode), y =
-// number of angle halvings; d_sel holds n_pulses int2.
-po_status launch_series_select(const Batch& b, const PulseDev* d_desc, const double* d_A, const double* d_A_edge,
-                               int2* d_sel, hipStream_t s);
-// Per-block series selection of the second-order evolution: x = variant of kFineDegree (or
-// kFineHalving), y = number of angle halvings, one int2 per kSelBlock modes of each pulse
-// (total_blocks).  The evolution launches below take this array; d_units holds total_units
-// doubles (one partial sum per 64 modes).
+// Per-block series selection of the second-order evolution (and of the yield gradient): x =
+// variant of kFineDegree (or kFineHalving), y = number of angle halvings, one int2 per kSelBlock
+// modes of each pulse (total_blocks).  The evolution launches below take this array; d_units
+// holds total_units doubles (one partial sum per 64 modes).
 po_status launch_block_select(const Batch& b, const PulseDev* d_desc, const double* d_A, int2* d_bsel,
                               hipStream_t s);
 po_status launch_evolve_grid(const Batch& b, const PulseDev* d_desc, const double* d_A, const double* d_A_edge,

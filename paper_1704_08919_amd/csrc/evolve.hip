@@ -51,7 +51,7 @@ __device__ __forceinline__ double grid_max_abs(double lo, int n, double dp) {
 // Per pulse: bound on x = (omega dt)^2 over every mode and step,
 //   x <= dt^2 [ max_n ((max|p_x| + |A_x,n|)^2 + (max|p_y| + |A_y,n|)^2) + 1 + max p_z^2 ],
 // and the series variant of kTanDegree it selects (sel.x) with the number of angle halvings
-// (sel.y).  Per pulse, for the yield gradient and (NODES = 2) the fourth-order step.
+// (sel.y).  Per pulse; used by the fourth-order step (NODES = 2).
 // NODES = 2: the table holds A at two nodes per step (fourth-order step); with theta^2 the bound
 // above, |w_s| <= theta + (sqrt3/6) theta^2 bounds the step's rotation angle.
 template <int NODES>
@@ -506,13 +506,6 @@ __global__ void __launch_bounds__(kItem) k_evolve4(Evolve4Args a) {
 }
 
 }  // namespace
-
-po_status launch_series_select(const Batch& b, const PulseDev* d_desc, const double* d_A, const double* d_A_edge,
-                               int2* d_sel, hipStream_t s) {
-  hipLaunchKernelGGL(k_series_select<1>, dim3(b.n_pulses), dim3(256), 0, s, d_desc, d_A, d_A_edge, d_sel);
-  PO_HIP(hipGetLastError());
-  return PO_OK;
-}
 
 po_status launch_block_select(const Batch& b, const PulseDev* d_desc, const double* d_A, int2* d_bsel,
                               hipStream_t s) {

@@ -159,7 +159,7 @@ __device__ __forceinline__ double2 back_step(State& psi, State& chi, double2 r, 
 // degree M per T variant keeps the remainder below 2^-59 up to that variant's largest x.
 constexpr double pow2i(int n) { return n == 0 ? 1.0 : 2.0 * pow2i(n - 1); }
 constexpr double cos2_coef(int k) { return k == 0 ? 1.0 : (k % 2 ? -1.0 : 1.0) * pow2i(2 * k - 1) / factorial(2 * k); }
-constexpr int kCos2Degree[kNumTan] = {5, 6, 7, 8};
+constexpr int kCos2Degree[kNumFine] = {6, 6, 7, 7, 7, 8, 8, 8};
 
 template <int K>
 __device__ __forceinline__ void horner_cos2(double x, double& c) {
@@ -187,7 +187,7 @@ __device__ __forceinline__ void horner_tan1(double x, double& R) {
 template <int MODE>
 __device__ __forceinline__ double2 back_step_tan(State& psi, State& chi, double2 r, double pxdt, double pydt,
                                                  double qz, double qz2, double& sig) {
-  constexpr int N = kTanDegree[MODE], M = kCos2Degree[MODE];
+  constexpr int N = kFineDegree[MODE], M = kCos2Degree[MODE];
   const double qx = pxdt + r.x, qy = pydt + r.y;
   const double x = fma(qx, qx, fma(qy, qy, qz2));
   constexpr double cn = tan_coef(N);
@@ -217,7 +217,7 @@ __device__ __forceinline__ void fold_scale(State& psi, State& chi, double& sig) 
 template <int MODE>
 __device__ __forceinline__ double2 back_any(State& psi, State& chi, double2 r, double pxdt, double pydt, double qz,
                                             double qz2, int h, double inv4h, double& sig) {
-  if constexpr (MODE < kHalvingMode) return back_step_tan<MODE>(psi, chi, r, pxdt, pydt, qz, qz2, sig);
+  if constexpr (MODE < kFineHalving) return back_step_tan<MODE>(psi, chi, r, pxdt, pydt, qz, qz2, sig);
   else return back_step<false>(psi, chi, r, pxdt, pydt, qz, qz2, h, inv4h);
 }
 
@@ -225,7 +225,7 @@ __device__ __forceinline__ double2 back_any(State& psi, State& chi, double2 r, d
 template <int MODE>
 __device__ __forceinline__ void fwd_step(State& v, double2 rec, double pxdt, double pydt, double qz, double qz2, int h,
                                          double inv4h) {
-  if constexpr (MODE < kHalvingMode) step_tan<kTanDegree[MODE]>(v, rec, pxdt, pydt, qz, qz2);
+  if constexpr (MODE < kFineHalving) step_tan<kFineDegree[MODE]>(v, rec, pxdt, pydt, qz, qz2);
   else step_halving(v, rec, pxdt, pydt, qz, qz2, h, inv4h);
 }
 
@@ -289,7 +289,7 @@ struct GradArgs {
   int n_pulses;
   const double* A;
   const double* Aedge;
-  const int2* sel;
+  const int2* sel;      // per selection block (the evolution's k_block_select)
   const int64_t* goff;  // per pulse: first double of its item partials
   double* part;         // [items of pulse][nt][2] per pulse
   double* epart;        // [total items][4]: dA(t_i) x, y, dA(t_f) x, y
@@ -311,7 +311,7 @@ __device__ __forceinline__ void grad_item(const GradArgs& a, int item, int pi, d
   const int li = item - d.item_off;
   const int64_t m = int64_t(li) * kItem + threadIdx.x;
   const bool active = m < nmodes;
-  const int h = a.sel[pi].y;
+  const int h = a.sel[d.blk_off + li * kItem / kSelBlock].y;
   const double inv4h = ldexp(1.0, -2 * h);
   const double2* A = reinterpret_cast<const double2*>(a.A) + d.tab_off;
   const double2 ain = reinterpret_cast<const double2*>(a.Aedge)[2 * pi];
@@ -342,7 +342,7 @@ __device__ __forceinline__ void grad_item(const GradArgs& a, int item, int pi, d
     } else {
       for (int k = 0; k < len; ++k) fwd_step<MODE>(psi, tab[k], pxdt, pydt, qz, qz2, h, inv4h);
     }
-    if constexpr (MODE < kHalvingMode) renormalise(psi);
+    if constexpr (MODE < kFineHalving) renormalise(psi);
   }
 
   // t_f: normalise each block, alpha_s = <+_s(P_out)|psi_s>, final-state terms; chi_s = alpha_s |+_s>
@@ -395,7 +395,7 @@ __device__ __forceinline__ void grad_item(const GradArgs& a, int item, int pi, d
       tab[threadIdx.x] = make_double2(-t.x * dt, -t.y * dt);
     }
     __syncthreads();
-    if constexpr (MODE < kHalvingMode) fold_scale(psi, chi, sig);
+    if constexpr (MODE < kFineHalving) fold_scale(psi, chi, sig);
     // a short group first (len not a multiple of kGroup), then full groups
     int top = len - 1;
     const int r = len % kGroup;
@@ -424,7 +424,7 @@ __device__ __forceinline__ void grad_item(const GradArgs& a, int item, int pi, d
     }
   }
 
-  if constexpr (MODE < kHalvingMode) fold_scale(psi, chi, sig);  // chi~ -> the true chi'_0
+  if constexpr (MODE < kFineHalving) fold_scale(psi, chi, sig);  // chi~ -> the true chi'_0
 
   // t_i: d|-> = -|+><+|dh|->/(2 w), dP = -dA(t_i); chi holds U^+ ... alpha |+_out> = alpha chi_0
   double g_in_x = 0.0, g_in_y = 0.0;
@@ -463,12 +463,18 @@ __global__ void __launch_bounds__(kItem) __attribute__((amdgpu_waves_per_eu(3)))
   __shared__ double2 bufs[kWaves][kGroup][64];
   const int item = xcd_item(blockIdx.x, gridDim.x);
   const int pi = find_pulse_item(a.desc, a.n_pulses, item);
-  switch (a.sel[pi].x) {
+  // the item's variant is that of the evolution's selection block holding it
+  const PulseDev& d = a.desc[pi];
+  switch (a.sel[d.blk_off + (item - d.item_off) * kItem / kSelBlock].x) {
     case 0: grad_item<0>(a, item, pi, tab, red, bufs); break;
     case 1: grad_item<1>(a, item, pi, tab, red, bufs); break;
     case 2: grad_item<2>(a, item, pi, tab, red, bufs); break;
     case 3: grad_item<3>(a, item, pi, tab, red, bufs); break;
-    default: grad_item<kHalvingMode>(a, item, pi, tab, red, bufs); break;
+    case 4: grad_item<4>(a, item, pi, tab, red, bufs); break;
+    case 5: grad_item<5>(a, item, pi, tab, red, bufs); break;
+    case 6: grad_item<6>(a, item, pi, tab, red, bufs); break;
+    case 7: grad_item<7>(a, item, pi, tab, red, bufs); break;
+    default: grad_item<kFineHalving>(a, item, pi, tab, red, bufs); break;
   }
 }
 
