@@ -106,7 +106,7 @@ po_status build_batch(int32_t n, const po_pulse_spec* specs, const po_grid* grid
   *b = Batch{};
   b->n_pulses = n;
   int64_t tab = 0, modes = 0, coeff = 0, spec = 0;
-  int64_t units = 0, items = 0, blocks = 0;
+  int64_t units = 0, items = 0, blocks = 0, chunks = 0;
   for (int i = 0; i < n; ++i) {
     PulseDev d;
     std::memset(&d, 0, sizeof d);
@@ -117,6 +117,7 @@ po_status build_batch(int32_t n, const po_pulse_spec* specs, const po_grid* grid
     d.unit_off = units;
     d.item_off = int32_t(items);
     d.blk_off = int32_t(blocks);
+    d.chk_off = int32_t(chunks);
     if (specs) {
       const po_pulse_spec& s = specs[i];
       d.nt = s.nt;
@@ -133,6 +134,7 @@ po_status build_batch(int32_t n, const po_pulse_spec* specs, const po_grid* grid
       d.norm_value = s.norm_value;
       d.stat_blocks = s.norm == PO_NORM_NONE ? 0 : (s.nt + 1 + 255) / 256;
       tab += s.nt;
+      chunks += (s.nt + kChunkSteps - 1) / kChunkSteps;
       coeff += 4 * int64_t(s.n_s);
       spec += 4 * int64_t(d.nlines);
       b->max_nt = std::max(b->max_nt, s.nt);
@@ -171,6 +173,7 @@ po_status build_batch(int32_t n, const po_pulse_spec* specs, const po_grid* grid
   b->total_units = units;
   b->total_items = int32_t(items);
   b->total_blocks = int32_t(blocks);
+  b->total_chunks = int32_t(chunks);
   return PO_OK;
 }
 
@@ -219,15 +222,15 @@ po_status evolve_impl(const Batch& b, const PulseDev* d_desc, const double* d_A,
     PO_TRY(units.alloc(sizeof(double) * size_t(b.total_units), s));
     d_units = static_cast<double*>(units.ptr);
   }
-  PO_TRY(sel.alloc(sizeof(int2) * size_t(b.total_blocks), s));
-  int2* d_sel = static_cast<int2*>(sel.ptr);
+  PO_TRY(sel.alloc(sizeof(double) * 4 * size_t(b.total_chunks), s));
+  double* d_ranges = static_cast<double*>(sel.ptr);
   hipEvent_t e0 = nullptr;
   const bool timed = timer_start(s, &e0);
-  PO_TRY(launch_block_select(b, d_desc, d_A, d_sel, s));
-  PO_TRY(launch_evolve_grid(b, d_desc, d_A, d_A_edge, d_sel, d_f, d_units, s));
+  PO_TRY(launch_chunk_ranges(b, d_desc, d_A, d_ranges, s));
+  PO_TRY(launch_evolve_grid(b, d_desc, d_A, d_A_edge, d_ranges, d_f, d_units, s));
   if (timed) {
     timer_stop(s, e0);
-    PO_TRY(timer_count(b.n_pulses, d_desc, d_sel, s));
+    PO_TRY(timer_count(b.n_pulses, d_desc, d_ranges, s));
   }
   if (d_J) PO_TRY(launch_yield_from_units(b, d_desc, d_units, d_J, s));
   return PO_OK;
@@ -281,14 +284,14 @@ bool timer_start(hipStream_t s, hipEvent_t* e0) {
   return true;
 }
 
-po_status timer_count(int n_pulses, const PulseDev* d_desc, const int2* d_sel, hipStream_t s) {
+po_status timer_count(int n_pulses, const PulseDev* d_desc, const double* d_ranges, hipStream_t s) {
   unsigned long long* c;
   {
     std::lock_guard<std::mutex> lk(g_timer_mu);
     if (!g_timer_on || !g_counts) return PO_OK;
     c = g_counts;
   }
-  return launch_count_mode_steps(n_pulses, d_desc, d_sel, c, s);
+  return launch_count_mode_steps(n_pulses, d_desc, d_ranges, c, s);
 }
 
 void timer_stop(hipStream_t s, hipEvent_t e0) {

@@ -34,6 +34,7 @@ po_status check_device_range(const void* p, size_t bytes, size_t align, const ch
 constexpr int kUnit = 64;         // momentum modes per reduction unit, one wave (fixed: sets the sum order)
 constexpr int kItem = 256;        // modes per workgroup in the default (non-plan) evolution launch
 constexpr int kSelBlock = 512;    // modes per series-selection block: a multiple of every launch's item
+constexpr int kChunkSteps = 256;  // time steps per LDS chunk of the per-mode kernels (and per table range)
 constexpr int kMaxLines = 8192;   // spectral lines per pulse
 constexpr int kMaxNs = 64;        // B-spline coefficients per spectral function
 constexpr int kMaxSub = 8;        // sample points per step of po_field_samples
@@ -44,7 +45,8 @@ struct PulseDev {
   int64_t coeff_off;  // first coefficient (doubles)
   int64_t spec_off;   // first spectral record in the scratch spectra (4 doubles per line)
   int32_t nt, ns, order, nlines;
-  int32_t nmin, norm, stat_blocks, pad0;
+  int32_t nmin, norm, stat_blocks;
+  int32_t chk_off;    // first 256-step chunk of this pulse in the batch (table ranges per chunk)
   int32_t n[3];
   int64_t unit_off;   // first 64-mode reduction unit of this pulse in the batch
   int32_t nunits;
@@ -61,6 +63,7 @@ struct Batch {
   int64_t total_units = 0;
   int32_t total_items = 0;     // workgroups of the default evolution launch
   int32_t total_blocks = 0;    // series-selection blocks (kSelBlock modes, per pulse)
+  int32_t total_chunks = 0;    // kChunkSteps-step chunks of all pulses
   int32_t max_stat_blocks = 0; // largest per-pulse block count of the field statistics pass
   int32_t max_nt = 0;
   int32_t max_lines = 0;       // most spectral lines of any pulse
@@ -111,18 +114,22 @@ struct EvolveConfig {
   int mpl = 1;
   int persistent = 0;
 };
-// Per-block series selection of the second-order evolution (and of the yield gradient): x =
-// variant of kFineDegree (or kFineHalving), y = number of angle halvings, one int2 per kSelBlock
-// modes of each pulse (total_blocks).  The evolution launches below take this array; d_units
-// holds total_units doubles (one partial sum per 64 modes).
+// Per-block series selection of the yield gradient: x = variant of kFineDegree (or kFineHalving),
+// y = number of angle halvings, one int2 per kSelBlock modes of each pulse (total_blocks).
 po_status launch_block_select(const Batch& b, const PulseDev* d_desc, const double* d_A, int2* d_bsel,
                               hipStream_t s);
+// Range of the table per 256-step chunk of each pulse, d_ranges [total_chunks][4] = (min A_x,
+// max A_x, min A_y, max A_y); the second-order evolution picks its series variant per chunk and
+// selection block from it.  The evolution launches below take this array; d_units holds
+// total_units doubles (one partial sum per 64 modes).
+po_status launch_chunk_ranges(const Batch& b, const PulseDev* d_desc, const double* d_A, double* d_ranges,
+                              hipStream_t s);
 po_status launch_evolve_grid(const Batch& b, const PulseDev* d_desc, const double* d_A, const double* d_A_edge,
-                             const int2* d_bsel, double* d_f, double* d_units, hipStream_t s);
+                             const double* d_ranges, double* d_f, double* d_units, hipStream_t s);
 // Persistent launch: items are {pulse, first mode} pairs of cfg.threads * cfg.mpl modes each,
 // taken in queue order through the counter (reset on the stream before the launch).
 po_status launch_evolve_persistent(const EvolveConfig& cfg, int n_pulses, const PulseDev* d_desc, const double* d_A,
-                                   const double* d_A_edge, const int2* d_sel, const int2* d_queue, int n_items,
+                                   const double* d_A_edge, const double* d_ranges, const int2* d_queue, int n_items,
                                    int n_workgroups, int* d_counter, double* d_f, double* d_units, hipStream_t s);
 int evolve_workgroups_per_cu(const EvolveConfig& cfg);
 // Fourth-order (Magnus) evolution: series selection over both nodes of every step and one
@@ -142,12 +149,13 @@ po_status launch_yield_from_units(const Batch& b, const PulseDev* d_desc, const 
 po_status plan_evolve(const po_plan* plan, int32_t n, const po_pulse_spec* specs, const po_grid* grids,
                       const double* d_A, const double* d_edge, double* d_f, double* d_J, hipStream_t s);
 // Kernel timers (api.hip): start returns true (and records *e0) when timers are enabled;
-// timer_count enqueues the per-variant mode-step count of a block selection (no-op when disabled).
+// timer_count enqueues the per-variant mode-step count of an evolution launch from its chunk
+// ranges (no-op when disabled).
 constexpr int kSeriesVariants = 9;  // T series of degree 6..13, then the angle-halving path
 bool timer_start(hipStream_t s, hipEvent_t* e0);
 void timer_stop(hipStream_t s, hipEvent_t e0);
-po_status timer_count(int n_pulses, const PulseDev* d_desc, const int2* d_sel, hipStream_t s);
-po_status launch_count_mode_steps(int n_pulses, const PulseDev* d_desc, const int2* d_sel,
+po_status timer_count(int n_pulses, const PulseDev* d_desc, const double* d_ranges, hipStream_t s);
+po_status launch_count_mode_steps(int n_pulses, const PulseDev* d_desc, const double* d_ranges,
                                   unsigned long long* d_counts, hipStream_t s);
 
 po_status launch_de_propose(const po_de_params& p, int64_t gen, const double* d_pop, double* d_trial,

@@ -14,7 +14,7 @@
 namespace po {
 namespace {
 
-constexpr int kChunk = 256;   // steps staged per LDS buffer
+constexpr int kChunk = kChunkSteps;   // steps staged per LDS buffer
 
 constexpr double factorial(int n) { return n <= 1 ? 1.0 : double(n) * factorial(n - 1); }
 // Maclaurin coefficients of cos(sqrt x) and sin(sqrt x)/sqrt x.

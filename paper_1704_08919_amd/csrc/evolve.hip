@@ -19,9 +19,9 @@
 // For any value of T, 1 - i T Q_s is a scalar multiple of a unitary matrix (its square modulus
 // is (1 + T^2 x) 1), so rounding in T perturbs only the rotation angle.  T -- or C and S on the
 // large-step path, which halves the angle -- is a truncated Maclaurin series in x whose
-// remainder is below 2^-56 on the whole range of x of the 512-mode block the item belongs to (a
-// box of momenta against the range of the pulse's table); it is shared by both blocks, because
-// omega does not depend on s.
+// remainder is below 2^-56 on the whole range of x of the 512-mode block the item belongs to and
+// the 256-step chunk (a box of momenta against the range of the table in the chunk); it is shared
+// by both blocks, because omega does not depend on s.
 //
 // Work decomposition: a workgroup of THREADS lanes (64-wide waves) owns an item of
 // THREADS x MPL consecutive modes of one pulse, MPL modes per lane.  The pulse's table of -A dt
@@ -100,13 +100,95 @@ __global__ void __launch_bounds__(256) k_series_select(const PulseDev* __restric
   }
 }
 
-// Per block of kSelBlock consecutive modes of a pulse: bound on x = (omega dt)^2 over the block's
-// modes and every step,
-//   x <= dt^2 [ max|p_x - A_x|^2 + max|p_y - A_y|^2 + 1 + max p_z^2 ],
-// each maximum over the block's box of cell-centred momenta and the range of the pulse's table,
-// and the variant of kFineDegree it selects (x) with the number of angle halvings (y).  Items of
-// every launch shape lie inside one block, so each mode's arithmetic is still the same whatever
-// the launch.  One workgroup per pulse: the table's extremes, then one thread per block.
+// Box of cell-centred momenta of selection block b (kSelBlock consecutive modes) of a pulse:
+// [pxl, pxh] x [pyl, pyh] and the largest p_z^2.
+struct BlockBox {
+  double pxl, pxh, pyl, pyh, pz2;
+};
+
+__device__ __forceinline__ BlockBox block_box(const PulseDev& d, int b) {
+  const int nx = d.n[0], ny = d.n[1];
+  const int64_t nmodes = int64_t(nx) * ny * d.n[2];
+  const int64_t m0 = int64_t(b) * kSelBlock, m1 = min(m0 + kSelBlock, nmodes) - 1;
+  const int64_t r0 = m0 / nx, r1 = m1 / nx;  // rows (iy, iz)
+  const int64_t z0 = r0 / ny, z1 = r1 / ny;
+  const int ix0 = r0 == r1 ? int(m0 % nx) : 0, ix1 = r0 == r1 ? int(m1 % nx) : nx - 1;
+  const int iy0 = z0 == z1 ? int(r0 % ny) : 0, iy1 = z0 == z1 ? int(r1 % ny) : ny - 1;
+  const double px0 = d.lo[0] + (ix0 + 0.5) * d.dp[0], px1 = d.lo[0] + (ix1 + 0.5) * d.dp[0];
+  const double py0 = d.lo[1] + (iy0 + 0.5) * d.dp[1], py1 = d.lo[1] + (iy1 + 0.5) * d.dp[1];
+  const double pz0 = d.lo[2] + (z0 + 0.5) * d.dp[2], pz1 = d.lo[2] + (z1 + 0.5) * d.dp[2];
+  return BlockBox{fmin(px0, px1), fmax(px0, px1), fmin(py0, py1), fmax(py0, py1), fmax(pz0 * pz0, pz1 * pz1)};
+}
+
+// Series variant (x: index of kFineDegree or kFineHalving; y: angle halvings) for a block box
+// against a range [lx, hx] x [ly, hy] of table values: with the largest |p - A| per component,
+//   x = (omega dt)^2 <= dt^2 [ max|p_x - A_x|^2 + max|p_y - A_y|^2 + 1 + max p_z^2 ].
+__device__ __forceinline__ int2 choose_variant(const BlockBox& bb, double lx, double hx, double ly, double hy,
+                                               double dt) {
+  const double X = fmax(fmax(bb.pxh - lx, hx - bb.pxl), 0.0);
+  const double Y = fmax(fmax(bb.pyh - ly, hy - bb.pyl), 0.0);
+  const double xb = (X * X + Y * Y + 1.0 + bb.pz2) * dt * dt * (1.0 + 1e-6);
+  int mode = kFineHalving, h = 0;
+  for (int k = kNumFine - 1; k >= 0; --k)
+    if (xb <= kFineXmax[k]) mode = k;
+  if (mode == kFineHalving) {
+    double x = xb;
+    while (x > kCosSinXmax) {
+      x *= 0.25;
+      ++h;
+    }
+  }
+  return make_int2(mode, h);
+}
+
+// Variant of a block for the whole table (the union of its nchunks chunk ranges rg[c][4]).
+__device__ __forceinline__ int2 block_variant(const BlockBox& bb, const double* rg, int nchunks, double dt) {
+  double lx = rg[0], hx = rg[1], ly = rg[2], hy = rg[3];
+  for (int c = 1; c < nchunks; ++c) {
+    lx = fmin(lx, rg[4 * c]); hx = fmax(hx, rg[4 * c + 1]);
+    ly = fmin(ly, rg[4 * c + 2]); hy = fmax(hy, rg[4 * c + 3]);
+  }
+  return choose_variant(bb, lx, hx, ly, hy, dt);
+}
+
+// Variant of chunk c given the block's (bmode): the block's on the angle-halving path, else the
+// lower of the block's and the one for the chunk's own range (both cover the chunk's steps).
+__device__ __forceinline__ int chunk_mode(const BlockBox& bb, const double* rg, int c, int bmode, double dt) {
+  if (bmode == kFineHalving) return bmode;
+  return min(choose_variant(bb, rg[4 * c], rg[4 * c + 1], rg[4 * c + 2], rg[4 * c + 3], dt).x, bmode);
+}
+
+// Range (min A_x, max A_x, min A_y, max A_y) of the table over chunk blockIdx.x of pulse blockIdx.y.
+__global__ void __launch_bounds__(256) k_chunk_ranges(const PulseDev* __restrict__ desc, const double* __restrict__ A,
+                                                      double* __restrict__ ranges) {
+  const PulseDev d = desc[blockIdx.y];
+  const int c = blockIdx.x;
+  const int nchunks = (d.nt + kChunk - 1) / kChunk;
+  if (c >= nchunks) return;
+  const int n = c * kChunk + int(threadIdx.x);
+  double lx = INFINITY, hx = -INFINITY, ly = INFINITY, hy = -INFINITY;
+  if (n < d.nt) {
+    const double2 a = reinterpret_cast<const double2*>(A)[d.tab_off + n];
+    lx = hx = a.x;
+    ly = hy = a.y;
+  }
+  __shared__ double red[4][256];
+  red[0][threadIdx.x] = -lx; red[1][threadIdx.x] = hx; red[2][threadIdx.x] = -ly; red[3][threadIdx.x] = hy;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w)
+      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = fmax(red[k][threadIdx.x], red[k][threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) {
+    const double v = red[threadIdx.x][0];
+    ranges[4 * int64_t(d.chk_off + c) + threadIdx.x] = (threadIdx.x % 2 == 0) ? -v : v;
+  }
+}
+
+// Per block of kSelBlock consecutive modes of a pulse, the variant for the range of the whole
+// table (the yield gradient's choice).  Items of every launch shape lie inside one block.  One
+// workgroup per pulse: the table's extremes, then one thread per block.
 __global__ void __launch_bounds__(256) k_block_select(const PulseDev* __restrict__ desc, const double* __restrict__ A,
                                                       int2* __restrict__ bsel) {
   const PulseDev d = desc[blockIdx.x];
@@ -126,35 +208,10 @@ __global__ void __launch_bounds__(256) k_block_select(const PulseDev* __restrict
     __syncthreads();
   }
   const double axl = -red[0][0], axh = red[1][0], ayl = -red[2][0], ayh = red[3][0];
-  const int nx = d.n[0], ny = d.n[1];
-  const int64_t nmodes = int64_t(nx) * ny * d.n[2];
+  const int64_t nmodes = int64_t(d.n[0]) * d.n[1] * d.n[2];
   const int nblk = int((nmodes + kSelBlock - 1) / kSelBlock);
-  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
-    const int64_t m0 = int64_t(b) * kSelBlock, m1 = min(m0 + kSelBlock, nmodes) - 1;
-    const int64_t r0 = m0 / nx, r1 = m1 / nx;                      // rows (iy, iz)
-    const int64_t z0 = r0 / ny, z1 = r1 / ny;
-    const int ix0 = r0 == r1 ? int(m0 % nx) : 0, ix1 = r0 == r1 ? int(m1 % nx) : nx - 1;
-    const int iy0 = z0 == z1 ? int(r0 % ny) : 0, iy1 = z0 == z1 ? int(r1 % ny) : ny - 1;
-    const double pxl = d.lo[0] + (ix0 + 0.5) * d.dp[0], pxh = d.lo[0] + (ix1 + 0.5) * d.dp[0];
-    const double pyl = d.lo[1] + (iy0 + 0.5) * d.dp[1], pyh = d.lo[1] + (iy1 + 0.5) * d.dp[1];
-    const double pzl = d.lo[2] + (z0 + 0.5) * d.dp[2], pzh = d.lo[2] + (z1 + 0.5) * d.dp[2];
-    // largest |p - a| over p and a in their intervals
-    const double X = fmax(fmax(fmax(pxl, pxh) - axl, axh - fmin(pxl, pxh)), 0.0);
-    const double Y = fmax(fmax(fmax(pyl, pyh) - ayl, ayh - fmin(pyl, pyh)), 0.0);
-    const double Z = fmax(fabs(pzl), fabs(pzh));
-    const double xb = (X * X + Y * Y + 1.0 + Z * Z) * d.dt * d.dt * (1.0 + 1e-6);
-    int mode = kFineHalving, h = 0;
-    for (int k = kNumFine - 1; k >= 0; --k)
-      if (xb <= kFineXmax[k]) mode = k;
-    if (mode == kFineHalving) {
-      double x = xb;
-      while (x > kCosSinXmax) {
-        x *= 0.25;
-        ++h;
-      }
-    }
-    bsel[d.blk_off + b] = make_int2(mode, h);
-  }
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+    bsel[d.blk_off + b] = choose_variant(block_box(d, b), axl, axh, ayl, ayh, d.dt);
 }
 
 template <int MODE>  // MODE < kFineHalving: T series of degree kFineDegree[MODE]; else C, S with angle halving
@@ -169,25 +226,102 @@ struct EvolveArgs {
   int n_pulses;
   const double* A;
   const double* Aedge;
-  const int2* sel;  // per selection block (k_block_select)
+  const double* ranges;  // [total_chunks][4] table range per chunk (k_chunk_ranges)
   double* f;
   double* units;
 };
 
-// Evolves the item of THREADS * MPL modes of pulse pi starting at mode `first`, writes f and the
-// 64-mode unit sums.  Every lane of the workgroup must call it (it contains barriers).
-template <int MODE, int THREADS, int MPL>
-__device__ __forceinline__ void process_item(const EvolveArgs& a, int pi, int first, int h, double2 (*lds)[kChunk]) {
+// Steps of one chunk (len records of buf) in series variant MODE for the MPL modes of a lane; the
+// tangent form then rescales the states by exact powers of two.
+template <int MODE, int MPL>
+__device__ __forceinline__ void run_chunk(State (&v)[MPL], const double2* buf, int len, const double (&pxdt)[MPL],
+                                          const double (&pydt)[MPL], const double (&qz)[MPL], const double (&qz2)[MPL],
+                                          int h) {
+  const double inv4h = ldexp(1.0, -2 * h);
+  if (len == kChunk) {
+#pragma unroll(MPL == 1 ? 4 : 2)
+    for (int k = 0; k < kChunk; ++k) {
+      const double2 rec = buf[k];
+#pragma unroll
+      for (int j = 0; j < MPL; ++j) one_step<MODE>(v[j], rec, pxdt[j], pydt[j], qz[j], qz2[j], h, inv4h);
+    }
+  } else {
+    for (int k = 0; k < len; ++k) {
+      const double2 rec = buf[k];
+#pragma unroll
+      for (int j = 0; j < MPL; ++j) one_step<MODE>(v[j], rec, pxdt[j], pydt[j], qz[j], qz2[j], h, inv4h);
+    }
+  }
+  if constexpr (MODE < kFineHalving) {
+#pragma unroll
+    for (int j = 0; j < MPL; ++j) renormalise(v[j]);
+  }
+}
+
+// The chunks of an item: table records staged through LDS (double-buffered, one barrier per
+// chunk) and the steps of each chunk in its variant -- the block's on the angle-halving path
+// (HALVING), else the lower of the block's and the one for the chunk's own table range.
+template <bool HALVING, int THREADS, int MPL>
+__device__ __forceinline__ void chunk_loop(State (&v)[MPL], const double2* tab, int nt, double dt, const double* rg,
+                                           const BlockBox& bb, int bmode, int bh, const double (&pxdt)[MPL],
+                                           const double (&pydt)[MPL], const double (&qz)[MPL],
+                                           const double (&qz2)[MPL], double2 (*lds)[kChunk]) {
   constexpr int kPre = kChunk / THREADS;  // table records each lane stages per chunk
+  const int nchunks = (nt + kChunk - 1) / kChunk;
+#pragma unroll
+  for (int r = 0; r < kPre; ++r) {
+    const int n = r * THREADS + threadIdx.x;
+    const double2 t = n < nt ? tab[n] : make_double2(0.0, 0.0);
+    lds[0][n] = make_double2(-t.x * dt, -t.y * dt);
+  }
+  __syncthreads();
+  for (int c = 0; c < nchunks; ++c) {
+    double2 pre[kPre];
+#pragma unroll
+    for (int r = 0; r < kPre; ++r) {
+      const int n = (c + 1) * kChunk + r * THREADS + threadIdx.x;
+      pre[r] = (c + 1 < nchunks && n < nt) ? tab[n] : make_double2(0.0, 0.0);
+    }
+    const double2* buf = lds[c & 1];
+    const int len = min(kChunk, nt - c * kChunk);
+    if constexpr (HALVING) {
+      run_chunk<kFineHalving, MPL>(v, buf, len, pxdt, pydt, qz, qz2, bh);
+    } else {
+      const int mode = __builtin_amdgcn_readfirstlane(chunk_mode(bb, rg, c, bmode, dt));
+      switch (mode) {
+        case 0: run_chunk<0, MPL>(v, buf, len, pxdt, pydt, qz, qz2, 0); break;
+        case 1: run_chunk<1, MPL>(v, buf, len, pxdt, pydt, qz, qz2, 0); break;
+        case 2: run_chunk<2, MPL>(v, buf, len, pxdt, pydt, qz, qz2, 0); break;
+        case 3: run_chunk<3, MPL>(v, buf, len, pxdt, pydt, qz, qz2, 0); break;
+        case 4: run_chunk<4, MPL>(v, buf, len, pxdt, pydt, qz, qz2, 0); break;
+        case 5: run_chunk<5, MPL>(v, buf, len, pxdt, pydt, qz, qz2, 0); break;
+        case 6: run_chunk<6, MPL>(v, buf, len, pxdt, pydt, qz, qz2, 0); break;
+        default: run_chunk<7, MPL>(v, buf, len, pxdt, pydt, qz, qz2, 0); break;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < kPre; ++r)
+      lds[(c + 1) & 1][r * THREADS + threadIdx.x] = make_double2(-pre[r].x * dt, -pre[r].y * dt);
+    __syncthreads();
+  }
+}
+
+// Evolves the item of THREADS * MPL modes of pulse pi starting at mode `first`, writes f and the
+// 64-mode unit sums.  Every lane of the workgroup must call it (it contains barriers).  The
+// series variant is chosen from the item's selection block (items never straddle blocks) and the
+// table ranges, so it depends only on the pulse, the block and the chunk, never on the launch.
+template <int THREADS, int MPL>
+__device__ __forceinline__ void process_item(const EvolveArgs& a, int pi, int first, double2 (*lds)[kChunk]) {
   const PulseDev& d = a.desc[pi];
   const int nt = d.nt;
   const double dt = d.dt;
   const int nx = d.n[0], ny = d.n[1];
   const int64_t nmodes = int64_t(nx) * ny * d.n[2];
-  const double inv4h = ldexp(1.0, -2 * h);
   const double2* tab = reinterpret_cast<const double2*>(a.A) + d.tab_off;
   const double2* edge = reinterpret_cast<const double2*>(a.Aedge) + 2 * pi;
   const double2 ain = edge[0];
+  const BlockBox bb = block_box(d, first / kSelBlock);
+  const double* rg = a.ranges + 4 * int64_t(d.chk_off);
 
   State v[MPL];
   double pxdt[MPL], pydt[MPL], qz[MPL], qz2[MPL];
@@ -207,46 +341,14 @@ __device__ __forceinline__ void process_item(const EvolveArgs& a, int pi, int fi
     qz2[j] = qz[j] * qz[j];
   }
 
-  const int nchunks = (nt + kChunk - 1) / kChunk;
-#pragma unroll
-  for (int r = 0; r < kPre; ++r) {
-    const int n = r * THREADS + threadIdx.x;
-    const double2 t = n < nt ? tab[n] : make_double2(0.0, 0.0);
-    lds[0][n] = make_double2(-t.x * dt, -t.y * dt);
-  }
-  __syncthreads();
-  for (int c = 0; c < nchunks; ++c) {
-    double2 pre[kPre];
-#pragma unroll
-    for (int r = 0; r < kPre; ++r) {
-      const int n = (c + 1) * kChunk + r * THREADS + threadIdx.x;
-      pre[r] = (c + 1 < nchunks && n < nt) ? tab[n] : make_double2(0.0, 0.0);
-    }
-    const double2* buf = lds[c & 1];
-    const int len = min(kChunk, nt - c * kChunk);
-    if (len == kChunk) {
-#pragma unroll(MPL == 1 ? 4 : 2)
-      for (int k = 0; k < kChunk; ++k) {
-        const double2 rec = buf[k];
-#pragma unroll
-        for (int j = 0; j < MPL; ++j) one_step<MODE>(v[j], rec, pxdt[j], pydt[j], qz[j], qz2[j], h, inv4h);
-      }
-    } else {
-      for (int k = 0; k < len; ++k) {
-        const double2 rec = buf[k];
-#pragma unroll
-        for (int j = 0; j < MPL; ++j) one_step<MODE>(v[j], rec, pxdt[j], pydt[j], qz[j], qz2[j], h, inv4h);
-      }
-    }
-    if constexpr (MODE < kFineHalving) {
-#pragma unroll
-      for (int j = 0; j < MPL; ++j) renormalise(v[j]);
-    }
-#pragma unroll
-    for (int r = 0; r < kPre; ++r)
-      lds[(c + 1) & 1][r * THREADS + threadIdx.x] = make_double2(-pre[r].x * dt, -pre[r].y * dt);
-    __syncthreads();
-  }
+  // The block's variant for the whole table: on the angle-halving path it is kept for every
+  // chunk; otherwise each chunk takes the lower of it and its own (chunk_mode).
+  const int2 bs = block_variant(bb, rg, (nt + kChunk - 1) / kChunk, dt);
+  const int bmode = __builtin_amdgcn_readfirstlane(bs.x), bh = __builtin_amdgcn_readfirstlane(bs.y);
+  if (bmode == kFineHalving)
+    chunk_loop<true, THREADS, MPL>(v, tab, nt, dt, rg, bb, bmode, bh, pxdt, pydt, qz, qz2, lds);
+  else
+    chunk_loop<false, THREADS, MPL>(v, tab, nt, dt, rg, bb, bmode, 0, pxdt, pydt, qz, qz2, lds);
 
   const double2 aout = edge[1];
 #pragma unroll
@@ -271,29 +373,12 @@ __device__ __forceinline__ void process_item(const EvolveArgs& a, int pi, int fi
   }
 }
 
-// The item's variant is that of the selection block holding it (items never straddle blocks).
-template <int THREADS, int MPL>
-__device__ __forceinline__ void dispatch_item(const EvolveArgs& a, int pi, int first, double2 (*lds)[kChunk]) {
-  const int2 sl = a.sel[a.desc[pi].blk_off + first / kSelBlock];
-  switch (sl.x) {
-    case 0: process_item<0, THREADS, MPL>(a, pi, first, 0, lds); break;
-    case 1: process_item<1, THREADS, MPL>(a, pi, first, 0, lds); break;
-    case 2: process_item<2, THREADS, MPL>(a, pi, first, 0, lds); break;
-    case 3: process_item<3, THREADS, MPL>(a, pi, first, 0, lds); break;
-    case 4: process_item<4, THREADS, MPL>(a, pi, first, 0, lds); break;
-    case 5: process_item<5, THREADS, MPL>(a, pi, first, 0, lds); break;
-    case 6: process_item<6, THREADS, MPL>(a, pi, first, 0, lds); break;
-    case 7: process_item<7, THREADS, MPL>(a, pi, first, 0, lds); break;
-    default: process_item<kFineHalving, THREADS, MPL>(a, pi, first, sl.y, lds); break;
-  }
-}
-
 // One workgroup per 256-mode item.
 __global__ void __launch_bounds__(kItem) k_evolve(EvolveArgs a) {
   __shared__ double2 lds[2][kChunk];
   const int item = xcd_item(blockIdx.x, gridDim.x);
   const int pi = find_pulse_item(a.desc, a.n_pulses, item);
-  dispatch_item<kItem, 1>(a, pi, (item - a.desc[pi].item_off) * kItem, lds);
+  process_item<kItem, 1>(a, pi, (item - a.desc[pi].item_off) * kItem, lds);
 }
 
 __global__ void k_reset_counter(int* counter) { *counter = 0; }
@@ -313,7 +398,7 @@ k_evolve_persistent(EvolveArgs a, const int2* __restrict__ queue, int n_items, i
     __syncthreads();
     if (item >= n_items) break;
     const int2 q = queue[item];
-    dispatch_item<THREADS, MPL>(a, q.x, q.y, lds);
+    process_item<THREADS, MPL>(a, q.x, q.y, lds);
   }
 }
 
@@ -342,18 +427,28 @@ __global__ void __launch_bounds__(256) k_yield(const PulseDev* __restrict__ desc
   if (threadIdx.x == 0) J[blockIdx.x] = s * d.dv;
 }
 
-// Diagnostics: adds modes x nt of every selection block to the count of the variant it selected.
+// Diagnostics: adds modes x steps of every (selection block, chunk) of every pulse to the count
+// of the variant the evolution chose for it (the same block_variant and chunk_mode).
 __global__ void __launch_bounds__(256) k_count_mode_steps(const PulseDev* __restrict__ desc, int n,
-                                                          const int2* __restrict__ bsel,
+                                                          const double* __restrict__ ranges,
                                                           unsigned long long* __restrict__ counts) {
   for (int i = 0; i < n; ++i) {
     const PulseDev& d = desc[i];
     const int64_t nmodes = int64_t(d.n[0]) * d.n[1] * d.n[2];
     const int nblk = int((nmodes + kSelBlock - 1) / kSelBlock);
+    const int nch = (d.nt + kChunk - 1) / kChunk;
+    const double* rg = ranges + 4 * int64_t(d.chk_off);
     for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
-      const int64_t m = min(int64_t(kSelBlock), nmodes - int64_t(b) * kSelBlock);
-      atomicAdd(&counts[min(max(bsel[d.blk_off + b].x, 0), kSeriesVariants - 1)],
-                (unsigned long long)m * (unsigned long long)d.nt);
+      const BlockBox bb = block_box(d, b);
+      const unsigned long long mb = (unsigned long long)min(int64_t(kSelBlock), nmodes - int64_t(b) * kSelBlock);
+      unsigned long long local[kSeriesVariants] = {};
+      const int bmode = block_variant(bb, rg, nch, d.dt).x;
+      for (int c = 0; c < nch; ++c) {
+        const int mode = chunk_mode(bb, rg, c, bmode, d.dt);
+        local[min(max(mode, 0), kSeriesVariants - 1)] += mb * (unsigned long long)min(kChunk, d.nt - c * kChunk);
+      }
+      for (int k = 0; k < kSeriesVariants; ++k)
+        if (local[k]) atomicAdd(&counts[k], local[k]);
     }
   }
 }
@@ -514,9 +609,17 @@ po_status launch_block_select(const Batch& b, const PulseDev* d_desc, const doub
   return PO_OK;
 }
 
+po_status launch_chunk_ranges(const Batch& b, const PulseDev* d_desc, const double* d_A, double* d_ranges,
+                              hipStream_t s) {
+  const int max_chunks = (b.max_nt + kChunk - 1) / kChunk;
+  hipLaunchKernelGGL(k_chunk_ranges, dim3(max_chunks, b.n_pulses), dim3(256), 0, s, d_desc, d_A, d_ranges);
+  PO_HIP(hipGetLastError());
+  return PO_OK;
+}
+
 po_status launch_evolve_grid(const Batch& b, const PulseDev* d_desc, const double* d_A, const double* d_A_edge,
-                             const int2* d_sel, double* d_f, double* d_units, hipStream_t s) {
-  EvolveArgs a{d_desc, b.n_pulses, d_A, d_A_edge, d_sel, d_f, d_units};
+                             const double* d_ranges, double* d_f, double* d_units, hipStream_t s) {
+  EvolveArgs a{d_desc, b.n_pulses, d_A, d_A_edge, d_ranges, d_f, d_units};
   hipLaunchKernelGGL(k_evolve, dim3(b.total_items), dim3(kItem), 0, s, a);
   PO_HIP(hipGetLastError());
   return PO_OK;
@@ -530,9 +633,9 @@ int evolve_workgroups_per_cu(const EvolveConfig& cfg) {
 }
 
 po_status launch_evolve_persistent(const EvolveConfig& cfg, int n_pulses, const PulseDev* d_desc, const double* d_A,
-                                   const double* d_A_edge, const int2* d_sel, const int2* d_queue, int n_items,
+                                   const double* d_A_edge, const double* d_ranges, const int2* d_queue, int n_items,
                                    int n_workgroups, int* d_counter, double* d_f, double* d_units, hipStream_t s) {
-  EvolveArgs a{d_desc, n_pulses, d_A, d_A_edge, d_sel, d_f, d_units};
+  EvolveArgs a{d_desc, n_pulses, d_A, d_A_edge, d_ranges, d_f, d_units};
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, d_counter);
   PO_HIP(hipGetLastError());
   const int key = cfg.threads * 10 + cfg.mpl;
@@ -549,9 +652,9 @@ po_status launch_evolve_persistent(const EvolveConfig& cfg, int n_pulses, const 
   return PO_OK;
 }
 
-po_status launch_count_mode_steps(int n_pulses, const PulseDev* d_desc, const int2* d_sel,
+po_status launch_count_mode_steps(int n_pulses, const PulseDev* d_desc, const double* d_ranges,
                                   unsigned long long* d_counts, hipStream_t s) {
-  hipLaunchKernelGGL(k_count_mode_steps, dim3(1), dim3(256), 0, s, d_desc, n_pulses, d_sel, d_counts);
+  hipLaunchKernelGGL(k_count_mode_steps, dim3(1), dim3(256), 0, s, d_desc, n_pulses, d_ranges, d_counts);
   PO_HIP(hipGetLastError());
   return PO_OK;
 }

@@ -25,7 +25,7 @@ struct po_plan {
   PulseDev* d_desc = nullptr;
   int2* d_queue = nullptr;
   int* d_counter = nullptr;
-  int2* d_sel = nullptr;
+  double* d_ranges = nullptr;  // table range per chunk
   double* d_units = nullptr;
   double* d_A = nullptr;
   double* d_edge = nullptr;
@@ -47,7 +47,7 @@ namespace {
 void free_all(po_plan* p) {
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
-  void* bufs[] = {p->d_desc, p->d_queue, p->d_counter, p->d_sel, p->d_units, p->d_A, p->d_edge,
+  void* bufs[] = {p->d_desc, p->d_queue, p->d_counter, p->d_ranges, p->d_units, p->d_A, p->d_edge,
                   p->d_spec, p->d_part, p->d_scale, p->d_probe, p->d_Jprobe};
   for (void* q : bufs)
     if (q) (void)hipFree(q);
@@ -102,13 +102,13 @@ po_status enqueue(po_plan* p, const double* d_coeff, const double* d_A, const do
     d_A = p->d_A;
     d_edge = p->d_edge;
   }
-  PO_TRY(launch_block_select(p->b, p->d_desc, d_A, p->d_sel, s));
+  PO_TRY(launch_chunk_ranges(p->b, p->d_desc, d_A, p->d_ranges, s));
   double* units = d_J ? p->d_units : nullptr;
   if (p->cfg.persistent)
-    PO_TRY(launch_evolve_persistent(p->cfg, p->n, p->d_desc, d_A, d_edge, p->d_sel, p->d_queue, p->n_items,
+    PO_TRY(launch_evolve_persistent(p->cfg, p->n, p->d_desc, d_A, d_edge, p->d_ranges, p->d_queue, p->n_items,
                                     p->workgroups, p->d_counter, d_f, units, s));
   else
-    PO_TRY(launch_evolve_grid(p->b, p->d_desc, d_A, d_edge, p->d_sel, d_f, units, s));
+    PO_TRY(launch_evolve_grid(p->b, p->d_desc, d_A, d_edge, p->d_ranges, d_f, units, s));
   if (d_J) PO_TRY(launch_yield_from_units(p->b, p->d_desc, p->d_units, d_J, s));
   return PO_OK;
 }
@@ -220,7 +220,7 @@ po_status plan_create(int32_t n, const po_pulse_spec* specs, const po_grid* grid
   PO_TRY(dalloc(&p->d_desc, n));
   PO_HIP(hipMemcpy(p->d_desc, p->h_desc.data(), sizeof(PulseDev) * n, hipMemcpyHostToDevice));
   PO_TRY(dalloc(&p->d_counter, 1));
-  PO_TRY(dalloc(&p->d_sel, size_t(p->b.total_blocks)));
+  PO_TRY(dalloc(&p->d_ranges, 4 * size_t(p->b.total_chunks)));
   PO_TRY(dalloc(&p->d_units, size_t(p->b.total_units)));
   PO_TRY(dalloc(&p->d_A, size_t(2 * p->b.total_rows)));
   PO_TRY(dalloc(&p->d_edge, size_t(4 * n)));
@@ -287,7 +287,7 @@ po_status plan_evolve(const po_plan* cp, int32_t n, const po_pulse_spec* specs, 
   po_plan* p = const_cast<po_plan*>(cp);
   PO_TRY(check_plan_match(p, n, specs, grids));
   PO_TRY(enqueue(p, nullptr, d_A, d_edge, d_J, d_f, s));
-  return timer_count(p->n, p->d_desc, p->d_sel, s);
+  return timer_count(p->n, p->d_desc, p->d_ranges, s);
 }
 
 bool plan_matches(const po_plan* p, int32_t n, const po_pulse_spec* specs, const po_grid* grids) {
@@ -367,7 +367,7 @@ po_status po_plan_evaluate(struct po_plan* p, const double* d_coeff, double* d_J
   PO_HIP(hipGraphLaunch(p->exec, s));
   if (timed) {
     timer_stop(s, e0);
-    PO_TRY(timer_count(p->n, p->d_desc, p->d_sel, s));
+    PO_TRY(timer_count(p->n, p->d_desc, p->d_ranges, s));
   }
   return PO_OK;
 }
