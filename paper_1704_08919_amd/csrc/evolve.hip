@@ -429,27 +429,26 @@ __global__ void __launch_bounds__(256) k_yield(const PulseDev* __restrict__ desc
 
 // Diagnostics: adds modes x steps of every (selection block, chunk) of every pulse to the count
 // of the variant the evolution chose for it (the same block_variant and chunk_mode).
-__global__ void __launch_bounds__(256) k_count_mode_steps(const PulseDev* __restrict__ desc, int n,
+// One workgroup per pulse, one thread per block.
+__global__ void __launch_bounds__(256) k_count_mode_steps(const PulseDev* __restrict__ desc,
                                                           const double* __restrict__ ranges,
                                                           unsigned long long* __restrict__ counts) {
-  for (int i = 0; i < n; ++i) {
-    const PulseDev& d = desc[i];
-    const int64_t nmodes = int64_t(d.n[0]) * d.n[1] * d.n[2];
-    const int nblk = int((nmodes + kSelBlock - 1) / kSelBlock);
-    const int nch = (d.nt + kChunk - 1) / kChunk;
-    const double* rg = ranges + 4 * int64_t(d.chk_off);
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
-      const BlockBox bb = block_box(d, b);
-      const unsigned long long mb = (unsigned long long)min(int64_t(kSelBlock), nmodes - int64_t(b) * kSelBlock);
-      unsigned long long local[kSeriesVariants] = {};
-      const int bmode = block_variant(bb, rg, nch, d.dt).x;
-      for (int c = 0; c < nch; ++c) {
-        const int mode = chunk_mode(bb, rg, c, bmode, d.dt);
-        local[min(max(mode, 0), kSeriesVariants - 1)] += mb * (unsigned long long)min(kChunk, d.nt - c * kChunk);
-      }
-      for (int k = 0; k < kSeriesVariants; ++k)
-        if (local[k]) atomicAdd(&counts[k], local[k]);
+  const PulseDev& d = desc[blockIdx.x];
+  const int64_t nmodes = int64_t(d.n[0]) * d.n[1] * d.n[2];
+  const int nblk = int((nmodes + kSelBlock - 1) / kSelBlock);
+  const int nch = (d.nt + kChunk - 1) / kChunk;
+  const double* rg = ranges + 4 * int64_t(d.chk_off);
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+    const BlockBox bb = block_box(d, b);
+    const unsigned long long mb = (unsigned long long)min(int64_t(kSelBlock), nmodes - int64_t(b) * kSelBlock);
+    unsigned long long local[kSeriesVariants] = {};
+    const int bmode = block_variant(bb, rg, nch, d.dt).x;
+    for (int c = 0; c < nch; ++c) {
+      const int mode = chunk_mode(bb, rg, c, bmode, d.dt);
+      local[min(max(mode, 0), kSeriesVariants - 1)] += mb * (unsigned long long)min(kChunk, d.nt - c * kChunk);
     }
+    for (int k = 0; k < kSeriesVariants; ++k)
+      if (local[k]) atomicAdd(&counts[k], local[k]);
   }
 }
 
@@ -654,7 +653,7 @@ po_status launch_evolve_persistent(const EvolveConfig& cfg, int n_pulses, const 
 
 po_status launch_count_mode_steps(int n_pulses, const PulseDev* d_desc, const double* d_ranges,
                                   unsigned long long* d_counts, hipStream_t s) {
-  hipLaunchKernelGGL(k_count_mode_steps, dim3(1), dim3(256), 0, s, d_desc, n_pulses, d_ranges, d_counts);
+  hipLaunchKernelGGL(k_count_mode_steps, dim3(n_pulses), dim3(256), 0, s, d_desc, d_ranges, d_counts);
   PO_HIP(hipGetLastError());
   return PO_OK;
 }
