@@ -24,6 +24,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 128 FLOP/clk x 2.4 GHz
+# The fixed per-mode-step count of a degree-8 cos/sin step (C - i S Q on two blocks), kept beside
+# the count of the step actually required for reference.
+FIXED_FLOP_PER_MODE_STEP = 97
 # FP64 operations of one mode-step per series variant of the evolution kernel (an FMA counts 2).
 # tan(theta)/theta series of degree n: q (2 adds), x = |q|^2 (2 FMA), the series (n FMA), T q
 # (3 mul), and 1 - i T Q on two 2x2 blocks (8 real components x 3 FMA) = 57 + 2n.
@@ -47,6 +50,19 @@ def evolve_sources_sha256():
         with open(os.path.join(ROOT, "paper_1704_08919_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def fp64_counter_record():
+    """Measured FP64 work of one evolution call (rocprof counters) from the committed record, if
+    taken on the evolution kernel's sources as they are now (else None)."""
+    path = os.path.join(HERE_PROFILES, "k_evolve_fp64_counters_de_generation.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+        sha = evolve_sources_sha256()
+    except OSError:
+        return None
+    return rec if rec.get("evolve_sources_sha256") == sha else None
 
 
 def hbm_traffic_record():
@@ -333,8 +349,8 @@ def main():
                     help="run a plain 512 MiB device copy first (reference for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU layout is a design "
-              "note, not a build target", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the library has no multi-GPU path",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -383,6 +399,7 @@ def main():
     flops = sum(FLOP_PER_MODE_STEP[k] * v for k, v in by_series.items())
     achieved = flops / (evolve_ms / 1e3) / 1e12
     traffic = hbm_traffic_record()
+    measured = fp64_counter_record()
     best = float(fit.max().item())
     out = {
         "metric": "mode-steps/s (FP64)",
@@ -408,7 +425,11 @@ def main():
                      "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": traffic["bytes_per_call"] if traffic else None,
                      "kernel": "k_evolve (per-mode evolution + projection)",
-                     "flop_per_mode_step_avg": flops / counted, "mode_steps_by_series": by_series},
+                     "flop_per_mode_step_avg": flops / counted, "mode_steps_by_series": by_series,
+                     "flop_per_mode_step_measured": measured["flop_per_mode_step"] if measured else None,
+                     "fp64_issue_frac": (measured["fp64_instr_per_mode_step"] * mode_steps / ev_s
+                                         / (FP64_PEAK_TFLOPS * 1e12 / 2)) if measured else None,
+                     "achieved_at_fixed_97_flop": FIXED_FLOP_PER_MODE_STEP * mode_steps / ev_s / 1e12},
     }
     if not args.no_uneven:
         out["uneven_batch"] = guarded(uneven_batch, api, W, torch, mode_steps / ev_s)
