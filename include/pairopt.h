@@ -120,7 +120,9 @@ po_status po_pulse_synth(int32_t n_pulses, const po_pulse_spec* specs, const dou
  * (second-order, unitary).  The Hamiltonian splits into two 2x2 blocks that are evolved
  * separately and f is their sum, f in [0, 2].
  *  specs     only nt and T are read (dt = T / nt).
- *  d_A       [sum nt][2] double: A at the step midpoints.
+ *  d_A       [sum nt][2] double: A at the step midpoints.  The tables are not checked on the
+ *            host: a non-finite or absurdly large entry (|A dt| beyond ~2^60) gives non-finite or
+ *            meaningless f and J, and the call still completes.
  *  d_A_edge  [n_pulses][2][2] double: A(t_i) (initial state) and A(t_f) (projection).
  *  d_f       out [sum M] double or NULL: f(t_f, p) per mode.
  *  d_J       out [n_pulses] double or NULL: J = Delta V sum_p f (Sec. IV A, Eq. opt_prob).

@@ -47,6 +47,7 @@ constexpr int kNumTan = 4;
 constexpr int kTanDegree[kNumTan] = {6, 8, 10, 13};
 constexpr double kTanXmax[kNumTan] = {0.0099, 0.0337, 0.0735, 0.1558};
 constexpr double kCosSinXmax = 0.3612;
+constexpr int kMaxHalvings = 60;  // x up to 0.3612 * 4^60 ~ 5e35; beyond (or non-finite) the choice stops here
 constexpr int kHalvingMode = kNumTan;
 constexpr int kNumModes = kNumTan + 1;
 // Every degree from 6 to 13, for the per-block choice of the second-order evolution (same remainder

@@ -91,7 +91,7 @@ __global__ void __launch_bounds__(256) k_series_select(const PulseDev* __restric
       if (xb <= kTanXmax[k]) mode = k;
     if (mode == kHalvingMode) {
       double x = xb;
-      while (x > kCosSinXmax) {
+      while (x > kCosSinXmax && h < kMaxHalvings) {
         x *= 0.25;
         ++h;
       }
@@ -133,7 +133,7 @@ __device__ __forceinline__ int2 choose_variant(const BlockBox& bb, double lx, do
     if (xb <= kFineXmax[k]) mode = k;
   if (mode == kFineHalving) {
     double x = xb;
-    while (x > kCosSinXmax) {
+    while (x > kCosSinXmax && h < kMaxHalvings) {
       x *= 0.25;
       ++h;
     }

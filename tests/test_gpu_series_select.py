@@ -93,3 +93,21 @@ def test_variants_follow_the_table_range():
     spec, grid, seed = CASES["weak_sheet"]
     A, counts = run_counts(spec, grid, W.draw_coeff(seed, 1, spec["n_s"]))
     assert np.count_nonzero(counts) > 1
+
+
+def test_non_finite_and_huge_tables_complete():
+    # an infinite and an absurdly large table entry: the series choice stops at its cap, the call
+    # returns and the affected pulses give non-finite J, the others are unaffected
+    spec, grid, seed = CASES["box"]
+    specs = [spec] * 3
+    A, edge, _, _ = api.synth(specs, W.draw_coeff(seed, 3, spec["n_s"]))
+    _, J0 = api.evolve(specs, [grid] * 3, A, edge, want_f=False)
+    nt = spec["nt"]
+    A[nt + 5, 0] = float("inf")
+    A[2 * nt + 7, 1] = 1e200
+    _, J = api.evolve(specs, [grid] * 3, A, edge, want_f=False)
+    J, J0 = J.cpu().numpy(), J0.cpu().numpy()
+    say(f"J with bad tables {J}, clean {J0}")
+    assert J[0] == J0[0]
+    assert not np.isfinite(J[1])
+    assert not np.isfinite(J[2]) or abs(J[2] - J0[2]) > 1e-3 * abs(J0[2])
