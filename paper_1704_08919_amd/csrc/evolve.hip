@@ -151,11 +151,15 @@ __device__ __forceinline__ int2 block_variant(const BlockBox& bb, const double* 
   return choose_variant(bb, lx, hx, ly, hy, dt);
 }
 
-// Variant of chunk c given the block's (bmode): the block's on the angle-halving path, else the
-// lower of the block's and the one for the chunk's own range (both cover the chunk's steps).
-__device__ __forceinline__ int chunk_mode(const BlockBox& bb, const double* rg, int c, int bmode, double dt) {
-  if (bmode == kFineHalving) return bmode;
-  return min(choose_variant(bb, rg[4 * c], rg[4 * c + 1], rg[4 * c + 2], rg[4 * c + 3], dt).x, bmode);
+// Variant of chunk c given the block's (bmode).  A block within the T-series range: the lower of
+// the block's variant and the one for the chunk's own range (both cover the chunk's steps).  A
+// block on the angle-halving path: its chunks take that path with their own number of halvings,
+// or, when their own range allows any T series, the degree-13 one (two code paths only, so the
+// loop keeps to its register budget).
+__device__ __forceinline__ int2 chunk_variant(const BlockBox& bb, const double* rg, int c, int bmode, double dt) {
+  const int2 own = choose_variant(bb, rg[4 * c], rg[4 * c + 1], rg[4 * c + 2], rg[4 * c + 3], dt);
+  if (bmode == kFineHalving) return own.x == kFineHalving ? own : make_int2(kNumFine - 1, 0);
+  return make_int2(min(own.x, bmode), 0);
 }
 
 // Range (min A_x, max A_x, min A_y, max A_y) of the table over chunk blockIdx.x of pulse blockIdx.y.
@@ -259,11 +263,11 @@ __device__ __forceinline__ void run_chunk(State (&v)[MPL], const double2* buf, i
 }
 
 // The chunks of an item: table records staged through LDS (double-buffered, one barrier per
-// chunk) and the steps of each chunk in its variant -- the block's on the angle-halving path
-// (HALVING), else the lower of the block's and the one for the chunk's own table range.
+// chunk) and the steps of each chunk in its variant (chunk_variant); HALVING: the block's own
+// variant is the angle-halving path.
 template <bool HALVING, int THREADS, int MPL>
 __device__ __forceinline__ void chunk_loop(State (&v)[MPL], const double2* tab, int nt, double dt, const double* rg,
-                                           const BlockBox& bb, int bmode, int bh, const double (&pxdt)[MPL],
+                                           const BlockBox& bb, int bmode, const double (&pxdt)[MPL],
                                            const double (&pydt)[MPL], const double (&qz)[MPL],
                                            const double (&qz2)[MPL], double2 (*lds)[kChunk]) {
   constexpr int kPre = kChunk / THREADS;  // table records each lane stages per chunk
@@ -284,10 +288,14 @@ __device__ __forceinline__ void chunk_loop(State (&v)[MPL], const double2* tab, 
     }
     const double2* buf = lds[c & 1];
     const int len = min(kChunk, nt - c * kChunk);
+    const int2 cv = chunk_variant(bb, rg, c, bmode, dt);
+    const int mode = __builtin_amdgcn_readfirstlane(cv.x);
     if constexpr (HALVING) {
-      run_chunk<kFineHalving, MPL>(v, buf, len, pxdt, pydt, qz, qz2, bh);
+      if (mode == kFineHalving)
+        run_chunk<kFineHalving, MPL>(v, buf, len, pxdt, pydt, qz, qz2, __builtin_amdgcn_readfirstlane(cv.y));
+      else
+        run_chunk<kNumFine - 1, MPL>(v, buf, len, pxdt, pydt, qz, qz2, 0);
     } else {
-      const int mode = __builtin_amdgcn_readfirstlane(chunk_mode(bb, rg, c, bmode, dt));
       switch (mode) {
         case 0: run_chunk<0, MPL>(v, buf, len, pxdt, pydt, qz, qz2, 0); break;
         case 1: run_chunk<1, MPL>(v, buf, len, pxdt, pydt, qz, qz2, 0); break;
@@ -341,14 +349,12 @@ __device__ __forceinline__ void process_item(const EvolveArgs& a, int pi, int fi
     qz2[j] = qz[j] * qz[j];
   }
 
-  // The block's variant for the whole table: on the angle-halving path it is kept for every
-  // chunk; otherwise each chunk takes the lower of it and its own (chunk_mode).
-  const int2 bs = block_variant(bb, rg, (nt + kChunk - 1) / kChunk, dt);
-  const int bmode = __builtin_amdgcn_readfirstlane(bs.x), bh = __builtin_amdgcn_readfirstlane(bs.y);
+  // The block's variant for the whole table bounds its chunks' (chunk_variant).
+  const int bmode = __builtin_amdgcn_readfirstlane(block_variant(bb, rg, (nt + kChunk - 1) / kChunk, dt).x);
   if (bmode == kFineHalving)
-    chunk_loop<true, THREADS, MPL>(v, tab, nt, dt, rg, bb, bmode, bh, pxdt, pydt, qz, qz2, lds);
+    chunk_loop<true, THREADS, MPL>(v, tab, nt, dt, rg, bb, bmode, pxdt, pydt, qz, qz2, lds);
   else
-    chunk_loop<false, THREADS, MPL>(v, tab, nt, dt, rg, bb, bmode, 0, pxdt, pydt, qz, qz2, lds);
+    chunk_loop<false, THREADS, MPL>(v, tab, nt, dt, rg, bb, bmode, pxdt, pydt, qz, qz2, lds);
 
   const double2 aout = edge[1];
 #pragma unroll
@@ -373,8 +379,9 @@ __device__ __forceinline__ void process_item(const EvolveArgs& a, int pi, int fi
   }
 }
 
-// One workgroup per 256-mode item.
-__global__ void __launch_bounds__(kItem) k_evolve(EvolveArgs a) {
+// One workgroup per 256-mode item; four waves per SIMD (the register budget of the variant
+// switch; only the chunk loop of the angle-halving path spills, outside its step loops).
+__global__ void __launch_bounds__(kItem) __attribute__((amdgpu_waves_per_eu(4))) k_evolve(EvolveArgs a) {
   __shared__ double2 lds[2][kChunk];
   const int item = xcd_item(blockIdx.x, gridDim.x);
   const int pi = find_pulse_item(a.desc, a.n_pulses, item);
@@ -428,7 +435,7 @@ __global__ void __launch_bounds__(256) k_yield(const PulseDev* __restrict__ desc
 }
 
 // Diagnostics: adds modes x steps of every (selection block, chunk) of every pulse to the count
-// of the variant the evolution chose for it (the same block_variant and chunk_mode).
+// of the variant the evolution chose for it (the same block_variant and chunk_variant).
 // One workgroup per pulse, one thread per block.
 __global__ void __launch_bounds__(256) k_count_mode_steps(const PulseDev* __restrict__ desc,
                                                           const double* __restrict__ ranges,
@@ -444,7 +451,7 @@ __global__ void __launch_bounds__(256) k_count_mode_steps(const PulseDev* __rest
     unsigned long long local[kSeriesVariants] = {};
     const int bmode = block_variant(bb, rg, nch, d.dt).x;
     for (int c = 0; c < nch; ++c) {
-      const int mode = chunk_mode(bb, rg, c, bmode, d.dt);
+      const int mode = chunk_variant(bb, rg, c, bmode, d.dt).x;
       local[min(max(mode, 0), kSeriesVariants - 1)] += mb * (unsigned long long)min(kChunk, d.nt - c * kChunk);
     }
     for (int k = 0; k < kSeriesVariants; ++k)
