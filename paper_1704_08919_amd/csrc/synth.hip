@@ -153,6 +153,98 @@ __device__ void field_at(const PulseDev& d, const double4* __restrict__ sp, int6
   }
 }
 
+// Line data of up to 256 lines of a pulse, staged in LDS by a workgroup: the spectral record and
+// the factors 1/(2 Om), 1/(4 (dw + Om)), 1/(4 (dw - Om)) of the three terms of A (0 where the
+// frequency vanishes and the term takes its t - t_f form instead).
+struct LineTile {
+  double4 q[256];
+  double f0[256], f1[256], f2[256];
+};
+
+// field_at for every lane of a workgroup at its own half-step index h (all lanes must call it:
+// the lines are staged tile by tile with barriers).  The phase index r = k (h - nt) mod 2 nt
+// advances by h - nt from one line to the next, so only the first line needs a division; the
+// phase itself is evaluated exactly (sincospi of the reduced index) on every 16th line and carried
+// to the next 15 by rotating with the step angle pi (h - nt) / nt (a few ulps per line).
+__device__ void field_tiled(const PulseDev& d, const double4* __restrict__ sp, int64_t h, bool want_E, bool want_A,
+                            LineTile& L, double E[2], double A[2]) {
+  const int64_t nt = d.nt, two_nt = 2 * int64_t(d.nt);
+  const int64_t hm = h - nt;
+  const double inv_nt = 1.0 / double(d.nt);
+  double ex = 0.0, ey = 0.0, ax = 0.0, ay = 0.0;
+  double sd = 0.0, cd = 1.0;  // Delta omega t
+  if (want_A) line_phase(1, hm, two_nt, inv_nt, &sd, &cd);
+  const double tmf = double(h - two_nt) * (0.5 * d.dt);  // t - t_f
+  int64_t r = (int64_t(d.nmin) * hm) % two_nt;
+  if (r < 0) r += two_nt;
+  double sr, cr;  // rotation by one line: pi (h - nt) / nt
+  sincospi(double(hm < 0 ? hm + two_nt : hm) * inv_nt, &sr, &cr);
+  double s = 0.0, c = 1.0;
+  for (int j0 = 0; j0 < d.nlines; j0 += 256) {
+    const int cnt = min(256, d.nlines - j0);
+    __syncthreads();
+    if (int(threadIdx.x) < cnt) {
+      const int64_t k = int64_t(d.nmin) + j0 + threadIdx.x;
+      L.q[threadIdx.x] = sp[j0 + threadIdx.x];
+      L.f0[threadIdx.x] = k == 0 ? 0.0 : 0.5 / (double(k) * d.dw);
+      L.f1[threadIdx.x] = 0.25 / (double(k + 1) * d.dw);
+      L.f2[threadIdx.x] = k == 1 ? 0.0 : 0.25 / (double(1 - k) * d.dw);
+    }
+    __syncthreads();
+    for (int t = 0; t < cnt; ++t) {
+      const int64_t k = int64_t(d.nmin) + j0 + t;
+      if (((j0 + t) & 15) == 0) {
+        sincospi(double(r) * inv_nt, &s, &c);
+      } else {
+        const double cn = fma(c, cr, -(s * sr));
+        s = fma(s, cr, c * sr);
+        c = cn;
+      }
+      r += hm;
+      if (r >= two_nt) r -= two_nt;
+      if (r < 0) r += two_nt;
+      const double4 q = L.q[t];  // (cEx, sEx, cEy, sEy)
+      if (want_E) {
+        ex += q.x * c + q.y * s;
+        ey += q.z * c + q.w * s;
+      }
+      if (want_A) {
+        const double sgn = (k & 1) ? -1.0 : 1.0;
+        const double cp = c * cd - s * sd, spp = s * cd + c * sd;  // (Om + dw) t
+        const double cm = cd * c + sd * s, smm = sd * c - cd * s;  // (dw - Om) t
+        double tx, ty;
+        if (k == 0) {
+          tx = 0.5 * tmf * q.x;
+          ty = 0.5 * tmf * q.z;
+        } else {
+          tx = L.f0[t] * (q.x * s - q.y * c + sgn * q.y);
+          ty = L.f0[t] * (q.z * s - q.w * c + sgn * q.w);
+        }
+        tx += L.f1[t] * (q.x * spp - q.y * cp - sgn * q.y);
+        ty += L.f1[t] * (q.z * spp - q.w * cp - sgn * q.w);
+        if (k == 1) {
+          tx += 0.25 * tmf * q.x;
+          ty += 0.25 * tmf * q.z;
+        } else {
+          tx += L.f2[t] * (q.x * smm + q.y * cm + sgn * q.y);
+          ty += L.f2[t] * (q.z * smm + q.w * cm + sgn * q.w);
+        }
+        ax -= tx;
+        ay -= ty;
+      }
+    }
+  }
+  if (want_E) {
+    const double g = cospi(double(hm) * (0.5 * inv_nt));  // cos(pi t / T)
+    E[0] = g * g * ex;
+    E[1] = g * g * ey;
+  }
+  if (want_A) {
+    A[0] = ax;
+    A[1] = ay;
+  }
+}
+
 // Per block: max |E| over step nodes (PEAK) or sum |E|^2 over midpoints (ENERGY) -> part[pulse][block].
 __global__ void __launch_bounds__(256) k_field_stats(const PulseDev* __restrict__ desc,
                                                      const double* __restrict__ spec, int stride,
@@ -161,21 +253,15 @@ __global__ void __launch_bounds__(256) k_field_stats(const PulseDev* __restrict_
   if (d.norm == PO_NORM_NONE || int(blockIdx.x) >= d.stat_blocks) return;
   const double4* sp = reinterpret_cast<const double4*>(spec + d.spec_off);
   __shared__ double red[256];
+  __shared__ LineTile L;
   const int64_t n = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const bool peak = d.norm == PO_NORM_PEAK;
+  // nodes 0..nt (PEAK) or midpoints 0..nt-1 (ENERGY); every lane takes part in the line staging
+  const bool active = peak ? n <= d.nt : n < d.nt;
+  double E[2], A[2];
+  field_tiled(d, sp, active ? (peak ? 2 * n : 2 * n + 1) : 0, true, false, L, E, A);
   double v = 0.0;
-  if (d.norm == PO_NORM_PEAK) {
-    if (n <= d.nt) {
-      double E[2], A[2];
-      field_at(d, sp, 2 * n, true, false, E, A);
-      v = sqrt(E[0] * E[0] + E[1] * E[1]);
-    }
-  } else {
-    if (n < d.nt) {
-      double E[2], A[2];
-      field_at(d, sp, 2 * n + 1, true, false, E, A);
-      v = E[0] * E[0] + E[1] * E[1];
-    }
-  }
+  if (active) v = peak ? sqrt(E[0] * E[0] + E[1] * E[1]) : E[0] * E[0] + E[1] * E[1];
   red[threadIdx.x] = v;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -224,14 +310,18 @@ __global__ void __launch_bounds__(256) k_tables(const PulseDev* __restrict__ des
                                                 const double* __restrict__ scale, double* __restrict__ Aout,
                                                 double* __restrict__ Eout, double* __restrict__ Aedge) {
   const PulseDev d = desc[blockIdx.y];
+  if (int64_t(blockIdx.x) * 256 >= d.nt) return;  // whole workgroup: beyond this pulse's steps
   const int64_t n = int64_t(blockIdx.x) * 256 + threadIdx.x;
   const double4* sp = reinterpret_cast<const double4*>(spec + d.spec_off);
   const double s = scale[blockIdx.y];
-  if (n < d.nt) {
+  __shared__ LineTile L;
+  {
     double E[2], A[2];
-    field_at(d, sp, 2 * n + 1, Eout != nullptr, true, E, A);
-    reinterpret_cast<double2*>(Aout)[d.tab_off + n] = make_double2(s * A[0], s * A[1]);
-    if (Eout) reinterpret_cast<double2*>(Eout)[d.tab_off + n] = make_double2(s * E[0], s * E[1]);
+    field_tiled(d, sp, n < d.nt ? 2 * n + 1 : 1, Eout != nullptr, true, L, E, A);
+    if (n < d.nt) {
+      reinterpret_cast<double2*>(Aout)[d.tab_off + n] = make_double2(s * A[0], s * A[1]);
+      if (Eout) reinterpret_cast<double2*>(Eout)[d.tab_off + n] = make_double2(s * E[0], s * E[1]);
+    }
   }
   if (blockIdx.x == 0 && threadIdx.x < 2) {
     double E[2], A[2];

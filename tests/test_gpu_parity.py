@@ -83,6 +83,8 @@ def test_synth_tables_match_oracle(orc, case):
         Ar, Er, er, sr = orc.synth(s, c)
         nt = s["nt"]
         assert abs(scale[i] - sr) <= 1e-13 * sr
+        say(f"  pulse {i}: A err / max|A| {np.max(np.abs(A[off:off + nt] - Ar)) / np.max(np.abs(Ar)):.2e}, "
+            f"E err / max|E| {np.max(np.abs(E[off:off + nt] - Er)) / np.max(np.abs(Er)):.2e}")
         assert np.max(np.abs(A[off:off + nt] - Ar)) <= 1e-12 * np.max(np.abs(Ar))
         assert np.max(np.abs(E[off:off + nt] - Er)) <= 1e-12 * np.max(np.abs(Er))
         assert np.max(np.abs(edge[i] - er)) <= 1e-12 * np.max(np.abs(Ar))
