@@ -13,7 +13,7 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
-if not torch.cuda.is_available():  # pragma: no cover - collected on CPU hosts, run on the GPU machine
+if not torch.cuda.is_available():  # pragma: no cover - collected on hosts without a GPU
     pytest.skip("no GPU", allow_module_level=True)
 
 from paper_1704_08919_amd import api  # noqa: E402
