@@ -449,11 +449,11 @@ po_status po_evolve_modes_m4(int32_t n, const po_pulse_spec* specs, const po_gri
     PO_TRY(units.alloc(sizeof(double) * size_t(b.total_units), s));
     d_units = static_cast<double*>(units.ptr);
   }
-  PO_TRY(sel.alloc(sizeof(int2) * size_t(n), s));
+  PO_TRY(sel.alloc(sizeof(double) * 4 * size_t(b.total_chunks), s));
   const PulseDev* d_desc = static_cast<PulseDev*>(desc.ptr);
-  int2* d_sel = static_cast<int2*>(sel.ptr);
-  PO_TRY(launch_series_select4(b, d_desc, d_Ag, d_A_edge, d_sel, s));
-  PO_TRY(launch_evolve4_grid(b, d_desc, d_Ag, d_A_edge, d_sel, d_f, d_units, s));
+  double* d_ranges = static_cast<double*>(sel.ptr);
+  PO_TRY(launch_chunk_ranges4(b, d_desc, d_Ag, d_ranges, s));
+  PO_TRY(launch_evolve4_grid(b, d_desc, d_Ag, d_A_edge, d_ranges, d_f, d_units, s));
   if (d_J) PO_TRY(launch_yield_from_units(b, d_desc, d_units, d_J, s));
   return PO_OK;
 }

@@ -132,12 +132,13 @@ po_status launch_evolve_persistent(const EvolveConfig& cfg, int n_pulses, const 
                                    const double* d_A_edge, const double* d_ranges, const int2* d_queue, int n_items,
                                    int n_workgroups, int* d_counter, double* d_f, double* d_units, hipStream_t s);
 int evolve_workgroups_per_cu(const EvolveConfig& cfg);
-// Fourth-order (Magnus) evolution: series selection over both nodes of every step and one
-// workgroup per 256 modes; d_Ag is [sum nt][2 nodes][2] with desc.tab_off counted in steps.
-po_status launch_series_select4(const Batch& b, const PulseDev* d_desc, const double* d_Ag, const double* d_A_edge,
-                                int2* d_sel, hipStream_t s);
+// Fourth-order (Magnus) evolution: table ranges over both nodes of every step per chunk
+// (d_ranges [total_chunks][4]) and one workgroup per 256 modes; d_Ag is [sum nt][2 nodes][2] with
+// desc.tab_off counted in steps.
+po_status launch_chunk_ranges4(const Batch& b, const PulseDev* d_desc, const double* d_Ag, double* d_ranges,
+                               hipStream_t s);
 po_status launch_evolve4_grid(const Batch& b, const PulseDev* d_desc, const double* d_Ag, const double* d_A_edge,
-                              const int2* d_sel, double* d_f, double* d_units, hipStream_t s);
+                              const double* d_ranges, double* d_f, double* d_units, hipStream_t s);
 // Kinetic equation (qke.hip): tables at the 2 nt + 1 half-step points, desc.tab_off in points.
 po_status launch_qke_grid(const Batch& b, const PulseDev* d_desc, const double* d_E, const double* d_Ed,
                           const double* d_A, int linear, double* d_f, double* d_units, hipStream_t s);

@@ -38,24 +38,17 @@ constexpr TanCoef tan_coefs() {
 constexpr TanCoef kTan = tan_coefs();
 constexpr double tan_coef(int n) { return kTan.a[2 * n + 1]; }
 
-// Series variants.  T-series degrees and the largest x at which the remainder
-// sum_{k>n} a_{2k+1} x^k <= a_{2n+3} x^{n+1} / (1 - 0.4053 x) (the coefficient ratio rises to
-// 4/pi^2 = 0.40528...) is below 2^-56.  Beyond the last, C and S of degree 7 (first omitted
-// term x^8/16! < 2^-56 for x <= 0.3612; both series alternate with decreasing terms) after h
-// angle halvings.
-constexpr int kNumTan = 4;
-constexpr int kTanDegree[kNumTan] = {6, 8, 10, 13};
-constexpr double kTanXmax[kNumTan] = {0.0099, 0.0337, 0.0735, 0.1558};
-constexpr double kCosSinXmax = 0.3612;
-constexpr int kMaxHalvings = 60;  // x up to 0.3612 * 4^60 ~ 5e35; beyond (or non-finite) the choice stops here
-constexpr int kHalvingMode = kNumTan;
-constexpr int kNumModes = kNumTan + 1;
-// Every degree from 6 to 13, for the per-block choice of the second-order evolution (same remainder
-// bound, largest x rounded down to four digits).  Index kFineHalving: the angle-halving path.
+// Series variants: the T series of every degree from 6 to 13 with the largest x at which the
+// remainder sum_{k>n} a_{2k+1} x^k <= a_{2n+3} x^{n+1} / (1 - 0.4053 x) (the coefficient ratio
+// rises to 4/pi^2 = 0.40528...) is below 2^-56, rounded down to four digits.  Beyond the last,
+// index kFineHalving: C and S of degree 7 (first omitted term x^8/16! < 2^-56 for x <= 0.3612;
+// both series alternate with decreasing terms) after h angle halvings.
 constexpr int kNumFine = 8;
 constexpr int kFineDegree[kNumFine] = {6, 7, 8, 9, 10, 11, 12, 13};
 constexpr double kFineXmax[kNumFine] = {0.0099, 0.0197, 0.0337, 0.0518, 0.0735, 0.0985, 0.1261, 0.1558};
 constexpr int kFineHalving = kNumFine;
+constexpr double kCosSinXmax = 0.3612;
+constexpr int kMaxHalvings = 60;  // x up to 0.3612 * 4^60 ~ 5e35; beyond (or non-finite) the choice stops here
 constexpr double kSqrt3Over6 = 0.28867513459481288225;  // sqrt(3)/6, Gauss-Legendre nodes 1/2 -+ sqrt(3)/6
 
 // Horner step k of the C and S series, coefficients forced to compile-time constants.

@@ -43,63 +43,6 @@
 namespace po {
 namespace {
 
-__device__ __forceinline__ double grid_max_abs(double lo, int n, double dp) {
-  // largest |p| over the cell-centred points lo + (i + 1/2) dp, i = 0..n-1 (dp = 0: a sheet)
-  return fmax(fabs(lo + 0.5 * dp), fabs(lo + (n - 0.5) * dp));
-}
-
-// Per pulse: bound on x = (omega dt)^2 over every mode and step,
-//   x <= dt^2 [ max_n ((max|p_x| + |A_x,n|)^2 + (max|p_y| + |A_y,n|)^2) + 1 + max p_z^2 ],
-// and the series variant of kTanDegree it selects (sel.x) with the number of angle halvings
-// (sel.y).  Per pulse; used by the fourth-order step (NODES = 2).
-// NODES = 2: the table holds A at two nodes per step (fourth-order step); with theta^2 the bound
-// above, |w_s| <= theta + (sqrt3/6) theta^2 bounds the step's rotation angle.
-template <int NODES>
-__global__ void __launch_bounds__(256) k_series_select(const PulseDev* __restrict__ desc, const double* __restrict__ A,
-                                                       const double* __restrict__ Aedge, int2* __restrict__ sel) {
-  const PulseDev d = desc[blockIdx.x];
-  const double pxm = grid_max_abs(d.lo[0], d.n[0], d.dp[0]);
-  const double pym = grid_max_abs(d.lo[1], d.n[1], d.dp[1]);
-  const double pzm = grid_max_abs(d.lo[2], d.n[2], d.dp[2]);
-  const double2* tab = reinterpret_cast<const double2*>(A) + NODES * d.tab_off;
-  double m = 0.0;
-  for (int64_t n = threadIdx.x; n < int64_t(NODES) * d.nt; n += blockDim.x) {
-    const double2 a = tab[n];
-    const double u = pxm + fabs(a.x), w = pym + fabs(a.y);
-    m = fmax(m, u * u + w * w);
-  }
-  if (threadIdx.x < 2) {
-    const double2 a = reinterpret_cast<const double2*>(Aedge)[2 * blockIdx.x + threadIdx.x];
-    const double u = pxm + fabs(a.x), w = pym + fabs(a.y);
-    m = fmax(m, u * u + w * w);
-  }
-  __shared__ double red[256];
-  red[threadIdx.x] = m;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (int(threadIdx.x) < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    double xb = (red[0] + 1.0 + pzm * pzm) * d.dt * d.dt * (1.0 + 1e-6);
-    if (NODES == 2) {
-      const double th = sqrt(xb);
-      xb = (th + kSqrt3Over6 * th * th) * (th + kSqrt3Over6 * th * th) * (1.0 + 1e-6);
-    }
-    int mode = kHalvingMode, h = 0;
-    for (int k = kNumTan - 1; k >= 0; --k)
-      if (xb <= kTanXmax[k]) mode = k;
-    if (mode == kHalvingMode) {
-      double x = xb;
-      while (x > kCosSinXmax && h < kMaxHalvings) {
-        x *= 0.25;
-        ++h;
-      }
-    }
-    sel[blockIdx.x] = make_int2(mode, h);
-  }
-}
-
 // Box of cell-centred momenta of selection block b (kSelBlock consecutive modes) of a pulse:
 // [pxl, pxh] x [pyl, pyh] and the largest p_z^2.
 struct BlockBox {
@@ -120,14 +63,11 @@ __device__ __forceinline__ BlockBox block_box(const PulseDev& d, int b) {
   return BlockBox{fmin(px0, px1), fmax(px0, px1), fmin(py0, py1), fmax(py0, py1), fmax(pz0 * pz0, pz1 * pz1)};
 }
 
-// Series variant (x: index of kFineDegree or kFineHalving; y: angle halvings) for a block box
-// against a range [lx, hx] x [ly, hy] of table values: with the largest |p - A| per component,
+// Series variant (x: index of kFineDegree or kFineHalving; y: angle halvings) for a bound xb on
+// the step angle squared.  For a block box against a range [lx, hx] x [ly, hy] of table values,
+// with the largest |p - A| per component,
 //   x = (omega dt)^2 <= dt^2 [ max|p_x - A_x|^2 + max|p_y - A_y|^2 + 1 + max p_z^2 ].
-__device__ __forceinline__ int2 choose_variant(const BlockBox& bb, double lx, double hx, double ly, double hy,
-                                               double dt) {
-  const double X = fmax(fmax(bb.pxh - lx, hx - bb.pxl), 0.0);
-  const double Y = fmax(fmax(bb.pyh - ly, hy - bb.pyl), 0.0);
-  const double xb = (X * X + Y * Y + 1.0 + bb.pz2) * dt * dt * (1.0 + 1e-6);
+__device__ __forceinline__ int2 variant_for_x(double xb) {
   int mode = kFineHalving, h = 0;
   for (int k = kNumFine - 1; k >= 0; --k)
     if (xb <= kFineXmax[k]) mode = k;
@@ -141,14 +81,35 @@ __device__ __forceinline__ int2 choose_variant(const BlockBox& bb, double lx, do
   return make_int2(mode, h);
 }
 
+// Bound on (omega dt)^2 for a block box against a range [lx, hx] x [ly, hy] of table values.
+__device__ __forceinline__ double x_bound(const BlockBox& bb, double lx, double hx, double ly, double hy, double dt) {
+  const double X = fmax(fmax(bb.pxh - lx, hx - bb.pxl), 0.0);
+  const double Y = fmax(fmax(bb.pyh - ly, hy - bb.pyl), 0.0);
+  return (X * X + Y * Y + 1.0 + bb.pz2) * dt * dt * (1.0 + 1e-6);
+}
+
+// NODES = 1: the second-order step's angle.  NODES = 2: the fourth-order step's, from theta^2 the
+// bound above over both Gauss nodes, |w_s| <= theta + (sqrt3/6) theta^2.
+template <int NODES>
+__device__ __forceinline__ int2 choose_variant(const BlockBox& bb, double lx, double hx, double ly, double hy,
+                                               double dt) {
+  double xb = x_bound(bb, lx, hx, ly, hy, dt);
+  if constexpr (NODES == 2) {
+    const double th = sqrt(xb);
+    xb = (th + kSqrt3Over6 * th * th) * (th + kSqrt3Over6 * th * th) * (1.0 + 1e-6);
+  }
+  return variant_for_x(xb);
+}
+
 // Variant of a block for the whole table (the union of its nchunks chunk ranges rg[c][4]).
+template <int NODES = 1>
 __device__ __forceinline__ int2 block_variant(const BlockBox& bb, const double* rg, int nchunks, double dt) {
   double lx = rg[0], hx = rg[1], ly = rg[2], hy = rg[3];
   for (int c = 1; c < nchunks; ++c) {
     lx = fmin(lx, rg[4 * c]); hx = fmax(hx, rg[4 * c + 1]);
     ly = fmin(ly, rg[4 * c + 2]); hy = fmax(hy, rg[4 * c + 3]);
   }
-  return choose_variant(bb, lx, hx, ly, hy, dt);
+  return choose_variant<NODES>(bb, lx, hx, ly, hy, dt);
 }
 
 // Variant of chunk c given the block's (bmode).  A block within the T-series range: the lower of
@@ -156,13 +117,16 @@ __device__ __forceinline__ int2 block_variant(const BlockBox& bb, const double* 
 // block on the angle-halving path: its chunks take that path with their own number of halvings,
 // or, when their own range allows any T series, the degree-13 one (two code paths only, so the
 // loop keeps to its register budget).
+template <int NODES = 1>
 __device__ __forceinline__ int2 chunk_variant(const BlockBox& bb, const double* rg, int c, int bmode, double dt) {
-  const int2 own = choose_variant(bb, rg[4 * c], rg[4 * c + 1], rg[4 * c + 2], rg[4 * c + 3], dt);
+  const int2 own = choose_variant<NODES>(bb, rg[4 * c], rg[4 * c + 1], rg[4 * c + 2], rg[4 * c + 3], dt);
   if (bmode == kFineHalving) return own.x == kFineHalving ? own : make_int2(kNumFine - 1, 0);
   return make_int2(min(own.x, bmode), 0);
 }
 
-// Range (min A_x, max A_x, min A_y, max A_y) of the table over chunk blockIdx.x of pulse blockIdx.y.
+// Range (min A_x, max A_x, min A_y, max A_y) of the table over chunk blockIdx.x of pulse blockIdx.y
+// (NODES = 2: over both Gauss-node values of every step).
+template <int NODES>
 __global__ void __launch_bounds__(256) k_chunk_ranges(const PulseDev* __restrict__ desc, const double* __restrict__ A,
                                                       double* __restrict__ ranges) {
   const PulseDev d = desc[blockIdx.y];
@@ -172,9 +136,12 @@ __global__ void __launch_bounds__(256) k_chunk_ranges(const PulseDev* __restrict
   const int n = c * kChunk + int(threadIdx.x);
   double lx = INFINITY, hx = -INFINITY, ly = INFINITY, hy = -INFINITY;
   if (n < d.nt) {
-    const double2 a = reinterpret_cast<const double2*>(A)[d.tab_off + n];
-    lx = hx = a.x;
-    ly = hy = a.y;
+#pragma unroll
+    for (int k = 0; k < NODES; ++k) {
+      const double2 a = reinterpret_cast<const double2*>(A)[NODES * (d.tab_off + n) + k];
+      lx = fmin(lx, a.x); hx = fmax(hx, a.x);
+      ly = fmin(ly, a.y); hy = fmax(hy, a.y);
+    }
   }
   __shared__ double red[4][256];
   red[0][threadIdx.x] = -lx; red[1][threadIdx.x] = hx; red[2][threadIdx.x] = -ly; red[3][threadIdx.x] = hy;
@@ -215,7 +182,7 @@ __global__ void __launch_bounds__(256) k_block_select(const PulseDev* __restrict
   const int64_t nmodes = int64_t(d.n[0]) * d.n[1] * d.n[2];
   const int nblk = int((nmodes + kSelBlock - 1) / kSelBlock);
   for (int b = threadIdx.x; b < nblk; b += blockDim.x)
-    bsel[d.blk_off + b] = choose_variant(block_box(d, b), axl, axh, ayl, ayh, d.dt);
+    bsel[d.blk_off + b] = choose_variant<1>(block_box(d, b), axl, axh, ayl, ayh, d.dt);
 }
 
 template <int MODE>  // MODE < kFineHalving: T series of degree kFineDegree[MODE]; else C, S with angle halving
@@ -521,11 +488,25 @@ __device__ __forceinline__ void renormalise_blocks(State& v) {
   v.cr = ldexp(v.cr, e2); v.ci = ldexp(v.ci, e2); v.dr = ldexp(v.dr, e2); v.di = ldexp(v.di, e2);
 }
 
-template <int MODE>
+template <int MODE>  // MODE < kFineHalving: T series of degree kFineDegree[MODE]; else angle halving
 __device__ __forceinline__ void one_step4(State& v, double4 rec, double pxdt, double pydt, double e, int h,
                                           double inv4h) {
-  if constexpr (MODE < kHalvingMode) step4_tan<kTanDegree[MODE]>(v, rec, pxdt, pydt, e);
+  if constexpr (MODE < kFineHalving) step4_tan<kFineDegree[MODE]>(v, rec, pxdt, pydt, e);
   else step4_halving(v, rec, pxdt, pydt, e, h, inv4h);
+}
+
+// Steps of one chunk in variant MODE; the tangent form then rescales each block.
+template <int MODE>
+__device__ __forceinline__ void run_chunk4(State& v, const double4* buf, int len, double pxdt, double pydt, double e,
+                                           int h) {
+  const double inv4h = ldexp(1.0, -2 * h);
+  if (len == kChunk) {
+#pragma unroll 2
+    for (int k = 0; k < kChunk; ++k) one_step4<MODE>(v, buf[k], pxdt, pydt, e, h, inv4h);
+  } else {
+    for (int k = 0; k < len; ++k) one_step4<MODE>(v, buf[k], pxdt, pydt, e, h, inv4h);
+  }
+  if constexpr (MODE < kFineHalving) renormalise_blocks(v);
 }
 
 struct Evolve4Args {
@@ -533,32 +514,18 @@ struct Evolve4Args {
   int n_pulses;
   const double* Ag;  // [sum nt][2 nodes][2] A at the Gauss-Legendre nodes
   const double* Aedge;
-  const int2* sel;
+  const double* ranges;  // [total_chunks][4] range of the node values per chunk (k_chunk_ranges<2>)
   double* f;
   double* units;
 };
 
-// One 256-mode item of pulse pi, one mode per lane; the structure of process_item.
-template <int MODE>
-__device__ __forceinline__ void process_item4(const Evolve4Args& a, int pi, int first, int h,
-                                              double4 (*lds)[kChunk]) {
-  const PulseDev& d = a.desc[pi];
-  const int nt = d.nt;
-  const double dt = d.dt;
-  const int64_t nmodes = int64_t(d.n[0]) * d.n[1] * d.n[2];
-  const double inv4h = ldexp(1.0, -2 * h);
-  const double4* tab = reinterpret_cast<const double4*>(a.Ag) + d.tab_off;
-  const double2* edge = reinterpret_cast<const double2*>(a.Aedge) + 2 * pi;
+// The chunks of a fourth-order item, as chunk_loop: the record staged per step is
+// (-(A_1 + A_2) dt/2, (sqrt3/6)(A_2 - A_1) dt); each chunk in its variant (chunk_variant<2>).
+template <bool HALVING>
+__device__ __forceinline__ void chunk_loop4(State& v, const double4* tab, int nt, double dt, const double* rg,
+                                            const BlockBox& bb, int bmode, double pxdt, double pydt, double e,
+                                            double4 (*lds)[kChunk]) {
   const double hdt = -0.5 * dt, kdt = kSqrt3Over6 * dt;
-  const int64_t m = int64_t(first) + threadIdx.x;
-  double px, py, pz;
-  mode_momentum(d, m < nmodes ? m : 0, px, py, pz);
-  const double ep = sqrt(fma(pz, pz, 1.0));
-  State v;
-  const double2 ain = edge[0];
-  init_state(v, px - ain.x, py - ain.y, ep);
-  const double pxdt = px * dt, pydt = py * dt, e = ep * dt;
-
   const int nchunks = (nt + kChunk - 1) / kChunk;
   {
     const double4 t = int(threadIdx.x) < nt ? tab[threadIdx.x] : make_double4(0.0, 0.0, 0.0, 0.0);
@@ -570,17 +537,55 @@ __device__ __forceinline__ void process_item4(const Evolve4Args& a, int pi, int 
     const double4 pre = (c + 1 < nchunks && n < nt) ? tab[n] : make_double4(0.0, 0.0, 0.0, 0.0);
     const double4* buf = lds[c & 1];
     const int len = min(kChunk, nt - c * kChunk);
-    if (len == kChunk) {
-#pragma unroll 2
-      for (int k = 0; k < kChunk; ++k) one_step4<MODE>(v, buf[k], pxdt, pydt, e, h, inv4h);
+    const int2 cv = chunk_variant<2>(bb, rg, c, bmode, dt);
+    const int mode = __builtin_amdgcn_readfirstlane(cv.x);
+    if constexpr (HALVING) {
+      if (mode == kFineHalving)
+        run_chunk4<kFineHalving>(v, buf, len, pxdt, pydt, e, __builtin_amdgcn_readfirstlane(cv.y));
+      else
+        run_chunk4<kNumFine - 1>(v, buf, len, pxdt, pydt, e, 0);
     } else {
-      for (int k = 0; k < len; ++k) one_step4<MODE>(v, buf[k], pxdt, pydt, e, h, inv4h);
+      switch (mode) {
+        case 0: run_chunk4<0>(v, buf, len, pxdt, pydt, e, 0); break;
+        case 1: run_chunk4<1>(v, buf, len, pxdt, pydt, e, 0); break;
+        case 2: run_chunk4<2>(v, buf, len, pxdt, pydt, e, 0); break;
+        case 3: run_chunk4<3>(v, buf, len, pxdt, pydt, e, 0); break;
+        case 4: run_chunk4<4>(v, buf, len, pxdt, pydt, e, 0); break;
+        case 5: run_chunk4<5>(v, buf, len, pxdt, pydt, e, 0); break;
+        case 6: run_chunk4<6>(v, buf, len, pxdt, pydt, e, 0); break;
+        default: run_chunk4<7>(v, buf, len, pxdt, pydt, e, 0); break;
+      }
     }
-    if constexpr (MODE < kHalvingMode) renormalise_blocks(v);
     lds[(c + 1) & 1][threadIdx.x] =
         make_double4(hdt * (pre.x + pre.z), hdt * (pre.y + pre.w), kdt * (pre.z - pre.x), kdt * (pre.w - pre.y));
     __syncthreads();
   }
+}
+
+// One 256-mode item of pulse pi, one mode per lane; the structure of process_item, with the
+// series variant per (selection block, chunk) from the range of both node values.
+__device__ __forceinline__ void process_item4(const Evolve4Args& a, int pi, int first, double4 (*lds)[kChunk]) {
+  const PulseDev& d = a.desc[pi];
+  const int nt = d.nt;
+  const double dt = d.dt;
+  const int64_t nmodes = int64_t(d.n[0]) * d.n[1] * d.n[2];
+  const double4* tab = reinterpret_cast<const double4*>(a.Ag) + d.tab_off;
+  const double2* edge = reinterpret_cast<const double2*>(a.Aedge) + 2 * pi;
+  const int64_t m = int64_t(first) + threadIdx.x;
+  double px, py, pz;
+  mode_momentum(d, m < nmodes ? m : 0, px, py, pz);
+  const double ep = sqrt(fma(pz, pz, 1.0));
+  State v;
+  const double2 ain = edge[0];
+  init_state(v, px - ain.x, py - ain.y, ep);
+  const double pxdt = px * dt, pydt = py * dt, e = ep * dt;
+  const BlockBox bb = block_box(d, first / kSelBlock);
+  const double* rg = a.ranges + 4 * int64_t(d.chk_off);
+  const int bmode = __builtin_amdgcn_readfirstlane(block_variant<2>(bb, rg, (nt + kChunk - 1) / kChunk, dt).x);
+  if (bmode == kFineHalving)
+    chunk_loop4<true>(v, tab, nt, dt, rg, bb, bmode, pxdt, pydt, e, lds);
+  else
+    chunk_loop4<false>(v, tab, nt, dt, rg, bb, bmode, pxdt, pydt, e, lds);
 
   const double2 aout = edge[1];
   double fv = 0.0;
@@ -591,19 +596,11 @@ __device__ __forceinline__ void process_item4(const Evolve4Args& a, int pi, int 
   if (a.units) write_unit(d, a.units, m, nmodes, fv);
 }
 
-__global__ void __launch_bounds__(kItem) k_evolve4(Evolve4Args a) {
+__global__ void __launch_bounds__(kItem) __attribute__((amdgpu_waves_per_eu(4))) k_evolve4(Evolve4Args a) {
   __shared__ double4 lds[2][kChunk];
   const int item = xcd_item(blockIdx.x, gridDim.x);
   const int pi = find_pulse_item(a.desc, a.n_pulses, item);
-  const int first = (item - a.desc[pi].item_off) * kItem;
-  const int2 sl = a.sel[pi];
-  switch (sl.x) {
-    case 0: process_item4<0>(a, pi, first, 0, lds); break;
-    case 1: process_item4<1>(a, pi, first, 0, lds); break;
-    case 2: process_item4<2>(a, pi, first, 0, lds); break;
-    case 3: process_item4<3>(a, pi, first, 0, lds); break;
-    default: process_item4<kHalvingMode>(a, pi, first, sl.y, lds); break;
-  }
+  process_item4(a, pi, (item - a.desc[pi].item_off) * kItem, lds);
 }
 
 }  // namespace
@@ -618,7 +615,7 @@ po_status launch_block_select(const Batch& b, const PulseDev* d_desc, const doub
 po_status launch_chunk_ranges(const Batch& b, const PulseDev* d_desc, const double* d_A, double* d_ranges,
                               hipStream_t s) {
   const int max_chunks = (b.max_nt + kChunk - 1) / kChunk;
-  hipLaunchKernelGGL(k_chunk_ranges, dim3(max_chunks, b.n_pulses), dim3(256), 0, s, d_desc, d_A, d_ranges);
+  hipLaunchKernelGGL(k_chunk_ranges<1>, dim3(max_chunks, b.n_pulses), dim3(256), 0, s, d_desc, d_A, d_ranges);
   PO_HIP(hipGetLastError());
   return PO_OK;
 }
@@ -679,16 +676,17 @@ po_status launch_yield_from_units(const Batch& b, const PulseDev* d_desc, const 
   return PO_OK;
 }
 
-po_status launch_series_select4(const Batch& b, const PulseDev* d_desc, const double* d_Ag, const double* d_A_edge,
-                                int2* d_sel, hipStream_t s) {
-  hipLaunchKernelGGL(k_series_select<2>, dim3(b.n_pulses), dim3(256), 0, s, d_desc, d_Ag, d_A_edge, d_sel);
+po_status launch_chunk_ranges4(const Batch& b, const PulseDev* d_desc, const double* d_Ag, double* d_ranges,
+                               hipStream_t s) {
+  const int max_chunks = (b.max_nt + kChunk - 1) / kChunk;
+  hipLaunchKernelGGL(k_chunk_ranges<2>, dim3(max_chunks, b.n_pulses), dim3(256), 0, s, d_desc, d_Ag, d_ranges);
   PO_HIP(hipGetLastError());
   return PO_OK;
 }
 
 po_status launch_evolve4_grid(const Batch& b, const PulseDev* d_desc, const double* d_Ag, const double* d_A_edge,
-                              const int2* d_sel, double* d_f, double* d_units, hipStream_t s) {
-  Evolve4Args a{d_desc, b.n_pulses, d_Ag, d_A_edge, d_sel, d_f, d_units};
+                              const double* d_ranges, double* d_f, double* d_units, hipStream_t s) {
+  Evolve4Args a{d_desc, b.n_pulses, d_Ag, d_A_edge, d_ranges, d_f, d_units};
   hipLaunchKernelGGL(k_evolve4, dim3(b.total_items), dim3(kItem), 0, s, a);
   PO_HIP(hipGetLastError());
   return PO_OK;
