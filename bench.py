@@ -28,12 +28,12 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 128 FLOP/clk x 2.4 GHz
 # the count of the step actually required for reference.
 FIXED_FLOP_PER_MODE_STEP = 97
 # FP64 operations of one mode-step per series variant of the evolution kernel (an FMA counts 2).
-# tan(theta)/theta series of degree n: q (2 adds), x = |q|^2 (2 FMA), the series (n FMA), T q
+# tan(theta)/theta polynomial of degree n: q (2 adds), x = |q|^2 (2 FMA), the polynomial (n FMA), T q
 # (3 mul), and 1 - i T Q on two 2x2 blocks (8 real components x 3 FMA) = 57 + 2n.
 # cos/sin of degree 7 (large steps): q, x, two series (14 FMA), S q, and C - i S Q on two blocks
 # (8 x (1 mul + 3 FMA)) = 93, plus 6 per angle halving (not counted: a lower bound).
-FLOP_PER_MODE_STEP = {"tan6": 69, "tan7": 71, "tan8": 73, "tan9": 75, "tan10": 77, "tan11": 79, "tan12": 81,
-                      "tan13": 83, "cossin7_halving": 93}
+FLOP_PER_MODE_STEP = {"tan4": 65, "tan5": 67, "tan6": 69, "tan7": 71, "tan8": 73, "tan9": 75, "tan10": 77,
+                      "tan11": 79, "cossin7_halving": 93}
 HERE_PROFILES = os.path.join(ROOT, "profiles")
 # launch shape of the plans used by the surrogate sections (fixed, so no autotuning is timed)
 PLAN = dict(threads=256, modes_per_lane=1, persistent=1)

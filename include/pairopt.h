@@ -423,8 +423,9 @@ po_status po_log10_standardize(const double* d_J, int32_t n, double floor_value,
 po_status po_timer_enable(int on);
 po_status po_timer_read(double* ms_total, int64_t* calls);
 /* Mode-steps evolved since the last read while timers were enabled, per series variant of the
- * second-order evolution kernel (chosen per block of 512 modes): counts[0..7] = tan(theta)/theta
- * series of degree 6, 7, ..., 13; counts[8] = cos/sin series of degree 7 with angle halving.
+ * second-order evolution kernel (chosen per block of 512 modes and chunk of 256 steps):
+ * counts[0..7] = tan(theta)/theta polynomial of degree 4, 5, ..., 11; counts[8] = cos/sin series of
+ * degree 7 with angle halving.
  * Entries beyond 9 are set to 0.  Synchronises the device; clears the counts. */
 po_status po_timer_mode_steps(uint64_t* counts, int32_t n);
 

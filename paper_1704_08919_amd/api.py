@@ -305,7 +305,7 @@ def po_log10_standardize(J, mean, inv_std, floor=1e-300, out=None, stream=None):
     return out
 
 
-SERIES_VARIANTS = ("tan6", "tan7", "tan8", "tan9", "tan10", "tan11", "tan12", "tan13", "cossin7_halving")
+SERIES_VARIANTS = ("tan4", "tan5", "tan6", "tan7", "tan8", "tan9", "tan10", "tan11", "cossin7_halving")
 
 
 def po_timer_mode_steps():

@@ -114,7 +114,7 @@ struct EvolveConfig {
   int mpl = 1;
   int persistent = 0;
 };
-// Per-block series selection of the yield gradient: x = variant of kFineDegree (or kFineHalving),
+// Per-block series selection of the yield gradient: x = variant of kFitDegree (or kFineHalving),
 // y = number of angle halvings, one int2 per kSelBlock modes of each pulse (total_blocks).
 po_status launch_block_select(const Batch& b, const PulseDev* d_desc, const double* d_A, int2* d_bsel,
                               hipStream_t s);

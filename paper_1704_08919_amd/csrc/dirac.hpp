@@ -8,6 +8,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "tan_fit.hpp"
 
 #pragma clang fp contract(off)
 
@@ -21,31 +22,12 @@ constexpr double factorial(int n) { return n <= 1 ? 1.0 : double(n) * factorial(
 constexpr double cos_coef(int k) { return (k % 2 ? -1.0 : 1.0) / factorial(2 * k); }
 constexpr double sinc_coef(int k) { return (k % 2 ? -1.0 : 1.0) / factorial(2 * k + 1); }
 
-// Maclaurin coefficients of tan(z) = sum_k a_k z^k from tan' = 1 + tan^2:
-// (k + 1) a_{k+1} = [k == 0] + sum_{i+j=k} a_i a_j, so tan(sqrt x)/sqrt x = sum_n a_{2n+1} x^n.
-struct TanCoef {
-  double a[48];
-};
-constexpr TanCoef tan_coefs() {
-  TanCoef t{};
-  for (int k = 0; k + 1 < 48; ++k) {
-    double s = (k == 0) ? 1.0 : 0.0;
-    for (int i = 0; i <= k; ++i) s += t.a[i] * t.a[k - i];
-    t.a[k + 1] = s / double(k + 1);
-  }
-  return t;
-}
-constexpr TanCoef kTan = tan_coefs();
-constexpr double tan_coef(int n) { return kTan.a[2 * n + 1]; }
-
-// Series variants: the T series of every degree from 6 to 13 with the largest x at which the
-// remainder sum_{k>n} a_{2k+1} x^k <= a_{2n+3} x^{n+1} / (1 - 0.4053 x) (the coefficient ratio
-// rises to 4/pi^2 = 0.40528...) is below 2^-56, rounded down to four digits.  Beyond the last,
-// index kFineHalving: C and S of degree 7 (first omitted term x^8/16! < 2^-56 for x <= 0.3612;
-// both series alternate with decreasing terms) after h angle halvings.
-constexpr int kNumFine = 8;
-constexpr int kFineDegree[kNumFine] = {6, 7, 8, 9, 10, 11, 12, 13};
-constexpr double kFineXmax[kNumFine] = {0.0099, 0.0197, 0.0337, 0.0518, 0.0735, 0.0985, 0.1261, 0.1558};
+// Series variants: T(x) = tan(sqrt x)/sqrt x = 1 + x R(x) with R a polynomial fit of degree
+// n - 1 (n = 4..11, tan_fit.hpp: Chebyshev interpolation on [0, X_n], |T_fit - T| <= 2^-57 there,
+// about two degrees fewer than the Maclaurin series needs for the same range).  Beyond the last
+// X_n, index kFineHalving: C and S of degree 7 (first omitted term x^8/16! < 2^-56 for
+// x <= 0.3612; both series alternate with decreasing terms) after h angle halvings.
+constexpr int kNumFine = kNumFit;
 constexpr int kFineHalving = kNumFine;
 constexpr double kCosSinXmax = 0.3612;
 constexpr int kMaxHalvings = 60;  // x up to 0.3612 * 4^60 ~ 5e35; beyond (or non-finite) the choice stops here
@@ -68,20 +50,39 @@ __device__ __forceinline__ void cos_sinc(double x, double& C, double& S) {
   horner_cs<D - 1>(x, C, S);
 }
 
-template <int K>
-__device__ __forceinline__ void horner_tan(double x, double& T) {
-  constexpr double c = tan_coef(K);
-  T = fma(T, x, c);
-  if constexpr (K > 0) horner_tan<K - 1>(x, T);
+// Coefficients of the fit of variant V, put in scalar registers where the caller loads them: the
+// empty asm statement per value keeps the compiler from materialising the constants of every
+// variant of a kernel at its entry (which exhausts the scalar registers); the values are unchanged.
+template <int V>
+struct Fit {
+  double c[kFitDegree[V]];
+};
+
+template <int V>
+__device__ __forceinline__ Fit<V> load_fit() {
+  Fit<V> f;
+#pragma unroll
+  for (int k = 0; k < kFitDegree[V]; ++k) {
+    f.c[k] = kFitCoef[V][k];
+    asm volatile("" : "+s"(f.c[k]));
+  }
+  return f;
 }
 
-// T(x) = tan(sqrt x)/sqrt x, degree N.
-template <int N>
-__device__ __forceinline__ double tan_ratio(double x) {
-  constexpr double c = tan_coef(N);
-  double T = c;
-  horner_tan<N - 1>(x, T);
-  return T;
+// R(x) = (T(x) - 1)/x of variant V (degree kFitDegree[V] - 1), by Horner's rule.
+template <int V>
+__device__ __forceinline__ double fit_R(double x, const Fit<V>& f) {
+  constexpr int n = kFitDegree[V];
+  double R = f.c[n - 1];
+#pragma unroll
+  for (int k = n - 2; k >= 0; --k) R = fma(R, x, f.c[k]);
+  return R;
+}
+
+// T(x) = tan(sqrt x)/sqrt x of variant V: kFitDegree[V] fused multiply-adds.
+template <int V>
+__device__ __forceinline__ double tan_ratio(double x, const Fit<V>& f) {
+  return fma(fit_R<V>(x, f), x, 1.0);
 }
 
 // (a_r, a_i, b_r, b_i) of block s = +1 and (c_r, c_i, d_r, d_i) of block s = -1.
@@ -119,12 +120,13 @@ __device__ __forceinline__ void rotate_tan(State& v, double T, double qx, double
   v = State{ar, ai, br, bi, cr, ci, dr, di};
 }
 
-template <int N>
-__device__ __forceinline__ void step_tan(State& v, double2 rec, double pxdt, double pydt, double qz, double qz2) {
+template <int V>  // series variant
+__device__ __forceinline__ void step_tan(State& v, double2 rec, double pxdt, double pydt, double qz, double qz2,
+                                         const Fit<V>& f) {
   const double qx = pxdt + rec.x;  // rec = -A dt
   const double qy = pydt + rec.y;
   const double x = fma(qx, qx, fma(qy, qy, qz2));
-  rotate_tan(v, tan_ratio<N>(x), qx, qy, qz);
+  rotate_tan(v, tan_ratio<V>(x, f), qx, qy, qz);
 }
 
 // Large-step path: C, S at x / 4^h, then h double-angle steps; the step stays unitary.

@@ -63,14 +63,14 @@ __device__ __forceinline__ BlockBox block_box(const PulseDev& d, int b) {
   return BlockBox{fmin(px0, px1), fmax(px0, px1), fmin(py0, py1), fmax(py0, py1), fmax(pz0 * pz0, pz1 * pz1)};
 }
 
-// Series variant (x: index of kFineDegree or kFineHalving; y: angle halvings) for a bound xb on
+// Series variant (x: index of the T fits or kFineHalving; y: angle halvings) for a bound xb on
 // the step angle squared.  For a block box against a range [lx, hx] x [ly, hy] of table values,
 // with the largest |p - A| per component,
 //   x = (omega dt)^2 <= dt^2 [ max|p_x - A_x|^2 + max|p_y - A_y|^2 + 1 + max p_z^2 ].
 __device__ __forceinline__ int2 variant_for_x(double xb) {
   int mode = kFineHalving, h = 0;
   for (int k = kNumFine - 1; k >= 0; --k)
-    if (xb <= kFineXmax[k]) mode = k;
+    if (xb <= kFitXmax[k]) mode = k;
   if (mode == kFineHalving) {
     double x = xb;
     while (x > kCosSinXmax && h < kMaxHalvings) {
@@ -185,13 +185,6 @@ __global__ void __launch_bounds__(256) k_block_select(const PulseDev* __restrict
     bsel[d.blk_off + b] = choose_variant<1>(block_box(d, b), axl, axh, ayl, ayh, d.dt);
 }
 
-template <int MODE>  // MODE < kFineHalving: T series of degree kFineDegree[MODE]; else C, S with angle halving
-__device__ __forceinline__ void one_step(State& v, double2 rec, double pxdt, double pydt, double qz, double qz2, int h,
-                                         double inv4h) {
-  if constexpr (MODE < kFineHalving) step_tan<kFineDegree[MODE]>(v, rec, pxdt, pydt, qz, qz2);
-  else step_halving(v, rec, pxdt, pydt, qz, qz2, h, inv4h);
-}
-
 struct EvolveArgs {
   const PulseDev* desc;
   int n_pulses;
@@ -203,29 +196,46 @@ struct EvolveArgs {
 };
 
 // Steps of one chunk (len records of buf) in series variant MODE for the MPL modes of a lane; the
-// tangent form then rescales the states by exact powers of two.
+// tangent form (the variant's fit coefficients loaded once per chunk) then rescales the states by
+// exact powers of two.
 template <int MODE, int MPL>
 __device__ __forceinline__ void run_chunk(State (&v)[MPL], const double2* buf, int len, const double (&pxdt)[MPL],
                                           const double (&pydt)[MPL], const double (&qz)[MPL], const double (&qz2)[MPL],
                                           int h) {
-  const double inv4h = ldexp(1.0, -2 * h);
-  if (len == kChunk) {
-#pragma unroll(MPL == 1 ? 4 : 2)
-    for (int k = 0; k < kChunk; ++k) {
-      const double2 rec = buf[k];
-#pragma unroll
-      for (int j = 0; j < MPL; ++j) one_step<MODE>(v[j], rec, pxdt[j], pydt[j], qz[j], qz2[j], h, inv4h);
-    }
-  } else {
-    for (int k = 0; k < len; ++k) {
-      const double2 rec = buf[k];
-#pragma unroll
-      for (int j = 0; j < MPL; ++j) one_step<MODE>(v[j], rec, pxdt[j], pydt[j], qz[j], qz2[j], h, inv4h);
-    }
-  }
   if constexpr (MODE < kFineHalving) {
+    const Fit<MODE> f = load_fit<MODE>();
+    if (len == kChunk) {
+#pragma unroll(MPL == 1 ? 4 : 2)
+      for (int k = 0; k < kChunk; ++k) {
+        const double2 rec = buf[k];
+#pragma unroll
+        for (int j = 0; j < MPL; ++j) step_tan<MODE>(v[j], rec, pxdt[j], pydt[j], qz[j], qz2[j], f);
+      }
+    } else {
+      for (int k = 0; k < len; ++k) {
+        const double2 rec = buf[k];
+#pragma unroll
+        for (int j = 0; j < MPL; ++j) step_tan<MODE>(v[j], rec, pxdt[j], pydt[j], qz[j], qz2[j], f);
+      }
+    }
 #pragma unroll
     for (int j = 0; j < MPL; ++j) renormalise(v[j]);
+  } else {
+    const double inv4h = ldexp(1.0, -2 * h);
+    if (len == kChunk) {
+#pragma unroll(MPL == 1 ? 4 : 2)
+      for (int k = 0; k < kChunk; ++k) {
+        const double2 rec = buf[k];
+#pragma unroll
+        for (int j = 0; j < MPL; ++j) step_halving(v[j], rec, pxdt[j], pydt[j], qz[j], qz2[j], h, inv4h);
+      }
+    } else {
+      for (int k = 0; k < len; ++k) {
+        const double2 rec = buf[k];
+#pragma unroll
+        for (int j = 0; j < MPL; ++j) step_halving(v[j], rec, pxdt[j], pydt[j], qz[j], qz2[j], h, inv4h);
+      }
+    }
   }
 }
 
@@ -457,12 +467,12 @@ __device__ __forceinline__ Magnus4 magnus4(double4 rec, double pxdt, double pydt
   return Magnus4{ab - egy, bb + egx, e + g, ab + egy, bb - egx, e - g};
 }
 
-template <int N>
-__device__ __forceinline__ void step4_tan(State& v, double4 rec, double pxdt, double pydt, double e) {
+template <int V>  // series variant
+__device__ __forceinline__ void step4_tan(State& v, double4 rec, double pxdt, double pydt, double e, const Fit<V>& f) {
   const Magnus4 w = magnus4(rec, pxdt, pydt, e);
   const double xp = fma(w.Xp, w.Xp, fma(w.Yp, w.Yp, w.Zp * w.Zp));
   const double xm = fma(w.Xm, w.Xm, fma(w.Ym, w.Ym, w.Zm * w.Zm));
-  const double Tp = tan_ratio<N>(xp), Tm = tan_ratio<N>(xm);
+  const double Tp = tan_ratio<V>(xp, f), Tm = tan_ratio<V>(xm, f);
   rotate_block_tan(v.ar, v.ai, v.br, v.bi, Tp * w.Xp, Tp * w.Yp, Tp * w.Zp);
   rotate_block_tan(v.cr, v.ci, v.dr, v.di, Tm * w.Xm, -(Tm * w.Ym), Tm * w.Zm);
 }
@@ -488,25 +498,28 @@ __device__ __forceinline__ void renormalise_blocks(State& v) {
   v.cr = ldexp(v.cr, e2); v.ci = ldexp(v.ci, e2); v.dr = ldexp(v.dr, e2); v.di = ldexp(v.di, e2);
 }
 
-template <int MODE>  // MODE < kFineHalving: T series of degree kFineDegree[MODE]; else angle halving
-__device__ __forceinline__ void one_step4(State& v, double4 rec, double pxdt, double pydt, double e, int h,
-                                          double inv4h) {
-  if constexpr (MODE < kFineHalving) step4_tan<kFineDegree[MODE]>(v, rec, pxdt, pydt, e);
-  else step4_halving(v, rec, pxdt, pydt, e, h, inv4h);
-}
-
 // Steps of one chunk in variant MODE; the tangent form then rescales each block.
 template <int MODE>
 __device__ __forceinline__ void run_chunk4(State& v, const double4* buf, int len, double pxdt, double pydt, double e,
                                            int h) {
-  const double inv4h = ldexp(1.0, -2 * h);
-  if (len == kChunk) {
+  if constexpr (MODE < kFineHalving) {
+    const Fit<MODE> f = load_fit<MODE>();
+    if (len == kChunk) {
 #pragma unroll 2
-    for (int k = 0; k < kChunk; ++k) one_step4<MODE>(v, buf[k], pxdt, pydt, e, h, inv4h);
+      for (int k = 0; k < kChunk; ++k) step4_tan<MODE>(v, buf[k], pxdt, pydt, e, f);
+    } else {
+      for (int k = 0; k < len; ++k) step4_tan<MODE>(v, buf[k], pxdt, pydt, e, f);
+    }
+    renormalise_blocks(v);
   } else {
-    for (int k = 0; k < len; ++k) one_step4<MODE>(v, buf[k], pxdt, pydt, e, h, inv4h);
+    const double inv4h = ldexp(1.0, -2 * h);
+    if (len == kChunk) {
+#pragma unroll 2
+      for (int k = 0; k < kChunk; ++k) step4_halving(v, buf[k], pxdt, pydt, e, h, inv4h);
+    } else {
+      for (int k = 0; k < len; ++k) step4_halving(v, buf[k], pxdt, pydt, e, h, inv4h);
+    }
   }
-  if constexpr (MODE < kFineHalving) renormalise_blocks(v);
 }
 
 struct Evolve4Args {

@@ -154,12 +154,11 @@ __device__ __forceinline__ double2 back_step(State& psi, State& chi, double2 r, 
 // chi' and leaves out the factors C: psi_n = sigma_n psi~_n and chi'_{n+1} = sigma_{n+1} chi~_{n+1}
 // with sigma_n = C_n sigma_{n+1}, so the term of step n is Sigma_n = sigma_n^2 = C_n^2 Sigma_{n+1}
 // times the same expression in psi~, chi~ with (S, D) -> (T, -R).  C^2 = cos^2 sqrt x comes from its
-// own series, R from the T series before its last Horner step (T = 1 + x R).
+// own series, R is the variant's fit (T = 1 + x R).
 // cos^2 sqrt x = 1 + sum_{k >= 1} (-1)^k 2^(2k-1) x^k / (2k)!, alternating with decreasing terms;
-// degree M per T variant keeps the remainder below 2^-59 up to that variant's largest x.
+// degree kFitCos2Degree[v] keeps the remainder below 2^-59 up to the variant's largest x.
 constexpr double pow2i(int n) { return n == 0 ? 1.0 : 2.0 * pow2i(n - 1); }
 constexpr double cos2_coef(int k) { return k == 0 ? 1.0 : (k % 2 ? -1.0 : 1.0) * pow2i(2 * k - 1) / factorial(2 * k); }
-constexpr int kCos2Degree[kNumFine] = {6, 6, 7, 7, 7, 8, 8, 8};
 
 template <int K>
 __device__ __forceinline__ void horner_cos2(double x, double& c) {
@@ -176,23 +175,13 @@ __device__ __forceinline__ double cos2_series(double x) {
   return c;
 }
 
-// Horner steps K..1 of the T series (the step with coefficient 1 left out).
-template <int K>
-__device__ __forceinline__ void horner_tan1(double x, double& R) {
-  constexpr double c = tan_coef(K);
-  R = fma(R, x, c);
-  if constexpr (K > 1) horner_tan1<K - 1>(x, R);
-}
-
 template <int MODE>
 __device__ __forceinline__ double2 back_step_tan(State& psi, State& chi, double2 r, double pxdt, double pydt,
-                                                 double qz, double qz2, double& sig) {
-  constexpr int N = kFineDegree[MODE], M = kCos2Degree[MODE];
+                                                 double qz, double qz2, double& sig, const Fit<MODE>& f) {
+  constexpr int M = kFitCos2Degree[MODE];
   const double qx = pxdt + r.x, qy = pydt + r.y;
   const double x = fma(qx, qx, fma(qy, qy, qz2));
-  constexpr double cn = tan_coef(N);
-  double R = cn;
-  horner_tan1<N - 1>(x, R);
+  const double R = fit_R<MODE>(x, f);
   const double T = fma(R, x, 1.0);
   const double c2 = cos2_series<M>(x);
   rotate_tan(psi, -T, qx, qy, qz);
@@ -213,19 +202,36 @@ __device__ __forceinline__ void fold_scale(State& psi, State& chi, double& sig) 
   sig = 1.0;
 }
 
+// Coefficients of the fit for the tangent-form variants (an empty record for the halving path).
+template <int MODE, bool TAN = (MODE < kFineHalving)>
+struct FitOf {
+  using type = Fit<MODE>;
+};
+template <int MODE>
+struct FitOf<MODE, false> {
+  struct type {};
+};
+
+template <int MODE>
+__device__ __forceinline__ typename FitOf<MODE>::type load_fit_of() {
+  if constexpr (MODE < kFineHalving) return load_fit<MODE>();
+  else return typename FitOf<MODE>::type{};
+}
+
 // One backward step in the form of the pulse's variant: tangent form (scale in sig) or exact C, S.
 template <int MODE>
 __device__ __forceinline__ double2 back_any(State& psi, State& chi, double2 r, double pxdt, double pydt, double qz,
-                                            double qz2, int h, double inv4h, double& sig) {
-  if constexpr (MODE < kFineHalving) return back_step_tan<MODE>(psi, chi, r, pxdt, pydt, qz, qz2, sig);
+                                            double qz2, int h, double inv4h, double& sig,
+                                            const typename FitOf<MODE>::type& f) {
+  if constexpr (MODE < kFineHalving) return back_step_tan<MODE>(psi, chi, r, pxdt, pydt, qz, qz2, sig, f);
   else return back_step<false>(psi, chi, r, pxdt, pydt, qz, qz2, h, inv4h);
 }
 
 // Forward step of the evolution in the form the pulse's series choice selects.
 template <int MODE>
 __device__ __forceinline__ void fwd_step(State& v, double2 rec, double pxdt, double pydt, double qz, double qz2, int h,
-                                         double inv4h) {
-  if constexpr (MODE < kFineHalving) step_tan<kFineDegree[MODE]>(v, rec, pxdt, pydt, qz, qz2);
+                                         double inv4h, const typename FitOf<MODE>::type& f) {
+  if constexpr (MODE < kFineHalving) step_tan<MODE>(v, rec, pxdt, pydt, qz, qz2, f);
   else step_halving(v, rec, pxdt, pydt, qz, qz2, h, inv4h);
 }
 
@@ -313,6 +319,7 @@ __device__ __forceinline__ void grad_item(const GradArgs& a, int item, int pi, d
   const bool active = m < nmodes;
   const int h = a.sel[d.blk_off + li * kItem / kSelBlock].y;
   const double inv4h = ldexp(1.0, -2 * h);
+  const auto fit = load_fit_of<MODE>();
   const double2* A = reinterpret_cast<const double2*>(a.A) + d.tab_off;
   const double2 ain = reinterpret_cast<const double2*>(a.Aedge)[2 * pi];
   const double2 aout = reinterpret_cast<const double2*>(a.Aedge)[2 * pi + 1];
@@ -338,9 +345,9 @@ __device__ __forceinline__ void grad_item(const GradArgs& a, int item, int pi, d
     __syncthreads();
     if (len == kChunk) {
 #pragma unroll 4
-      for (int k = 0; k < kChunk; ++k) fwd_step<MODE>(psi, tab[k], pxdt, pydt, qz, qz2, h, inv4h);
+      for (int k = 0; k < kChunk; ++k) fwd_step<MODE>(psi, tab[k], pxdt, pydt, qz, qz2, h, inv4h, fit);
     } else {
-      for (int k = 0; k < len; ++k) fwd_step<MODE>(psi, tab[k], pxdt, pydt, qz, qz2, h, inv4h);
+      for (int k = 0; k < len; ++k) fwd_step<MODE>(psi, tab[k], pxdt, pydt, qz, qz2, h, inv4h, fit);
     }
     if constexpr (MODE < kFineHalving) renormalise(psi);
   }
@@ -402,14 +409,14 @@ __device__ __forceinline__ void grad_item(const GradArgs& a, int item, int pi, d
     if (r != 0) {
 #pragma unroll 1
       for (int j = 0; j < r; ++j)
-        buf[j][lane] = back_any<MODE>(psi, chi, tab[top - j], pxdt, pydt, qz, qz2, h, inv4h, sig);
+        buf[j][lane] = back_any<MODE>(psi, chi, tab[top - j], pxdt, pydt, qz, qz2, h, inv4h, sig, fit);
       group_store(buf, red[wave], lane, top, r);
       top -= r;
     }
     for (; top >= 0; top -= kGroup) {
 #pragma unroll
       for (int j = 0; j < kGroup; ++j)
-        buf[j][lane] = back_any<MODE>(psi, chi, tab[top - j], pxdt, pydt, qz, qz2, h, inv4h, sig);
+        buf[j][lane] = back_any<MODE>(psi, chi, tab[top - j], pxdt, pydt, qz, qz2, h, inv4h, sig, fit);
       group_store(buf, red[wave], lane, top, kGroup);
     }
     __syncthreads();

@@ -1,7 +1,7 @@
-"""Series choice of the second-order evolution (the T series of Sec. II A's exact midpoint step),
+"""Series choice of the second-order evolution (the T polynomial of Sec. II A's exact midpoint step),
 checked on the GPU through the per-variant mode-step counters.  The variant is chosen per block
-of 512 modes and chunk of 256 steps; every (block, chunk) must use a series whose remainder
-bound covers the largest (omega dt)^2 its modes reach over the chunk's steps -- the choice may be
+of 512 modes and chunk of 256 steps; every (block, chunk) must use a polynomial whose error bound
+covers the largest (omega dt)^2 its modes reach over the chunk's steps -- the choice may be
 more conservative than needed, never less -- so, summed over blocks and chunks, the kernel's
 mode-steps at variants <= k never exceed those for which variant k is admissible.  The counts
 also add up to the mode-steps evolved."""
@@ -19,9 +19,9 @@ if not torch.cuda.is_available():  # pragma: no cover - collected on hosts witho
 from paper_1704_08919_amd import api  # noqa: E402
 from paper_1704_08919_amd import workloads as W  # noqa: E402
 
-# Largest x = (omega dt)^2 at which the tan(sqrt x)/sqrt x series of degree 6, 7, ..., 13 has a
-# remainder below 2^-56 (coefficient ratio bound 4/pi^2), rounded down; beyond: angle halving.
-XMAX = (0.0099, 0.0197, 0.0337, 0.0518, 0.0735, 0.0985, 0.1261, 0.1558)
+# Largest x = (omega dt)^2 of the tan(sqrt x)/sqrt x polynomial fits of degree 4, 5, ..., 11 (error
+# below 2^-57 up to there); beyond: angle halving.
+XMAX = (0.002512, 0.009969, 0.02657, 0.05434, 0.09267, 0.1509, 0.2148, 0.2572)
 BLOCK, CHUNK = 512, 256
 
 
