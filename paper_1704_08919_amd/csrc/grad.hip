@@ -14,15 +14,15 @@
 // perturbation of the block eigenvectors, energies -+ omega):
 //     d|->  = -|+><+|dh|->/(2 omega),   d<+|psi> = <+|dh|-><-|psi>/(2 omega),   dP = -dA.
 //
-// Since f_s is the same with chi_s replaced by alpha_s chi_s, the backward sweep carries
-// chi'_s = alpha_s chi_s and each term is 2 Re <chi'_{n+1}| dU/dq_j |psi_n>, of which only
-// Re <chi'|psi> and Im <chi'|tau_k|psi> enter.
+// Since f_s is the same with chi_s replaced by alpha_s chi_s, each term is
+// 2 Re <chi'_{n+1}| dU/dq_j |psi_n> with chi'_s = alpha_s chi_s, and it depends on the two states
+// only through W_s = Im <chi'_s|tau|psi_s>, a real 3-vector that the backward steps rotate.
 //
 // One workgroup of 256 lanes per 256-mode item, one mode per lane.  Forward: the evolution's own
 // step (tangent form or C, S with the pulse's angle halvings), states unit-normalised per block at
-// t_f.  Backward: the table is staged through LDS chunk by chunk in reverse; each step applies U^+
-// to psi and chi' (tangent form with the factors C carried in a per-lane scale, or the exact C, S
-// form on the angle-halving path) and forms the two derivative terms.  Their sum over the item's
+// t_f.  Backward: the table is staged through LDS chunk by chunk in reverse; each step forms the
+// two derivative terms from W_{n+1} and rotates it to W_n (coefficients from the tangent form's
+// fit and a cos^2 series, or from the exact C, S on the angle-halving path).  Their sum over the item's
 // modes is taken per step in a fixed order: each lane stores its terms for 8 steps in LDS, the wave
 // reads them back transposed (lane (j, p) adds the lanes p, p + 8, ..., p + 56 of step j), pairs
 // up the 8 lanes of a step (DPP), and the four waves are added in order; the results are written
@@ -76,12 +76,6 @@ __device__ __forceinline__ Blk block_of(const State& v, int s) {
   return s == 0 ? Blk{v.ar, v.ai, v.br, v.bi} : Blk{v.cr, v.ci, v.dr, v.di};
 }
 
-// z b for a complex scalar z and a block vector b.
-__device__ __forceinline__ Blk cscale(double zr, double zi, const Blk& b) {
-  return Blk{fma(zr, b.ar, -(zi * b.ai)), fma(zr, b.ai, zi * b.ar), fma(zr, b.br, -(zi * b.bi)),
-             fma(zr, b.bi, zi * b.br)};
-}
-
 // Unit eigenvectors of h_s(P) = P_x tau_x + s P_y tau_y + e tau_z: |+> = (w + e, P_x + i s P_y)/N,
 // |-> = (-(P_x - i s P_y), w + e)/N, N = sqrt(2 w (w + e)).
 __device__ __forceinline__ void eig_pm(double Px, double Py, double e, double s, Blk& up, Blk& dn, double& w) {
@@ -110,51 +104,58 @@ __device__ __forceinline__ void tau_xy(const Blk& x, const Blk& y, double s, dou
   yi = s * (b_r - a_r);
 }
 
-// Re <chi| dU/dq_j |psi> for j = x, y of one block, chi = (c1, c2) already carrying the factor
-// alpha, psi = (p1, p2), q = (qx, qy, qz) the block's vector.  Only four real numbers of the
-// block products enter: a = Re <chi|psi> and the imaginary parts of t_k = <chi|tau_k|psi>;
-//   Re[q_j (-S a - i D q.t) - i S t_j] = q_j (D q.Im t - S Re a) + S Im t_j.
-__device__ __forceinline__ void block_grad(double c1r, double c1i, double c2r, double c2i, double p1r, double p1i,
-                                           double p2r, double p2i, double S, double D, double qx, double qy,
-                                           double qz, double& gx, double& gy) {
-  const double a = fma(c2i, p2i, fma(c2r, p2r, fma(c1i, p1i, c1r * p1r)));
-  const double tx = fma(-c2i, p1r, fma(c2r, p1i, fma(-c1i, p2r, c1r * p2i)));   // Im(c1* p2 + c2* p1)
-  const double ty = fma(-c1i, p2i, fma(-c1r, p2r, fma(c2i, p1i, c2r * p1r)));   // Re(c2* p1 - c1* p2)
-  const double tz = fma(c2i, p2r, fma(-c2r, p2i, fma(-c1i, p1r, c1r * p1i)));   // Im(c1* p1 - c2* p2)
-  const double b = fma(qz, tz, fma(qy, ty, qx * tx));
-  const double w = fma(D, b, -(S * a));
-  gx = fma(qx, w, S * tx);
-  gy = fma(qy, w, S * ty);
+// The backward sweep carries, per block, the real 3-vector W = Im <chi'|tau|psi> instead of the two
+// states.  Moving both states back by one step changes V_k = <chi'|tau_k|psi> by the rotation that
+// the step induces on the Pauli vector,
+//     U tau_k U^+ = (C^2 - S^2 x) tau_k + 2 S^2 q_k (q.tau) - 2 C S (e_k x q).tau,
+// which is real, so W_n = (C^2 - S^2 x) W + 2 S^2 (q.W) q - 2 C S (q x W) with W = W_{n+1}.  And
+// since dU/dq_j U^+ = -i [q_j (S^2 + C D) q.tau + C S tau_j - S^2 (e_j x q).tau] has no identity part,
+//     Re <chi'_{n+1}| dU/dq_j |psi_n> = Re <chi'_{n+1}| dU/dq_j U^+ |psi_{n+1}>
+//                                    = q_j (S^2 + C D)(q.W) + C S W_j - S^2 (q x W)_j.
+// Block s = -1 has q = (q_x, -q_y, q_z); its y term enters with the sign s (dq_y/dA_y = -s dt).
+struct WPair {
+  double ax, ay, az;  // block s = +1
+  double bx, by, bz;  // block s = -1
+};
+
+// One backward step on W given the step's coefficients: k1 = C^2 - S^2 x, kq = 2 S^2, cb = S^2 + C D,
+// cs = C S, and the cross products u x W with u = l q, where the rotation takes -(2 C S / l) (u x W)
+// and the terms -(S^2 / l) (u x W).  Returns the two terms summed over the blocks.
+__device__ __forceinline__ double2 back_w(WPair& w, double qx, double qy, double qz, double k1, double kq, double cb,
+                                          double cs, double l, double rot_c, double term_c) {
+  const double ux = l * qx, uy = l * qy, uz = l * qz;
+  const double p0 = fma(qz, w.az, fma(qy, w.ay, qx * w.ax));
+  const double p1 = fma(qz, w.bz, fma(-qy, w.by, qx * w.bx));
+  const double c0x = fma(uy, w.az, -(uz * w.ay)), c0y = fma(uz, w.ax, -(ux * w.az)), c0z = fma(ux, w.ay, -(uy * w.ax));
+  const double c1x = fma(-uy, w.bz, -(uz * w.by)), c1y = fma(uz, w.bx, -(ux * w.bz)), c1z = fma(ux, w.by, uy * w.bx);
+  const double bp = cb * (p0 + p1);
+  const double gx = fma(qx, bp, fma(-term_c, c0x + c1x, cs * (w.ax + w.bx)));
+  const double gy = fma(qy, bp, fma(-term_c, c0y - c1y, cs * (w.ay - w.by)));
+  const double kp0 = kq * p0, kp1 = kq * p1;
+  w.ax = fma(k1, w.ax, fma(kp0, qx, -(rot_c * c0x)));
+  w.ay = fma(k1, w.ay, fma(kp0, qy, -(rot_c * c0y)));
+  w.az = fma(k1, w.az, fma(kp0, qz, -(rot_c * c0z)));
+  w.bx = fma(k1, w.bx, fma(kp1, qx, -(rot_c * c1x)));
+  w.by = fma(k1, w.by, fma(-kp1, qy, -(rot_c * c1y)));
+  w.bz = fma(k1, w.bz, fma(kp1, qz, -(rot_c * c1z)));
+  return make_double2(gx, gy);
 }
 
-// One backward step n: psi <- U_n^+ psi (psi_{n+1} -> psi_n), the derivative terms with chi_{n+1},
-// then chi <- U_n^+ chi.  Returns (sum_s Re<chi|dU/dq_x|psi>, sum_s s Re<chi|dU/dq_y|psi>).
-// SERIES: the step angle is within the degree-7 range (no halving, D from its own series).
-template <bool SERIES>
-__device__ __forceinline__ double2 back_step(State& psi, State& chi, double2 r, double pxdt, double pydt, double qz,
-                                             double qz2, int h, double inv4h) {
+// Exact C, S form (the angle-halving path): l = 1, the products with 2 C S and S^2 are explicit.
+__device__ __forceinline__ double2 back_w_exact(WPair& w, double2 r, double pxdt, double pydt, double qz, double qz2,
+                                                int h, double inv4h) {
   const double qx = pxdt + r.x, qy = pydt + r.y;
   const double x = fma(qx, qx, fma(qy, qy, qz2));
   double C, S, D;
-  if constexpr (SERIES) {
-    csd_series(x, C, S, D);
-  } else {
-    csd(x, h, inv4h, C, S, D);
-  }
-  rotate(psi, C, -S, qx, qy, qz);
-  double gx0, gy0, gx1, gy1;
-  block_grad(chi.ar, chi.ai, chi.br, chi.bi, psi.ar, psi.ai, psi.br, psi.bi, S, D, qx, qy, qz, gx0, gy0);
-  block_grad(chi.cr, chi.ci, chi.dr, chi.di, psi.cr, psi.ci, psi.dr, psi.di, S, D, qx, -qy, qz, gx1, gy1);
-  rotate(chi, C, -S, qx, qy, qz);
-  return make_double2(gx0 + gx1, gy0 - gy1);
+  csd(x, h, inv4h, C, S, D);
+  const double S2 = S * S, cs = C * S;
+  return back_w(w, qx, qy, qz, fma(-S2, x, C * C), S2 + S2, fma(C, D, S2), cs, 1.0, cs + cs, S2);
 }
 
-// Tangent form of the backward step (steps within the T-series range).  With U = C (1 - i T Q)
-// and S = C T, D = (C - S)/x = -C R where R = (T - 1)/x, the step applies (1 + i T Q) to psi and
-// chi' and leaves out the factors C: psi_n = sigma_n psi~_n and chi'_{n+1} = sigma_{n+1} chi~_{n+1}
-// with sigma_n = C_n sigma_{n+1}, so the term of step n is Sigma_n = sigma_n^2 = C_n^2 Sigma_{n+1}
-// times the same expression in psi~, chi~ with (S, D) -> (T, -R).  C^2 = cos^2 sqrt x comes from its
-// own series, R is the variant's fit (T = 1 + x R).
+// Tangent form (steps within the fit's range): with S = C T and C D = -C^2 R, R = (T - 1)/x, the
+// coefficients are C^2 (1 - T^2 x), 2 C^2 T^2, C^2 (T^2 - R) and C^2 T; C^2 = cos^2 sqrt x comes
+// from its own series, R is the variant's fit (T = 1 + x R).  The cross products carry l = 2 C^2 T,
+// which the rotation takes as it is and the terms times S^2 / l = T / 2.
 // cos^2 sqrt x = 1 + sum_{k >= 1} (-1)^k 2^(2k-1) x^k / (2k)!, alternating with decreasing terms;
 // degree kFitCos2Degree[v] keeps the remainder below 2^-59 up to the variant's largest x.
 constexpr double pow2i(int n) { return n == 0 ? 1.0 : 2.0 * pow2i(n - 1); }
@@ -176,30 +177,17 @@ __device__ __forceinline__ double cos2_series(double x) {
 }
 
 template <int MODE>
-__device__ __forceinline__ double2 back_step_tan(State& psi, State& chi, double2 r, double pxdt, double pydt,
-                                                 double qz, double qz2, double& sig, const Fit<MODE>& f) {
+__device__ __forceinline__ double2 back_w_tan(WPair& w, double2 r, double pxdt, double pydt, double qz, double qz2,
+                                              const Fit<MODE>& f) {
   constexpr int M = kFitCos2Degree[MODE];
   const double qx = pxdt + r.x, qy = pydt + r.y;
   const double x = fma(qx, qx, fma(qy, qy, qz2));
   const double R = fit_R<MODE>(x, f);
   const double T = fma(R, x, 1.0);
   const double c2 = cos2_series<M>(x);
-  rotate_tan(psi, -T, qx, qy, qz);
-  double gx0, gy0, gx1, gy1;
-  block_grad(chi.ar, chi.ai, chi.br, chi.bi, psi.ar, psi.ai, psi.br, psi.bi, T, -R, qx, qy, qz, gx0, gy0);
-  block_grad(chi.cr, chi.ci, chi.dr, chi.di, psi.cr, psi.ci, psi.dr, psi.di, T, -R, qx, -qy, qz, gx1, gy1);
-  rotate_tan(chi, -T, qx, qy, qz);
-  sig *= c2;
-  return make_double2(sig * (gx0 + gx1), sig * (gy0 - gy1));
-}
-
-// Folds Sigma back into the states (psi~, chi~ <- sqrt(Sigma) psi~, chi~ are then the true states) so
-// Sigma restarts at 1; once per chunk, which keeps Sigma far from underflow.
-__device__ __forceinline__ void fold_scale(State& psi, State& chi, double& sig) {
-  const double s = sqrt(sig);
-  psi.ar *= s; psi.ai *= s; psi.br *= s; psi.bi *= s; psi.cr *= s; psi.ci *= s; psi.dr *= s; psi.di *= s;
-  chi.ar *= s; chi.ai *= s; chi.br *= s; chi.bi *= s; chi.cr *= s; chi.ci *= s; chi.dr *= s; chi.di *= s;
-  sig = 1.0;
+  const double T2 = T * T;
+  const double cs = c2 * T, s2 = cs * T;
+  return back_w(w, qx, qy, qz, c2 * fma(-T2, x, 1.0), s2 + s2, c2 * (T2 - R), cs, cs + cs, 1.0, 0.5 * T);
 }
 
 // Coefficients of the fit for the tangent-form variants (an empty record for the halving path).
@@ -218,13 +206,12 @@ __device__ __forceinline__ typename FitOf<MODE>::type load_fit_of() {
   else return typename FitOf<MODE>::type{};
 }
 
-// One backward step in the form of the pulse's variant: tangent form (scale in sig) or exact C, S.
+// One backward step in the form of the pulse's variant.
 template <int MODE>
-__device__ __forceinline__ double2 back_any(State& psi, State& chi, double2 r, double pxdt, double pydt, double qz,
-                                            double qz2, int h, double inv4h, double& sig,
-                                            const typename FitOf<MODE>::type& f) {
-  if constexpr (MODE < kFineHalving) return back_step_tan<MODE>(psi, chi, r, pxdt, pydt, qz, qz2, sig, f);
-  else return back_step<false>(psi, chi, r, pxdt, pydt, qz, qz2, h, inv4h);
+__device__ __forceinline__ double2 back_any(WPair& w, double2 r, double pxdt, double pydt, double qz, double qz2, int h,
+                                            double inv4h, const typename FitOf<MODE>::type& f) {
+  if constexpr (MODE < kFineHalving) return back_w_tan<MODE>(w, r, pxdt, pydt, qz, qz2, f);
+  else return back_w_exact(w, r, pxdt, pydt, qz, qz2, h, inv4h);
 }
 
 // Forward step of the evolution in the form the pulse's series choice selects.
@@ -352,8 +339,9 @@ __device__ __forceinline__ void grad_item(const GradArgs& a, int item, int pi, d
     if constexpr (MODE < kFineHalving) renormalise(psi);
   }
 
-  // t_f: normalise each block, alpha_s = <+_s(P_out)|psi_s>, final-state terms; chi_s = alpha_s |+_s>
-  State chi;
+  // t_f: normalise each block, alpha_s = <+_s(P_out)|psi_s>, final-state terms, and
+  // W_s = Im(conj(alpha_s) <+_s|tau|psi_s>), the start of the backward sweep (chi'_s = alpha_s |+_s>)
+  WPair w;
   double g_out_x = 0.0, g_out_y = 0.0, f = 0.0;
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
@@ -380,18 +368,21 @@ __device__ __forceinline__ void grad_item(const GradArgs& a, int item, int pi, d
     const double tmy_r = fma(yr, mr, -(yi * mi)), tmy_i = fma(yr, mi, yi * mr);
     g_out_x += 2.0 * k * fma(al_r, tmx_r, al_i * tmx_i);
     g_out_y += 2.0 * k * fma(al_r, tmy_r, al_i * tmy_i);
-    const Blk cb = cscale(al_r, al_i, up_out);
+    // <+|tau_x|psi>, <+|tau_y|psi> (tau_y itself: s = 1), <+|tau_z|psi> = conj(u1) p1 - conj(u2) p2
+    double vxr, vxi, vyr, vyi;
+    tau_xy(up_out, p, 1.0, vxr, vxi, vyr, vyi);
+    const double vzr = fma(up_out.ar, p.ar, fma(up_out.ai, p.ai, -fma(up_out.br, p.br, up_out.bi * p.bi)));
+    const double vzi = fma(up_out.ar, p.ai, fma(-up_out.ai, p.ar, -fma(up_out.br, p.bi, -(up_out.bi * p.br))));
+    const double wx = fma(al_r, vxi, -(al_i * vxr)), wy = fma(al_r, vyi, -(al_i * vyr)),
+                 wz = fma(al_r, vzi, -(al_i * vzr));
     if (s == 0) {
-      psi.ar = p.ar; psi.ai = p.ai; psi.br = p.br; psi.bi = p.bi;
-      chi.ar = cb.ar; chi.ai = cb.ai; chi.br = cb.br; chi.bi = cb.bi;
+      w.ax = wx; w.ay = wy; w.az = wz;
     } else {
-      psi.cr = p.ar; psi.ci = p.ai; psi.dr = p.br; psi.di = p.bi;
-      chi.cr = cb.ar; chi.ci = cb.ai; chi.dr = cb.br; chi.di = cb.bi;
+      w.bx = wx; w.by = wy; w.bz = wz;
     }
   }
 
   // backward over the chunks in reverse, kGroup steps at a time (the last group of a chunk may be short)
-  double sig = 1.0;  // Sigma of the tangent form (unused by the exact form)
   double* part = a.part + a.goff[pi] + int64_t(li) * nt * 2;
   double2 (*buf)[64] = bufs[wave];
   for (int c = nchunks - 1; c >= 0; --c) {
@@ -402,21 +393,19 @@ __device__ __forceinline__ void grad_item(const GradArgs& a, int item, int pi, d
       tab[threadIdx.x] = make_double2(-t.x * dt, -t.y * dt);
     }
     __syncthreads();
-    if constexpr (MODE < kFineHalving) fold_scale(psi, chi, sig);
     // a short group first (len not a multiple of kGroup), then full groups
     int top = len - 1;
     const int r = len % kGroup;
     if (r != 0) {
 #pragma unroll 1
-      for (int j = 0; j < r; ++j)
-        buf[j][lane] = back_any<MODE>(psi, chi, tab[top - j], pxdt, pydt, qz, qz2, h, inv4h, sig, fit);
+      for (int j = 0; j < r; ++j) buf[j][lane] = back_any<MODE>(w, tab[top - j], pxdt, pydt, qz, qz2, h, inv4h, fit);
       group_store(buf, red[wave], lane, top, r);
       top -= r;
     }
     for (; top >= 0; top -= kGroup) {
 #pragma unroll
       for (int j = 0; j < kGroup; ++j)
-        buf[j][lane] = back_any<MODE>(psi, chi, tab[top - j], pxdt, pydt, qz, qz2, h, inv4h, sig, fit);
+        buf[j][lane] = back_any<MODE>(w, tab[top - j], pxdt, pydt, qz, qz2, h, inv4h, fit);
       group_store(buf, red[wave], lane, top, kGroup);
     }
     __syncthreads();
@@ -431,23 +420,13 @@ __device__ __forceinline__ void grad_item(const GradArgs& a, int item, int pi, d
     }
   }
 
-  if constexpr (MODE < kFineHalving) fold_scale(psi, chi, sig);  // chi~ -> the true chi'_0
-
-  // t_i: d|-> = -|+><+|dh|->/(2 w), dP = -dA(t_i); chi holds U^+ ... alpha |+_out> = alpha chi_0
-  double g_in_x = 0.0, g_in_y = 0.0;
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    const double sg = s == 0 ? 1.0 : -1.0;
-    Blk up_in, dn_in;
-    double w_in;
-    eig_pm(px - ain.x, py - ain.y, e, sg, up_in, dn_in, w_in);
-    double xr, xi, yr, yi, cr, ci;
-    tau_xy(up_in, dn_in, sg, xr, xi, yr, yi);
-    inner(block_of(chi, s), up_in, cr, ci);
-    const double k = 1.0 / (2.0 * w_in);  // (-1/(2w)) * (dP/dA = -1)
-    g_in_x += 2.0 * k * fma(cr, xr, -(ci * xi));
-    g_in_y += 2.0 * k * fma(cr, yr, -(ci * yi));
-  }
+  // t_i: d|-> = -|+><+|dh|->/(2 w), dP = -dA(t_i).  With chi'_0 = a |+> + b |->, the part of W_0
+  // across n = (P_x, s P_y, e)/w gives conj(a) <+|tau_k|-> = (n x W_0)_k, so the term of block s is
+  // (n x W_0)_x / w for x and s (n x W_0)_y / w for y.
+  const double Px = px - ain.x, Py = py - ain.y;
+  const double inv_w2 = 1.0 / fma(Px, Px, fma(Py, Py, e * e));
+  const double g_in_x = (fma(Py, w.az - w.bz, -(e * (w.ay + w.by)))) * inv_w2;
+  const double g_in_y = (fma(e, w.ax - w.bx, -(Px * (w.az - w.bz)))) * inv_w2;
   const double e4[4] = {g_in_x, g_in_y, g_out_x, g_out_y};
   __syncthreads();
   for (int j = 0; j < 4; ++j) {

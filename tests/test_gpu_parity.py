@@ -289,3 +289,25 @@ def test_de_generation_workload_full_size_sampled(orc):
     dv = (4 / 64) * (4 / 64) * (2 / 16)
     for pi in range(0, 64, 9):
         assert abs(J[pi] - dv * math.fsum(f[pi * M:(pi + 1) * M])) <= 1e-13 * J[pi]
+
+
+def test_surrogate_de_workload_full_size_sampled(orc):
+    """Three pulses of the surrogate-DE evaluator (128x128x32 modes, nt = 32768, T = 800) in one
+    call; sampled modes vs the oracle, J vs the ordered sum of the stored f."""
+    spec, g = W.surrogate_de_spec()
+    coeff = W.draw_coeff(5, 3, 8)
+    say("full-size surrogate-DE evaluator, 3 pulses")
+    J, f = api.evaluate([spec] * 3, [g] * 3, coeff, want_f=True)
+    J, f = host(J), host(f)
+    M = W.n_modes(g)
+    assert M == 128 * 128 * 32
+    assert np.all(np.isfinite(f)) and np.all(f >= 0) and np.all(f <= 2)
+    p, _ = orc.grid_points(g)
+    for pi in (0, 2):
+        Ar, _, er, _ = orc.synth(spec, coeff[pi])
+        idx = W.sample_mode_indices(100 + pi, M, 16)
+        fr = orc.evolve_points(Ar, er, spec["T"] / spec["nt"], p[idx])
+        assert_modes(f[pi * M + idx], fr, spec["nt"], f"surrogate-DE size pulse {pi} sampled")
+    dv = (4 / 128) * (4 / 128) * (2 / 32)
+    for pi in range(3):
+        assert abs(J[pi] - dv * math.fsum(f[pi * M:(pi + 1) * M])) <= 1e-13 * J[pi]
