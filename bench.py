@@ -39,7 +39,7 @@ HERE_PROFILES = os.path.join(ROOT, "profiles")
 PLAN = dict(threads=256, modes_per_lane=1, persistent=1)
 
 
-EVOLVE_SOURCES = ("evolve.hip", "dirac.hpp", "reduce.hpp", "common.hpp")
+EVOLVE_SOURCES = ("evolve.hip", "dirac.hpp", "tan_fit.hpp", "reduce.hpp", "common.hpp")
 
 
 def evolve_sources_sha256():

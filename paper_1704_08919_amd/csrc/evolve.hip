@@ -357,7 +357,7 @@ __device__ __forceinline__ void process_item(const EvolveArgs& a, int pi, int fi
 }
 
 // One workgroup per 256-mode item; four waves per SIMD (the register budget of the variant
-// switch; only the chunk loop of the angle-halving path spills, outside its step loops).
+// switch, met without spills).
 __global__ void __launch_bounds__(kItem) __attribute__((amdgpu_waves_per_eu(4))) k_evolve(EvolveArgs a) {
   __shared__ double2 lds[2][kChunk];
   const int item = xcd_item(blockIdx.x, gridDim.x);
@@ -369,9 +369,10 @@ __global__ void k_reset_counter(int* counter) { *counter = 0; }
 
 // Persistent workgroups: pull {pulse, first mode} items in queue order until the queue is empty.
 // Every workgroup reaches the exit: the counter only grows, and each pull returns a new index.
-// Register budget: four waves per SIMD with one mode per lane, three with two.
+// Register budget: four waves per SIMD with one mode per lane; two with two modes per lane, which
+// keep the same number of modes in flight per SIMD without spilling.
 template <int THREADS, int MPL>
-__global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(MPL == 1 ? 4 : 3)))
+__global__ void __launch_bounds__(THREADS) __attribute__((amdgpu_waves_per_eu(MPL == 1 ? 4 : 2)))
 k_evolve_persistent(EvolveArgs a, const int2* __restrict__ queue, int n_items, int* __restrict__ counter) {
   __shared__ double2 lds[2][kChunk];
   __shared__ int s_item;
