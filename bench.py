@@ -42,13 +42,24 @@ PLAN = dict(threads=256, modes_per_lane=1, persistent=1)
 EVOLVE_SOURCES = ("evolve.hip", "dirac.hpp", "tan_fit.hpp", "reduce.hpp", "common.hpp")
 
 
+def code_lines(text):
+    """The lines of a C++ source without // comments, trailing blanks and empty lines (the
+    evolution sources hold no block comments and no '//' inside string literals)."""
+    out = []
+    for line in text.splitlines():
+        code = line.split("//", 1)[0].rstrip()
+        if code:
+            out.append(code)
+    return "\n".join(out) + "\n"
+
+
 def evolve_sources_sha256():
-    """Hash of the sources the evolution kernel is compiled from."""
+    """Hash of the code (comments left out) the evolution kernel is compiled from."""
     import hashlib
     h = hashlib.sha256()
     for name in EVOLVE_SOURCES:
-        with open(os.path.join(ROOT, "paper_1704_08919_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1704_08919_amd", "csrc", name), encoding="utf-8") as fh:
+            h.update(code_lines(fh.read()).encode())
     return h.hexdigest()
 
 

@@ -17,11 +17,12 @@
 // applies only 1 - i T Q_s (three FMAs per real component) and divides by the norms at the
 // end; the state is rescaled by an exact power of two once per LDS chunk to stay in range.
 // For any value of T, 1 - i T Q_s is a scalar multiple of a unitary matrix (its square modulus
-// is (1 + T^2 x) 1), so rounding in T perturbs only the rotation angle.  T -- or C and S on the
-// large-step path, which halves the angle -- is a truncated Maclaurin series in x whose
-// remainder is below 2^-56 on the whole range of x of the 512-mode block the item belongs to and
-// the 256-step chunk (a box of momenta against the range of the table in the chunk); it is shared
-// by both blocks, because omega does not depend on s.
+// is (1 + T^2 x) 1), so rounding in T perturbs only the rotation angle.  T is a polynomial in x
+// (a fit of (T - 1)/x whose error is below 2^-57) of the lowest degree that covers the whole
+// range of x of the 512-mode block the item belongs to in the 256-step chunk (a box of momenta
+// against the range of the table in the chunk); beyond the fits' range the large-step path
+// halves the angle and takes C and S from truncated Maclaurin series (remainder below 2^-56).
+// Either is shared by both blocks, because omega does not depend on s.
 //
 // Work decomposition: a workgroup of THREADS lanes (64-wide waves) owns an item of
 // THREADS x MPL consecutive modes of one pulse, MPL modes per lane.  The pulse's table of -A dt

@@ -46,3 +46,10 @@ def test_fp64_counter_record_fields():
         v = c["counters"]
         fl = 64 * (2 * v["SQ_INSTS_VALU_FMA_F64"] + v["SQ_INSTS_VALU_MUL_F64"] + v["SQ_INSTS_VALU_ADD_F64"])
         assert abs(fl - c["fp64_flop"]) <= 1e-9 * fl
+
+
+def test_source_hash_ignores_comments_only():
+    text = "int a = 1;  // one\n// a comment line\n\n  b(a);   \n"
+    assert bench.code_lines(text) == "int a = 1;\n  b(a);\n"
+    assert bench.code_lines(text + "// more\n") == bench.code_lines(text)
+    assert bench.code_lines(text.replace("1;", "2;")) != bench.code_lines(text)
