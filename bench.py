@@ -196,6 +196,35 @@ def surrogate_de(api, W, S, torch, pop=512, generations=200, seed=0):
     return out
 
 
+def surrogate_de_full(api, W, S, torch, phase, generations, seed=0, target_J=None, plain_wall_s=None):
+    """Surrogate-assisted DE at the full configuration (pop 512, 2x(8+8) coefficients, T = 800,
+    nt = 32768, 128x128x32 modes), one phase per process (a plain generation takes ~10 s):
+    phase "plain" runs plain DE for `generations`; phase "surrogate" runs the screened DE from the
+    same seed and initial population until the best J reaches target_J (0.99 of the plain run's
+    best) or plain_wall_s passes.  Prints progress every generation."""
+    spec, grid = W.surrogate_de_spec()
+    pop = 512
+    per_gen = pop * W.n_modes(grid) * spec["nt"]
+    out = {"workload": f"surrogate_de_full: pop {pop}, T=800, nt=32768, 128x128x32 modes, seed {seed}",
+           "phase": phase, "mode_steps_per_plain_generation": per_gen}
+    if phase == "plain":
+        r = S.run_de(spec, grid, pop, generations, seed, mode="plain", plan_config=PLAN, progress_every=1)
+        out.update({k: r[k] for k in ("generations", "wall_s", "plain_evaluations", "best_J")})
+        out["s_per_generation"] = r["wall_s"] / (r["generations"] + 1)  # + the initial population
+        out["mode_steps_per_s"] = per_gen * (r["generations"] + 1) / r["wall_s"]
+        out["target_J_next_phase"] = 0.99 * r["best_J"]
+        out["plain_time_to_target_s"] = S.time_to_reach(r["history"], 0.99 * r["best_J"])
+    else:
+        r = S.run_de(spec, grid, pop, 10 * generations, seed, mode="surrogate", time_limit=plain_wall_s,
+                     target=target_J, plan_config=PLAN, progress_every=1)
+        tt = S.time_to_reach(r["history"], target_J)
+        out.update({k: r[k] for k in ("generations", "wall_s", "plain_evaluations", "best_J", "train_s")})
+        out.update({"target_J": target_J, "plain_wall_s": plain_wall_s, "time_to_target_s": tt,
+                    "speedup_vs_plain_wall": plain_wall_s / tt if tt else None})
+    out["history_every_10"] = [list(h) for h in r["history"][::10]] + [list(r["history"][-1])]
+    return out
+
+
 def de_variants(api, W, torch, pop=64, generations=60, islands=4, migrate_every=5, seed=0):
     """Plain DE/rand/1/bin (F = 0.8, CR = 0.9, one population) against self-adaptive jDE on
     `islands` islands with ring migration every `migrate_every` generations (Sec. IV B), from the
@@ -358,6 +387,11 @@ def main():
                     help="skip the accuracy-versus-time comparison of the Dirac, Magnus and kinetic solvers")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a plain 512 MiB device copy first (reference for HBM counter scaling)")
+    ap.add_argument("--surrogate-de-full", choices=("plain", "surrogate"),
+                    help="run only one phase of the full-configuration surrogate-DE comparison")
+    ap.add_argument("--full-generations", type=int, default=80, help="plain-DE generations of that comparison")
+    ap.add_argument("--target-J", type=float, help="surrogate phase: 0.99 x the plain phase's best J")
+    ap.add_argument("--plain-wall-s", type=float, help="surrogate phase: the plain phase's wall time")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the library has no multi-GPU path",
@@ -370,6 +404,13 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.surrogate_de_full:
+        from paper_1704_08919_amd import surrogate as S
+        if args.surrogate_de_full == "surrogate" and (args.target_J is None or args.plain_wall_s is None):
+            ap.error("--surrogate-de-full surrogate needs --target-J and --plain-wall-s from the plain phase")
+        print(json.dumps(surrogate_de_full(api, W, S, torch, args.surrogate_de_full, args.full_generations,
+                                           args.seed, args.target_J, args.plain_wall_s)), flush=True)
+        return
     if args.calibrate_copy:
         src = torch.ones(64 * 2 ** 20, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)

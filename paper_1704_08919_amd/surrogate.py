@@ -16,6 +16,7 @@ history on the host.
 from __future__ import annotations
 
 import math
+import sys
 import time
 
 import numpy as np
@@ -139,11 +140,12 @@ def _best(fit):
 
 def run_de(spec, grid, pop=512, generations=200, seed=0, mode="surrogate", top=0.1, retrain_every=20,
            epochs_initial=60, epochs_retrain=15, retrain_steps=150, width=256, depth=3, time_limit=None,
-           target=None, F=0.8, CR=0.9, plan_config=None):
+           target=None, F=0.8, CR=0.9, plan_config=None, progress_every=0):
     """One DE run.  mode: "plain" (every trial evaluated), "surrogate" (network screening) or
     "random" (random screening, the ablation).  Stops after `generations`, at `time_limit`
     seconds, or once the best plain-evaluated J reaches `target`.  Returns a dict with the
-    best-so-far history (seconds, plain evaluations, J)."""
+    best-so-far history (seconds, plain evaluations, J).  progress_every > 0 prints the
+    best-so-far to stderr every that many generations."""
     n_s = spec["n_s"]
     D = 4 * n_s
     k = pop if mode == "plain" else int(math.ceil(top * pop))
@@ -196,6 +198,9 @@ def run_de(spec, grid, pop=512, generations=200, seed=0, mode="surrogate", top=0
         evals += k
         best = _best(fit)
         hist.append((time.perf_counter() - t0, evals, best))
+        if progress_every and (g + 1) % progress_every == 0:
+            print(f"{mode} DE generation {g + 1}: {hist[-1][0]:.1f} s, {evals} plain evaluations, best J {best:.6e}",
+                  file=sys.stderr, flush=True)
         if target is not None and best >= target:
             break
         if time_limit is not None and hist[-1][0] >= time_limit:
