@@ -22,12 +22,12 @@
 // step (tangent form or C, S with the pulse's angle halvings), states unit-normalised per block at
 // t_f.  Backward: the table is staged through LDS chunk by chunk in reverse; each step forms the
 // two derivative terms from W_{n+1} and rotates it to W_n (coefficients from the tangent form's
-// fit and a cos^2 series, or from the exact C, S on the angle-halving path).  Their sum over the item's
-// modes is taken per step in a fixed order: each lane stores its terms for 8 steps in LDS, the wave
-// reads them back transposed (lane (j, p) adds the lanes p, p + 8, ..., p + 56 of step j), pairs
-// up the 8 lanes of a step (DPP), and the four waves are added in order; the results are written
-// as item partials [item][n][2], and a second kernel sums the items of each pulse in order.  So
-// the gradient, like J, does not depend on scheduling.
+// fit and a cos^2 series, or from the exact C, S on the angle-halving path).  Their sum over the
+// item's modes is taken per step in a fixed order: each lane stores its terms for 8 steps in LDS,
+// the wave reads them back transposed (lane (j, p) adds the lanes p, p + 8, ..., p + 56 of step
+// j), pairs up the 8 lanes of a step (DPP), and the four waves are added in order; the results are
+// written as item partials [item][n][2], and a second kernel sums the items of each pulse in
+// order.  So the gradient, like J, does not depend on scheduling.
 #include "dirac.hpp"
 #include "reduce.hpp"
 
