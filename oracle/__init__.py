@@ -62,6 +62,7 @@ def lib():
             "orc_field_samples_ld": (None, [c_int, c_int, c_double, c_double, c_double, c_int, c_int, c_double,
                                             _D, c_int, _D, c_int, _D, _D, _D]),
             "orc_evolve4_points_ld": (None, [c_int, c_double, _D, _D, c_long, _D, _D, c_int]),
+            "orc_evolve_split_points_ld": (None, [c_int, c_int, c_double, _D, _D, c_long, _D, _D, c_int]),
             "orc_grad_table_fd_ld": (None, [c_int, c_double, _D, _D, _I, _D, _D, c_double, c_int, _L, _D, c_int]),
             "orc_grad_coeff_fd_ld": (None, [c_int, c_int, c_double, c_double, c_double, c_int, c_int, c_double, _D, _I,
                                             _D, _D, c_double, _D, _D, _D, _D, c_int]),
@@ -237,6 +238,24 @@ def evolve4_points(A_gauss, A_edge, dt, p, nthreads=0):
     nt = A_gauss.size // 4
     f = np.zeros(p.shape[0])
     lib().orc_evolve4_points_ld(nt, float(dt), _d(A_gauss), _d(A_edge), p.shape[0], _d(p), _d(f), int(nthreads))
+    return f
+
+
+_W1 = 1.0 / (2.0 - 2.0 ** (1.0 / 3.0))
+SPLIT4_OFFSETS = (_W1 / 2, 0.5, 1.0 - _W1 / 2)  # substep midpoints of the fourth-order splitting
+
+
+def evolve_split_points(A_tab, A_edge, dt, p, order=2, nthreads=0):
+    """Pair density f by the split-operator step (Sec. II A; H_0 = alpha_z p_z + beta m against the
+    field-driven transverse part): order 2 = Strang with A_tab[nt][2] at the step midpoints,
+    order 4 = its triple-jump composition with A_tab[nt][3][2] at SPLIT4_OFFSETS of every step."""
+    A_tab, A_edge, p = _arr(A_tab), _arr(A_edge), _arr(p).reshape(-1, 3)
+    if order not in (2, 4):
+        raise ValueError("order must be 2 or 4")
+    nt = A_tab.size // (2 if order == 2 else 6)
+    f = np.zeros(p.shape[0])
+    lib().orc_evolve_split_points_ld(int(order), nt, float(dt), _d(A_tab), _d(A_edge), p.shape[0], _d(p), _d(f),
+                                     int(nthreads))
     return f
 
 

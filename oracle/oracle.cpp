@@ -394,6 +394,87 @@ R evolve4_mode(int nt, R dt, const double* Ag, const double Ain[2], const double
 }
 
 // ---------------------------------------------------------------------------------------
+// Split-operator steps (Sec. II A names a second-order split-operator scheme; Sec. V C names a
+// fourth-order splitting as future work).  The frozen Hamiltonian splits into the part the field
+// does not touch and the field-driven transverse part,
+//   H_0 = alpha_z p_z + beta m,   H_perp(t) = alpha_x P_x(t) + alpha_y P_y(t),
+// (at p_z = 0 this is the mass / kinetic split), and each factor is exponentiated exactly:
+// H_0^2 = (m^2 + p_z^2) 1 and H_perp^2 = (P_x^2 + P_y^2) 1, so
+//   exp(-i H h) = cos(|H| h) - i sin(|H| h) / |H| * H   for either part.
+// One Strang step of size h with the transverse field frozen at the step midpoint:
+//   psi <- exp(-i H_0 h/2) exp(-i H_perp(t + h/2) h) exp(-i H_0 h/2) psi.
+// Fourth order: the triple-jump composition of that symmetric step (Yoshida, Phys. Lett. A 150
+// (1990) 262), sizes w1 dt, w0 dt, w1 dt with w1 = 1 / (2 - 2^(1/3)), w0 = 1 - 2 w1; the field of
+// substep i is taken at its own midpoint, i.e. at t_n + c_i dt with c = (w1/2, 1/2, 1 - w1/2).
+// At[nt][nsub][2] holds A at those points (nsub = 1: the step midpoint).
+// ---------------------------------------------------------------------------------------
+template <class R>
+void apply_matrix(const C<R> U[4][4], C<R> psi[4]) {
+  C<R> nxt[4];
+  for (int a = 0; a < 4; ++a) {
+    nxt[a] = 0;
+    for (int b = 0; b < 4; ++b) nxt[a] += U[a][b] * psi[b];
+  }
+  for (int a = 0; a < 4; ++a) psi[a] = nxt[a];
+}
+
+// exp(-i H h) for a Hermitian 4x4 H with H^2 = w^2 1 (w >= 0).
+template <class R>
+void exp_involutive(const C<R> H[4][4], R w, R h, C<R> U[4][4]) {
+  const R c = std::cos(w * h), sw = (w > 0) ? std::sin(w * h) / w : h;
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) U[a][b] = (a == b ? C<R>(c) : C<R>(0)) - C<R>(0, 1) * sw * H[a][b];
+}
+
+template <class R>
+R evolve_split_mode(int nt, R dt, int nsub, const double* At, const double Ain[2], const double Aout[2],
+                    const double p[3]) {
+  const R px = R(p[0]), py = R(p[1]), pz = R(p[2]);
+  const R w1 = R(1) / (R(2) - std::cbrt(R(2)));
+  const R w[3] = {nsub == 1 ? R(1) : w1, R(1) - R(2) * w1, w1};
+  R Pin[3] = {px - R(Ain[0]), py - R(Ain[1]), pz};
+  C<R> u[2][4], v[2][4];
+  R w_in;
+  free_spinors<R>(Pin, u, v, &w_in);
+  C<R> psi[2][4];
+  for (int s = 0; s < 2; ++s) for (int a = 0; a < 4; ++a) psi[s][a] = v[s][a];
+  // H_0 = alpha_z p_z + beta m: the Hamiltonian at P = (0, 0, p_z) minus nothing else.
+  const R Pz[3] = {R(0), R(0), pz};
+  C<R> H0[4][4];
+  hamiltonian<R>(Pz, H0);
+  const R e = std::sqrt(R(1) + pz * pz);
+  for (int n = 0; n < nt; ++n)
+    for (int i = 0; i < nsub; ++i) {
+      const R h = w[i] * dt;
+      const R Px = px - R(At[2 * (nsub * n + i)]), Py = py - R(At[2 * (nsub * n + i) + 1]);
+      // H_perp = alpha_x P_x + alpha_y P_y: the Hamiltonian at (P_x, P_y, 0) without beta m
+      const R Pp[3] = {Px, Py, R(0)};
+      C<R> Hp[4][4], Uh[4][4], Up[4][4];
+      hamiltonian<R>(Pp, Hp);
+      for (int a = 0; a < 4; ++a) Hp[a][a] -= (a < 2 ? R(1) : R(-1));
+      exp_involutive<R>(H0, e, h / R(2), Uh);
+      exp_involutive<R>(Hp, std::sqrt(Px * Px + Py * Py), h, Up);
+      for (int s = 0; s < 2; ++s) {
+        apply_matrix<R>(Uh, psi[s]);
+        apply_matrix<R>(Up, psi[s]);
+        apply_matrix<R>(Uh, psi[s]);
+      }
+    }
+  R Pout[3] = {px - R(Aout[0]), py - R(Aout[1]), pz};
+  C<R> uo[2][4], vo[2][4];
+  R w_out;
+  free_spinors<R>(Pout, uo, vo, &w_out);
+  R f = 0;
+  for (int s = 0; s < 2; ++s)
+    for (int sp = 0; sp < 2; ++sp) {
+      C<R> ov = 0;
+      for (int a = 0; a < 4; ++a) ov += std::conj(uo[sp][a]) * psi[s][a];
+      f += std::norm(ov);
+    }
+  return f / ((R(2) * w_out) * (R(2) * w_in));
+}
+
+// ---------------------------------------------------------------------------------------
 // Quantum kinetic equation (Sec. II B), 6 components, classical RK4.  The paper's field
 // plane (e_2, e_3) is the x-y plane here and e_1 is z (a cyclic relabelling, so
 // (E x Edot).e_1 = Ex Edot_y - Ey Edot_x and p_1 = p_z).  f = 1 - chi_1.
@@ -801,6 +882,18 @@ void orc_evolve4_points_ld(int nt, double dt, const double* Ag, const double* Ae
   const int nth = nthreads_or_default(nthreads);
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nth)
   for (long m = 0; m < nm; ++m) f[m] = double(evolve4_mode<R>(nt, R(dt), Ag, Aedge, Aedge + 2, p + 3 * m));
+}
+
+// Split-operator evolution (see evolve_split_mode) of modes p[nm][3]: order 2 (Strang, At[nt][2]
+// at the step midpoints) or 4 (triple jump, At[nt][3][2]); Aedge[2][2] A(t_i) and A(t_f).
+void orc_evolve_split_points_ld(int order, int nt, double dt, const double* At, const double* Aedge, long nm,
+                                const double* p, double* f, int nthreads) {
+  using R = long double;
+  const int nsub = order == 4 ? 3 : 1;
+  const int nth = nthreads_or_default(nthreads);
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nth)
+  for (long m = 0; m < nm; ++m)
+    f[m] = double(evolve_split_mode<R>(nt, R(dt), nsub, At, Aedge, Aedge + 2, p + 3 * m));
 }
 
 // ---------------------------------------------------------------------------------------
