@@ -291,6 +291,45 @@ def test_de_generation_workload_full_size_sampled(orc):
         assert abs(J[pi] - dv * math.fsum(f[pi * M:(pi + 1) * M])) <= 1e-13 * J[pi]
 
 
+@pytest.mark.timeout(600)
+def test_de_generation_workload_full_pulse_vs_oracle(orc):
+    """One whole pulse of the 64-pulse DE generation (all 65,536 modes x nt = 16384), evaluated in
+    the benchmark's launch (all 64 pulses in one call): every mode against the long-double oracle
+    at the per-mode bar and J at relative 1e-8 (Sec. IV A, Eq. opt_prob)."""
+    w = W.de_generation(0)
+    specs, grids, coeff = w["specs"], w["grids"], w["coeff"]
+    J, f = api.evaluate(specs, grids, coeff, want_f=True)
+    J, f = host(J), host(f)
+    M = W.n_modes(grids[0])
+    pi = 0
+    say(f"full-size DE generation: long-double oracle on every mode of pulse {pi}")
+    Jr, fr = orc.evaluate(specs[pi], grids[pi], coeff[pi], precision="ld", want_f=True)
+    assert_modes(f[pi * M:(pi + 1) * M], fr, specs[pi]["nt"], f"DE generation pulse {pi}, all {M} modes")
+    assert_J(J[pi], Jr, f"DE generation pulse {pi}")
+
+
+@pytest.mark.timeout(600)
+def test_surrogate_de_workload_full_pulse_J_vs_oracle(orc):
+    """One whole pulse of the surrogate-DE evaluator (524,288 modes x nt = 32768, 1.7e10
+    mode-steps) against the double oracle (the long-double one would take ~10x longer): J at
+    relative 1e-8, and every mode within twice the per-mode bar -- both sides are FP64
+    evaluations whose distance to the exact discrete solution is within the bar, so their
+    distance to each other is within twice it."""
+    spec, g = W.surrogate_de_spec()
+    coeff = W.draw_coeff(5, 3, 8)
+    J, f = api.evaluate([spec] * 3, [g] * 3, coeff, want_f=True)
+    J, f = host(J), host(f)
+    M = W.n_modes(g)
+    pi = 1
+    say(f"full-size surrogate-DE evaluator: double oracle on every mode of pulse {pi}")
+    Jr, fr = orc.evaluate(spec, g, coeff[pi], precision="d", want_f=True)
+    tol = 2.0 * mode_tol(fr, spec["nt"])
+    err = np.abs(f[pi * M:(pi + 1) * M] - fr)
+    say(f"surrogate-DE pulse {pi}: {M} modes, max err/(2 tol) {np.max(err / tol):.3g}")
+    assert np.all(err <= tol)
+    assert_J(J[pi], Jr, f"surrogate-DE pulse {pi}")
+
+
 def test_surrogate_de_workload_full_size_sampled(orc):
     """Three pulses of the surrogate-DE evaluator (128x128x32 modes, nt = 32768, T = 800) in one
     call; sampled modes vs the oracle, J vs the ordered sum of the stored f."""

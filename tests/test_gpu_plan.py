@@ -19,8 +19,8 @@ from paper_1704_08919_amd import workloads as W  # noqa: E402
 from test_gpu_parity import assert_J, assert_modes, dev, host, say  # noqa: E402
 
 CONFIGS = [dict(threads=256, modes_per_lane=1, persistent=0), dict(threads=256, modes_per_lane=1, persistent=1),
-           dict(threads=128, modes_per_lane=2, persistent=1), dict(threads=64, modes_per_lane=1, persistent=1),
-           dict(threads=64, modes_per_lane=2, persistent=1, workgroups=37)]
+           dict(threads=256, modes_per_lane=2, persistent=1), dict(threads=128, modes_per_lane=2, persistent=1),
+           dict(threads=64, modes_per_lane=1, persistent=1), dict(threads=64, modes_per_lane=2, persistent=1, workgroups=37)]
 
 
 def small_uneven_batch(seed=0):
@@ -121,6 +121,7 @@ def test_autotune_and_cache(tmp_path):
     plan2.close()
 
 
+@pytest.mark.timeout(600)
 def test_uneven_batch_workload_full_size(orc):
     """256 pulses, nt from 4096 to 65536, grids 32^2 / 64^2x8 / 96^2x16, autotuned persistent plan;
     sampled modes against the oracle and J against the exact sum of f."""
@@ -149,4 +150,14 @@ def test_uneven_batch_workload_full_size(orc):
         dv = np.prod([(g["hi"][d] - g["lo"][d]) / g["n"][d] for d in range(3)
                       if not (g["n"][d] == 1 and g["lo"][d] == g["hi"][d])])
         assert abs(J[pi] - dv * math.fsum(f[offs[pi]:offs[pi + 1]])) <= 1e-13 * J[pi]
+    # one whole 96^2 x 16 pulse (the shortest of that grid) and one 32^2 sheet pulse against the
+    # long-double oracle: every mode at the per-mode bar, J at relative 1e-8
+    big = [i for i in range(256) if tuple(grids[i]["n"]) == (96, 96, 16)]
+    sheet = [i for i in range(256) if tuple(grids[i]["n"]) == (32, 32, 1)]
+    for pi in (min(big, key=lambda i: specs[i]["nt"]), max(sheet, key=lambda i: specs[i]["nt"])):
+        s, g = specs[pi], grids[pi]
+        say(f"uneven batch pulse {pi}: long-double oracle on all {W.n_modes(g)} modes (nt {s['nt']})")
+        Jr, fr = orc.evaluate(s, g, coeff[pi], precision="ld", want_f=True)
+        assert_modes(f[offs[pi]:offs[pi + 1]], fr, s["nt"], f"uneven batch pulse {pi}, every mode")
+        assert_J(J[pi], Jr, f"uneven batch pulse {pi}")
     plan.close()

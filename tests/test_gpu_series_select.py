@@ -5,6 +5,8 @@ covers the largest (omega dt)^2 its modes reach over the chunk's steps -- the ch
 more conservative than needed, never less -- so, summed over blocks and chunks, the kernel's
 mode-steps at variants <= k never exceed those for which variant k is admissible.  The counts
 also add up to the mode-steps evolved."""
+import os
+import re
 import sys
 
 import numpy as np
@@ -19,9 +21,11 @@ if not torch.cuda.is_available():  # pragma: no cover - collected on hosts witho
 from paper_1704_08919_amd import api  # noqa: E402
 from paper_1704_08919_amd import workloads as W  # noqa: E402
 
-# Largest x = (omega dt)^2 of the tan(sqrt x)/sqrt x polynomial fits of degree 4, 5, ..., 11 (error
-# below 2^-57 up to there); beyond: angle halving.
-XMAX = (0.002512, 0.009969, 0.02657, 0.05434, 0.09267, 0.1509, 0.2148, 0.2572)
+# Largest x = (omega dt)^2 of each tan(sqrt x)/sqrt x polynomial fit (error below 2^-57 up to there),
+# read from the generated header the kernels are compiled from; beyond the last: angle halving.
+_HDR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1704_08919_amd", "csrc",
+                    "tan_fit.hpp")
+XMAX = tuple(float(v) for v in re.search(r"kFitXmax\[kNumFit\] = \{([^}]*)\}", open(_HDR).read()).group(1).split(","))
 BLOCK, CHUNK = 512, 256
 
 
