@@ -94,6 +94,8 @@ def cpu_baseline(w, sample_modes, sample_pulses):
     import oracle
     from paper_1704_08919_amd import workloads as W
 
+    from oracle import build as oracle_build
+
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
     ms, dt = 0, 0.0
     for i in range(sample_pulses):
@@ -101,16 +103,25 @@ def cpu_baseline(w, sample_modes, sample_pulses):
         p, _ = oracle.grid_points(grid)
         p = p[:sample_modes]
         t0 = time.perf_counter()
-        A, _, edge, _ = oracle.synth(spec, coeff, precision="d", with_E=False)
-        f = oracle.evolve_points(A, edge, spec["T"] / spec["nt"], p, precision="d", nthreads=threads)
+        A, _, edge, _ = oracle.synth(spec, coeff, precision="d_fast", with_E=False)
+        f = oracle.evolve_points(A, edge, spec["T"] / spec["nt"], p, precision="d_fast", nthreads=threads)
         dt += time.perf_counter() - t0
         assert np.all(np.isfinite(f))
         ms += len(p) * spec["nt"]
     n_modes = W.n_modes(w["grids"][0])
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next(line.split(":", 1)[1].strip() for line in fh if line.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {"value": ms / dt, "unit": "mode-steps/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu, "host_cpus": os.cpu_count(),
+            "build_flags": " ".join(oracle_build.FAST_FLAGS),
             "sample": f"pulses 0..{sample_pulses - 1} of {w['name']}: synthesis + first "
                       f"{min(sample_modes, n_modes)} of {n_modes} modes each, all {w['specs'][0]['nt']} steps "
-                      f"({ms:.3e} mode-steps, {dt:.1f} s, double build, OpenMP)"}
+                      f"({ms:.3e} mode-steps, {dt:.1f} s, the oracle's double-precision 4x4 evolution, "
+                      f"OpenMP over modes)"}
 
 
 def guarded(fn, *a):
@@ -119,6 +130,28 @@ def guarded(fn, *a):
         return fn(*a)
     except Exception as e:  # noqa: BLE001
         return {"error": f"{type(e).__name__}: {e}"}
+
+
+def fma_probe(api, torch, waves=(4, 5, 6, 8), chains=(2, 4, 8), iters=4096):
+    """FP64 FMA issue rate with exactly w waves per SIMD and c independent chains per lane (the
+    ceiling the evolution kernel's FP64 rate is read against), as a fraction of the 78.6 TFLOP/s
+    peak; HIP events on the stream the probe runs on (torch's current stream)."""
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    sink = torch.empty(n_cu * max(waves) * 256, dtype=torch.float64, device="cuda")
+    rows = []
+    for w in waves:
+        for c in chains:
+            api.po_probe_fp64_fma(w, c, 64, sink)  # warm-up
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            flop = api.po_probe_fp64_fma(w, c, iters, sink)
+            e1.record()
+            torch.cuda.synchronize()
+            tf = flop / (e0.elapsed_time(e1) * 1e-3) / 1e12
+            rows.append({"waves_per_simd": w, "chains": c, "tflops": tf, "frac_of_peak": tf / FP64_PEAK_TFLOPS})
+    return {"what": "v_fma_f64 chains, exactly w waves per SIMD on every CU", "rows": rows,
+            "best_frac_at_4_waves": max(r["frac_of_peak"] for r in rows if r["waves_per_simd"] == 4),
+            "best_frac": max(r["frac_of_peak"] for r in rows)}
 
 
 def uneven_batch(api, W, torch, uniform_rate, reps=3):
@@ -196,32 +229,77 @@ def surrogate_de(api, W, S, torch, pop=512, generations=200, seed=0):
     return out
 
 
-def surrogate_de_full(api, W, S, torch, phase, generations, seed=0, target_J=None, plain_wall_s=None):
+def surrogate_de_full(api, W, S, torch, phase, generations, seed=0, target_J=None, plain_wall_s=None, run_in=None,
+                      run_out=None, time_budget_s=None, surrogate_limit_s=None):
     """Surrogate-assisted DE at the full configuration (pop 512, 2x(8+8) coefficients, T = 800,
-    nt = 32768, 128x128x32 modes), one phase per process (a plain generation takes ~10 s):
-    phase "plain" runs plain DE for `generations`; phase "surrogate" runs the screened DE from the
-    same seed and initial population until the best J reaches target_J (0.99 of the plain run's
-    best) or plain_wall_s passes.  Prints progress every generation."""
+    nt = 32768, 128x128x32 modes), one phase per process (a plain generation takes ~10 s).
+
+    phase "plain": plain DE up to `generations`, resumable: the state in run_in/plain_seed<seed>.npz
+    (if present) is continued, at most time_budget_s seconds are run in this process, and the new
+    state plus every trial and its J of the generations run here are written to run_out.
+    phase "surrogate": the screened DE from the same seed and initial population until the best J
+    reaches target_J (0.99 of the plain run's best) or surrogate_limit_s (default plain_wall_s)
+    passes.  Before its clock starts it times one plain evaluation of the 512-pulse population on
+    this GPU, so the plain run's wall time can be compared on the same device.  Prints progress
+    every generation."""
+    import numpy as np
     spec, grid = W.surrogate_de_spec()
     pop = 512
     per_gen = pop * W.n_modes(grid) * spec["nt"]
     out = {"workload": f"surrogate_de_full: pop {pop}, T=800, nt=32768, 128x128x32 modes, seed {seed}",
            "phase": phase, "mode_steps_per_plain_generation": per_gen}
     if phase == "plain":
-        r = S.run_de(spec, grid, pop, generations, seed, mode="plain", plan_config=PLAN, progress_every=1)
+        state_name = f"plain_seed{seed}.npz"
+        resume = None
+        if run_in and os.path.exists(os.path.join(run_in, state_name)):
+            with np.load(os.path.join(run_in, state_name)) as z:
+                resume = {k: z[k] for k in z.files}
+        record = []
+        r = S.run_de(spec, grid, pop, generations, seed, mode="plain", plan_config=PLAN, progress_every=1,
+                     resume=resume, time_budget=time_budget_s, record=record)
+        done = r["generations"]
         out.update({k: r[k] for k in ("generations", "wall_s", "plain_evaluations", "best_J")})
-        out["s_per_generation"] = r["wall_s"] / (r["generations"] + 1)  # + the initial population
-        out["mode_steps_per_s"] = per_gen * (r["generations"] + 1) / r["wall_s"]
-        out["target_J_next_phase"] = 0.99 * r["best_J"]
-        out["plain_time_to_target_s"] = S.time_to_reach(r["history"], 0.99 * r["best_J"])
+        out["generations_this_process"] = len(record)
+        out["s_per_generation"] = r["wall_s"] / (done + 1)  # + the initial population
+        out["mode_steps_per_s"] = per_gen * (done + 1) / r["wall_s"]
+        out["complete"] = done >= generations
+        if out["complete"]:
+            out["target_J_next_phase"] = 0.99 * r["best_J"]
+            out["plain_time_to_target_s"] = S.time_to_reach(r["history"], 0.99 * r["best_J"])
+        if run_out:
+            os.makedirs(run_out, exist_ok=True)
+            np.savez(os.path.join(run_out, state_name), pop=r["final_pop"], fit=r["final_fit"],
+                     generation=np.int64(done), evals=np.int64(r["plain_evaluations"]),
+                     history=np.asarray(r["history"], dtype=np.float64), wall_s=np.float64(r["wall_s"]))
+            if record:
+                g0, g1 = record[0][0], record[-1][0]
+                np.savez(os.path.join(run_out, f"plain_seed{seed}_trials_g{g0:03d}_{g1:03d}.npz"),
+                         generation=np.asarray([g for g, _, _ in record], dtype=np.int64),
+                         trials=np.stack([x for _, x, _ in record]).astype(np.float32),
+                         J=np.stack([j for _, _, j in record]))
+        hist = r["history"]
     else:
-        r = S.run_de(spec, grid, pop, 10 * generations, seed, mode="surrogate", time_limit=plain_wall_s,
+        ev = S.Evaluator(spec, grid, pop, PLAN)
+        x = torch.as_tensor(W.draw_coeff(seed, pop, spec["n_s"]).reshape(pop, -1), dtype=torch.float64, device="cuda")
+        ev(x)
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        ev(x)
+        torch.cuda.synchronize()
+        out["plain_evaluation_512_s_this_gpu"] = time.perf_counter() - tc
+        ev.close()
+        limit = surrogate_limit_s if surrogate_limit_s else plain_wall_s
+        r = S.run_de(spec, grid, pop, 10 * generations, seed, mode="surrogate", time_limit=limit,
                      target=target_J, plan_config=PLAN, progress_every=1)
         tt = S.time_to_reach(r["history"], target_J)
         out.update({k: r[k] for k in ("generations", "wall_s", "plain_evaluations", "best_J", "train_s")})
         out.update({"target_J": target_J, "plain_wall_s": plain_wall_s, "time_to_target_s": tt,
                     "speedup_vs_plain_wall": plain_wall_s / tt if tt else None})
-    out["history_every_10"] = [list(h) for h in r["history"][::10]] + [list(r["history"][-1])]
+        for key in ("rank_corr", "train_log"):
+            if key in r:
+                out[key] = r[key]
+        hist = r["history"]
+    out["history_every_10"] = [list(h) for h in hist[::10]] + [list(hist[-1])]
     return out
 
 
@@ -303,8 +381,11 @@ def solver_comparison(api, W, torch, n_p=512, nts=(5000, 10000, 20000, 50000, 10
                       nt_exact=2_000_000, target=1e-3):
     """The paper's accuracy-versus-time comparison (Sec. V C) on the circular multimode pulse of its
     2-D study: error eps = int |f - f_exact| / int f_exact over the momentum sheet against the GPU
-    time per momentum point, for the second-order Dirac step, the fourth-order Magnus step and
-    the kinetic equation with RK4; f_exact = fourth-order step at nt_exact.  Only the solver
+    time per momentum point, for the second-order Dirac step (exponential midpoint), the
+    fourth-order Magnus step, the split-operator steps (Strang, second order, and its fourth-order
+    triple-jump composition) and the kinetic equation with RK4; f_exact = fourth-order Magnus step
+    at nt_exact.  A row whose eps exceeds 1 (RK4 unstable for the fastest modes) is marked
+    unstable.  Only the solver
     call is timed (tables are built beforehand)."""
     w = W.circular_pulse(0, nt=nts[0], n_p=n_p)
     spec0, coeff, grid = w["specs"][0], w["coeff"], w["grids"][0]
@@ -319,6 +400,12 @@ def solver_comparison(api, W, torch, n_p=512, nts=(5000, 10000, 20000, 50000, 10
         if method == "magnus4":
             _, _, Ag, edge, _ = api.field_samples(s, coeff, api.GAUSS2)
             return lambda: api.po_evolve_modes_m4(s, [grid], Ag, edge, f=f)
+        if method == "split2":
+            A, edge, _, _ = api.synth(s, coeff)
+            return lambda: api.po_evolve_modes_split(s, [grid], 2, A, edge, f=f)
+        if method == "split4":
+            _, _, At, edge, _ = api.field_samples(s, coeff, api.SPLIT4_OFFSETS)
+            return lambda: api.po_evolve_modes_split(s, [grid], 4, At, edge, f=f)
         E, Ed, A, _, _ = api.field_samples(s, coeff, api.QKE_OFFSETS, with_end=True)
         return lambda: api.po_qke_modes(s, [grid], E, Ed, A, f=f)
 
@@ -332,7 +419,8 @@ def solver_comparison(api, W, torch, n_p=512, nts=(5000, 10000, 20000, 50000, 10
         torch.cuda.synchronize()
         return t0.elapsed_time(t1)
 
-    for method in ("dirac2", "magnus4", "qke"):  # load code objects before timing
+    methods = ("dirac2", "magnus4", "split2", "split4", "qke")
+    for method in methods:  # load code objects before timing
         timed(method, 1000)
     ms_exact = timed("magnus4", nt_exact)
     fe = f.clone()
@@ -345,14 +433,18 @@ def solver_comparison(api, W, torch, n_p=512, nts=(5000, 10000, 20000, 50000, 10
     timed("dirac2", nt_exact)
     check = eps()
     rows, reach = [], {}
-    for method in ("dirac2", "magnus4", "qke"):
+    for method in methods:
         prev = None
         for nt in nts:
             ms = timed(method, nt)
             e = eps()
             us = ms * 1e3 / M
-            rows.append({"method": method, "nt": nt, "eps": e, "us_per_mode": us,
-                         "mode_steps_per_s": M * nt / (ms * 1e-3)})
+            row = {"method": method, "nt": nt, "eps": e, "us_per_mode": us, "mode_steps_per_s": M * nt / (ms * 1e-3)}
+            if e is None or e > 1.0:
+                # RK4 outside its stability interval for the fastest modes: f grows without bound
+                row["eps"], row["unstable"] = None, True
+                e = None
+            rows.append(row)
             if method not in reach and e is not None and e <= target:
                 if prev is not None and prev[1] is not None and prev[1] > target:  # log-log interpolation
                     a = math.log(target / prev[1]) / math.log(e / prev[1])
@@ -363,10 +455,11 @@ def solver_comparison(api, W, torch, n_p=512, nts=(5000, 10000, 20000, 50000, 10
     out = {"workload": w["name"], "modes": M, "nt_exact": nt_exact, "exact_ms": ms_exact,
            "exact_check_eps_dirac2": check, "target_eps": target, "rows": rows,
            "us_per_mode_to_target": reach}
-    if "qke" in reach and "dirac2" in reach:
-        out["qke_over_dirac2_at_target"] = reach["qke"] / reach["dirac2"]
-    if "magnus4" in reach and "dirac2" in reach:
-        out["dirac2_over_magnus4_at_target"] = reach["dirac2"] / reach["magnus4"]
+    for m in ("magnus4", "split2", "split4", "qke"):
+        if m in reach and "dirac2" in reach:
+            out[f"{m}_over_dirac2_at_target"] = reach[m] / reach["dirac2"]
+    if reach:
+        out["cheapest_at_target"] = min(reach, key=reach.get)
     return out
 
 
@@ -380,6 +473,7 @@ def main():
     ap.add_argument("--cpu-sample-modes", type=int, default=65536)
     ap.add_argument("--cpu-sample-pulses", type=int, default=3)
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch plan measurement")
+    ap.add_argument("--no-fma-probe", action="store_true", help="skip the FP64 FMA issue-rate probe")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate training and DE comparison")
     ap.add_argument("--no-de-variants", action="store_true", help="skip the plain DE versus jDE-on-islands run")
     ap.add_argument("--no-local-search", action="store_true", help="skip the multistart BFGS local search")
@@ -392,6 +486,11 @@ def main():
     ap.add_argument("--full-generations", type=int, default=80, help="plain-DE generations of that comparison")
     ap.add_argument("--target-J", type=float, help="surrogate phase: 0.99 x the plain phase's best J")
     ap.add_argument("--plain-wall-s", type=float, help="surrogate phase: the plain phase's wall time")
+    ap.add_argument("--run-in", help="plain phase: directory holding the state to resume (plain_seed<seed>.npz)")
+    ap.add_argument("--run-out", help="plain phase: directory for the new state and the recorded trials")
+    ap.add_argument("--time-budget-s", type=float, help="plain phase: seconds of DE work in this process")
+    ap.add_argument("--surrogate-limit-s", type=float,
+                    help="surrogate phase: stop after this many seconds (default: the plain wall time)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the library has no multi-GPU path",
@@ -409,7 +508,8 @@ def main():
         if args.surrogate_de_full == "surrogate" and (args.target_J is None or args.plain_wall_s is None):
             ap.error("--surrogate-de-full surrogate needs --target-J and --plain-wall-s from the plain phase")
         print(json.dumps(surrogate_de_full(api, W, S, torch, args.surrogate_de_full, args.full_generations,
-                                           args.seed, args.target_J, args.plain_wall_s)), flush=True)
+                                           args.seed, args.target_J, args.plain_wall_s, args.run_in, args.run_out,
+                                           args.time_budget_s, args.surrogate_limit_s)), flush=True)
         return
     if args.calibrate_copy:
         src = torch.ones(64 * 2 ** 20, dtype=torch.float64, device="cuda")
@@ -483,6 +583,8 @@ def main():
                                          / (FP64_PEAK_TFLOPS * 1e12 / 2)) if measured else None,
                      "achieved_at_fixed_97_flop": FIXED_FLOP_PER_MODE_STEP * mode_steps / ev_s / 1e12},
     }
+    if not args.no_fma_probe:
+        out["fp64_fma_probe"] = guarded(fma_probe, api, torch)
     if not args.no_uneven:
         out["uneven_batch"] = guarded(uneven_batch, api, W, torch, mode_steps / ev_s)
     if not args.no_solvers:

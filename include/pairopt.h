@@ -198,6 +198,28 @@ po_status po_evolve_modes_m4(int32_t n_pulses, const po_pulse_spec* specs, const
                              void* stream);
 
 /* ---------------------------------------------------------------------------------------
+ * po_evolve_modes_split -- po_evolve_modes with a split-operator step: the frozen Hamiltonian
+ * splits into the part the field does not touch, alpha_z p_z + beta m, and the field-driven
+ * transverse part alpha_x P_x + alpha_y P_y, each factor exponentiated exactly (Sec. II A names a
+ * second-order split-operator scheme; at p_z = 0 this is the mass / kinetic split).
+ *  order     2: Strang's symmetric step, field at the step midpoint;
+ *            4: the triple-jump composition of three Strang steps of sizes w1 dt, w0 dt, w1 dt,
+ *            w1 = 1/(2 - 2^(1/3)), w0 = 1 - 2 w1 (Yoshida, Phys. Lett. A 150 (1990) 262): the
+ *            fourth-order splitting Sec. V C leaves for future work.
+ *  d_At      order 2: [sum nt][2] double, A at the step midpoints (the table of po_evolve_modes);
+ *            order 4: [sum nt][3][2] double, A at t_i + (n + c_k) dt with c = (w1/2, 1/2,
+ *            1 - w1/2), the midpoints of the three substeps (po_field_samples, n_sub = 3).
+ *  d_A_edge  [n_pulses][2][2] double: A(t_i), A(t_f).
+ *  d_f, d_J  as for po_evolve_modes (at least one non-NULL; same projection and fixed-order J).
+ * Unlike the midpoint exponential, a term split is not exact for a constant field: without any
+ * field it leaves a spurious density of order dt^4 (order 2) or dt^8 (order 4).
+ * Errors: PO_ERR_INVALID for an order other than 2 or 4 and as po_evolve_modes.
+ * --------------------------------------------------------------------------------------- */
+po_status po_evolve_modes_split(int32_t n_pulses, const po_pulse_spec* specs, const po_grid* grids,
+                                int32_t order, const double* d_At, const double* d_A_edge, double* d_f,
+                                double* d_J, void* stream);
+
+/* ---------------------------------------------------------------------------------------
  * Gradients for the local search of Sec. IV A (the gradient of the objective with respect to
  * the field parameters, which the BFGS iteration needs).  The paper obtains it from the adjoint
  * of the kinetic equation; here it is the exact derivative of the discrete Dirac evaluation of
@@ -383,8 +405,9 @@ void po_plan_destroy(struct po_plan* plan);
  * (beta1 0.9, beta2 0.999, eps 1e-8); loss = mean squared error.  GELU is the erf form.
  * Parameter vector (float): per hidden layer W [k_in][width] (row-major) then b [width]; then
  * the output weights [width] and bias [1].  Requires n_in and width multiples of 32; every
- * batch a multiple of 32 up to max_batch.  Inputs are the coefficients as doubles (rounded to
- * bf16 inside).  A network's calls must not overlap; it is bound to the device current at
+ * batch a multiple of 32 up to max_batch.  Inputs are the coefficients as doubles, 16-byte
+ * aligned (rounded to bf16 through float inside: the boundary takes the coefficient vectors the
+ * optimiser holds, so no separate conversion pass or bf16 copy is needed).  A network's calls must not overlap; it is bound to the device current at
  * creation.  Initial weights: uniform(-1/sqrt(k_in), 1/sqrt(k_in)) from Philox4x32-10(seed).
  * --------------------------------------------------------------------------------------- */
 struct po_mlp;
@@ -402,9 +425,21 @@ po_status po_mlp_loss_grad(struct po_mlp* net, const double* d_x, const float* d
                            float* d_loss, float* d_grad, void* stream);
 /* One Adam step with d_grad (NULL = the network's last gradient). */
 po_status po_mlp_adam_step(struct po_mlp* net, const float* d_grad, float lr, void* stream);
-/* po_mlp_loss_grad followed by po_mlp_adam_step. */
+/* po_mlp_loss_grad followed by po_mlp_adam_step (bitwise the same result).  The step's launches
+ * are captured into a HIP graph on the first call with a given set of pointers, batch and lr, and
+ * the graph is replayed by later calls with the same arguments. */
 po_status po_mlp_train_step(struct po_mlp* net, const double* d_x, const float* d_target, int32_t batch,
                             float lr, float* d_loss, void* stream);
+/* `steps` training steps on minibatches drawn from a data set held on the device:
+ *  d_X [n_rows][n_in] double (16-byte aligned) and d_J [n_rows] double (yields); step s uses the
+ *  rows d_idx[s batch .. s batch + batch - 1] (int32; entries outside [0, n_rows) read row 0) with
+ *  targets (log10(max(J, 1e-300)) - mean) * inv_std, the standardisation of po_log10_standardize;
+ *  d_losses [steps] float or NULL receives each step's loss.  Each step is the graph of
+ *  po_mlp_train_step (captured once per set of arguments), replayed without host work between
+ *  steps. */
+po_status po_mlp_train_indexed(struct po_mlp* net, const double* d_X, const double* d_J, int32_t n_rows,
+                               const int32_t* d_idx, int32_t steps, int32_t batch, double mean,
+                               double inv_std, float lr, float* d_losses, void* stream);
 void po_mlp_destroy(struct po_mlp* net);
 /* d_mask[i] = 1 for the k largest scores (ties: lower index first; NaN ranks last), else 0.
  * 1 <= n <= 8192. */
@@ -422,6 +457,13 @@ po_status po_log10_standardize(const double* d_J, int32_t n, double floor_value,
  * --------------------------------------------------------------------------------------- */
 po_status po_timer_enable(int on);
 po_status po_timer_read(double* ms_total, int64_t* calls);
+/* FP64 issue-rate probe (diagnostics): one launch in which exactly waves_per_simd (3..8) waves run
+ * on every SIMD, each lane running iters x 8 rounds of `chains` (1, 2, 4, 8) independent
+ * dependency chains of v_fma_f64.  d_sink [CUs x waves_per_simd x 256] double receives one value
+ * per lane; *flop (host, may be NULL) the FP64 operations launched (2 per FMA).  The caller times
+ * the launch on `stream`. */
+po_status po_probe_fp64_fma(int32_t waves_per_simd, int32_t chains, int64_t iters, double* d_sink, double* flop,
+                            void* stream);
 /* Mode-steps evolved since the last read while timers were enabled, per series variant of the
  * second-order evolution kernel (chosen per block of 512 modes and chunk of 256 steps):
  * counts[0..7] = tan(theta)/theta polynomial of degree 4, 5, ..., 11; counts[8] = cos/sin series of

@@ -17,6 +17,7 @@ import numpy as np
 from . import build as _build
 
 _lib = None
+_lib_fast = None
 
 _D = ctypes.POINTER(ctypes.c_double)
 _I = ctypes.POINTER(ctypes.c_int)
@@ -83,6 +84,21 @@ def lib():
     return _lib
 
 
+def lib_fast():
+    """The -O3 build with contraction allowed (timing only): double synthesis and evolution."""
+    global _lib_fast
+    if _lib_fast is None:
+        lib()
+        if not os.path.exists(_build.LIB_FAST):
+            _build.build(force=False)
+        L = ctypes.CDLL(_build.LIB_FAST)
+        for name in ("orc_synth_d", "orc_evolve_points_d"):
+            getattr(L, name).restype = getattr(_lib, name).restype
+            getattr(L, name).argtypes = getattr(_lib, name).argtypes
+        _lib_fast = L
+    return _lib_fast
+
+
 def _d(a):
     return a.ctypes.data_as(_D)
 
@@ -119,11 +135,13 @@ def field_at(spec, coeff, t):
 
 
 def synth(spec, coeff, precision="ld", with_E=True):
-    """Scaled tables of one pulse: A_mid[nt][2], E_mid[nt][2], A_edge[2][2], scale."""
+    """Scaled tables of one pulse: A_mid[nt][2], E_mid[nt][2], A_edge[2][2], scale.  precision
+    "ld", "d", or "d_fast" (the double routine of the -O3 timing build)."""
     coeff = _arr(coeff)
     nt = spec["nt"]
     A, E, edge, sc = np.zeros((nt, 2)), np.zeros((nt, 2)), np.zeros((2, 2)), np.zeros(1)
-    fn = lib().orc_synth_ld if precision == "ld" else lib().orc_synth_d
+    fn = {"ld": lambda: lib().orc_synth_ld, "d": lambda: lib().orc_synth_d,
+          "d_fast": lambda: lib_fast().orc_synth_d}[precision]()
     fn(spec["n_s"], spec["order"], spec["omega_min"], spec["omega_max"], spec["T"], nt, spec["norm"],
        spec["norm_value"], _d(coeff), _d(A), _d(E) if with_E else None, _d(edge), _d(sc))
     return A, (E if with_E else None), edge, float(sc[0])
@@ -131,10 +149,12 @@ def synth(spec, coeff, precision="ld", with_E=True):
 
 # --------------------------------------------------------------------------------- dynamics
 def evolve_points(A_mid, A_edge, dt, p, precision="ld", nthreads=0):
-    """Pair density f at momenta p[m][3] for any A table (Sec. II A)."""
+    """Pair density f at momenta p[m][3] for any A table (Sec. II A); precision "ld", "d" or
+    "d_fast" (the -O3 timing build)."""
     A_mid, A_edge, p = _arr(A_mid), _arr(A_edge), _arr(p).reshape(-1, 3)
     f = np.zeros(p.shape[0])
-    fn = lib().orc_evolve_points_ld if precision == "ld" else lib().orc_evolve_points_d
+    fn = {"ld": lambda: lib().orc_evolve_points_ld, "d": lambda: lib().orc_evolve_points_d,
+          "d_fast": lambda: lib_fast().orc_evolve_points_d}[precision]()
     fn(A_mid.shape[0], float(dt), _d(A_mid), _d(A_edge), p.shape[0], _d(p), _d(f), int(nthreads))
     return f
 

@@ -71,6 +71,8 @@ SIGNATURES = {
                              ctypes.c_int),
     "po_evolve_modes_m4": ([_I32, ctypes.POINTER(PulseSpec), ctypes.POINTER(Grid), _P, _P, _P, _P, _P],
                            ctypes.c_int),
+    "po_evolve_modes_split": ([_I32, ctypes.POINTER(PulseSpec), ctypes.POINTER(Grid), _I32, _P, _P, _P, _P, _P],
+                              ctypes.c_int),
     "po_evaluate": ([_I32, ctypes.POINTER(PulseSpec), ctypes.POINTER(Grid), _P, _P, _P, _P, _P, _P, _P, _P],
                     ctypes.c_int),
     "po_de_propose": ([ctypes.POINTER(DEParams), _I64, _P, _P, _P, _P], ctypes.c_int),
@@ -95,12 +97,15 @@ SIGNATURES = {
     "po_mlp_loss_grad": ([_P, _P, _P, _I32, _P, _P, _P], ctypes.c_int),
     "po_mlp_adam_step": ([_P, _P, ctypes.c_float, _P], ctypes.c_int),
     "po_mlp_train_step": ([_P, _P, _P, _I32, ctypes.c_float, _P, _P], ctypes.c_int),
+    "po_mlp_train_indexed": ([_P, _P, _P, _I32, _P, _I32, _I32, ctypes.c_double, ctypes.c_double, ctypes.c_float, _P,
+                              _P], ctypes.c_int),
     "po_mlp_destroy": ([_P], None),
     "po_topk_mask": ([_P, _I32, _I32, _P, _P], ctypes.c_int),
     "po_log10_standardize": ([_P, _I32, ctypes.c_double, ctypes.c_double, ctypes.c_double, _P, _P], ctypes.c_int),
     "po_mask_indices": ([_P, _I32, _P, _P, _P], ctypes.c_int),
     "po_gather_rows": ([_P, _I32, _I32, _P, _I32, _P, _P], ctypes.c_int),
     "po_scatter_values": ([_P, _P, _I32, ctypes.c_double, _P, _I32, _P], ctypes.c_int),
+    "po_probe_fp64_fma": ([_I32, _I32, _I64, _P, ctypes.POINTER(ctypes.c_double), _P], ctypes.c_int),
     "po_timer_enable": ([ctypes.c_int], ctypes.c_int),
     "po_timer_read": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "po_timer_mode_steps": ([ctypes.POINTER(ctypes.c_uint64), _I32], ctypes.c_int),

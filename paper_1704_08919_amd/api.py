@@ -93,6 +93,16 @@ def po_evolve_modes_m4(specs, grids, Ag, A_edge, f=None, J=None, stream=None):
     check(load().po_evolve_modes_m4(len(specs), sp, gr, _ptr(Ag), _ptr(A_edge), _ptr(f), _ptr(J), _stream(stream)))
 
 
+_W1 = 1.0 / (2.0 - 2.0 ** (1.0 / 3.0))
+SPLIT4_OFFSETS = (_W1 / 2, 0.5, 1.0 - _W1 / 2)  # substep midpoints of po_evolve_modes_split, order 4
+
+
+def po_evolve_modes_split(specs, grids, order, At, A_edge, f=None, J=None, stream=None):
+    sp, gr = _spec_array(specs), _grid_array(grids)
+    check(load().po_evolve_modes_split(len(specs), sp, gr, int(order), _ptr(At), _ptr(A_edge), _ptr(f), _ptr(J),
+                                       _stream(stream)))
+
+
 def po_yield_gradient(specs, grids, A, A_edge, gA, J=None, gedge=None, stream=None):
     sp, gr = _spec_array(specs), _grid_array(grids)
     check(load().po_yield_gradient(len(specs), sp, gr, _ptr(A), _ptr(A_edge), _ptr(J), _ptr(gA), _ptr(gedge),
@@ -209,6 +219,14 @@ def po_timer_enable(on=True):
     check(load().po_timer_enable(1 if on else 0))
 
 
+def po_probe_fp64_fma(waves_per_simd, chains, iters, sink, stream=None):
+    """Launches the FP64 FMA issue probe; returns the FP64 operations launched."""
+    flop = ctypes.c_double()
+    check(load().po_probe_fp64_fma(int(waves_per_simd), int(chains), int(iters), _ptr(sink), ctypes.byref(flop),
+                                   _stream(stream)))
+    return flop.value
+
+
 def po_timer_read():
     """(summed ms of the bracketed evolution launches, number of bracketed calls); clears them."""
     ms, n = ctypes.c_double(0.0), ctypes.c_int64(0)
@@ -255,6 +273,13 @@ class MLP:
     def train_step(self, x, target, lr=1e-3, loss=None, stream=None):
         check(load().po_mlp_train_step(self.handle, _ptr(x), _ptr(target, torch.float32), int(x.shape[0]), float(lr),
                                        _ptr(loss, torch.float32), _stream(stream)))
+
+    def train_indexed(self, X, J, idx, steps, batch, mean, inv_std, lr=1e-3, losses=None, stream=None):
+        """`steps` steps on minibatches X[idx[s batch:(s + 1) batch]] of a device data set, targets
+        the standardised log10 J (po_mlp_train_indexed)."""
+        check(load().po_mlp_train_indexed(self.handle, _ptr(X), _ptr(J), int(X.shape[0]), _ptr(idx, torch.int32),
+                                          int(steps), int(batch), float(mean), float(inv_std), float(lr),
+                                          _ptr(losses, torch.float32), _stream(stream)))
 
     def close(self):
         if getattr(self, "handle", None):
@@ -380,6 +405,14 @@ def evolve_m4(specs, grids, Ag, A_edge, want_f=True, want_J=True, device="cuda")
     f = torch.empty(n_modes(grids), dtype=torch.float64, device=device) if want_f else None
     J = torch.empty(len(specs), dtype=torch.float64, device=device) if want_J else None
     po_evolve_modes_m4(specs, grids, Ag, A_edge, f=f, J=J)
+    return f, J
+
+
+def evolve_split(specs, grids, order, At, A_edge, want_f=True, want_J=True, device="cuda"):
+    """Allocates outputs and runs po_evolve_modes_split: returns (f or None, J or None)."""
+    f = torch.empty(n_modes(grids), dtype=torch.float64, device=device) if want_f else None
+    J = torch.empty(len(specs), dtype=torch.float64, device=device) if want_J else None
+    po_evolve_modes_split(specs, grids, order, At, A_edge, f=f, J=J)
     return f, J
 
 

@@ -198,14 +198,32 @@ po_status upload(const std::vector<PulseDev>& h, Scratch& sc, hipStream_t s) {
   return PO_OK;
 }
 
+// Scratch of one evaluation (synthesis + evolution + yield), in elements.
+struct EvalSizes {
+  size_t spec, part, scl, units, ranges;
+};
+
+EvalSizes eval_sizes(int32_t n, const Batch& b) {
+  return EvalSizes{size_t(b.total_spec), size_t(std::max(1, b.max_stat_blocks)) * n, size_t(n),
+                   size_t(b.total_units), 4 * size_t(b.total_chunks)};
+}
+
+po_status synth_into(const po_pulse_spec* specs, const double* d_coeff, double* d_A, double* d_E, double* d_A_edge,
+                     double* d_scale, hipStream_t s, const Batch& b, const PulseDev* d_desc, double* d_spec,
+                     double* d_part, double* d_scl) {
+  (void)specs;
+  return launch_synth(b, d_desc, d_coeff, d_spec, d_part, d_scl, d_A, d_E, d_A_edge, d_scale, s);
+}
+
 po_status synth_impl(int32_t n, const po_pulse_spec* specs, const double* d_coeff, double* d_A, double* d_E,
                      double* d_A_edge, double* d_scale, hipStream_t s, const Batch& b, const PulseDev* d_desc) {
+  const EvalSizes z = eval_sizes(n, b);
   Scratch spec, part, scl;
-  PO_TRY(spec.alloc(sizeof(double) * b.total_spec, s));
-  PO_TRY(part.alloc(sizeof(double) * size_t(std::max(1, b.max_stat_blocks)) * n, s));
-  PO_TRY(scl.alloc(sizeof(double) * n, s));
-  return launch_synth(b, d_desc, d_coeff, static_cast<double*>(spec.ptr), static_cast<double*>(part.ptr),
-                      static_cast<double*>(scl.ptr), d_A, d_E, d_A_edge, d_scale, s);
+  PO_TRY(spec.alloc(sizeof(double) * z.spec, s));
+  PO_TRY(part.alloc(sizeof(double) * z.part, s));
+  PO_TRY(scl.alloc(sizeof(double) * z.scl, s));
+  return synth_into(specs, d_coeff, d_A, d_E, d_A_edge, d_scale, s, b, d_desc, static_cast<double*>(spec.ptr),
+                    static_cast<double*>(part.ptr), static_cast<double*>(scl.ptr));
 }
 
 // Event pairs bracketing evolution launches while timers are enabled.
@@ -213,6 +231,22 @@ std::mutex g_timer_mu;
 bool g_timer_on = false;
 std::vector<std::pair<hipEvent_t, hipEvent_t>> g_timer_events;
 unsigned long long* g_counts = nullptr;  // device: mode-steps per series variant (diagnostics)
+
+// Evolution and yield into caller-provided scratch: d_units [total_units] (used when d_J is
+// non-NULL), d_ranges [4 total_chunks].  timed: bracket the evolution with the kernel timers.
+po_status evolve_into(const Batch& b, const PulseDev* d_desc, const double* d_A, const double* d_A_edge, double* d_f,
+                      double* d_J, hipStream_t s, double* d_units, double* d_ranges, bool timed_ok) {
+  hipEvent_t e0 = nullptr;
+  const bool timed = timed_ok && timer_start(s, &e0);
+  PO_TRY(launch_chunk_ranges(b, d_desc, d_A, d_ranges, s));
+  PO_TRY(launch_evolve_grid(b, d_desc, d_A, d_A_edge, d_ranges, d_f, d_J ? d_units : nullptr, s));
+  if (timed) {
+    timer_stop(s, e0);
+    PO_TRY(timer_count(b.n_pulses, d_desc, d_ranges, s));
+  }
+  if (d_J) PO_TRY(launch_yield_from_units(b, d_desc, d_units, d_J, s));
+  return PO_OK;
+}
 
 po_status evolve_impl(const Batch& b, const PulseDev* d_desc, const double* d_A, const double* d_A_edge, double* d_f,
                       double* d_J, hipStream_t s) {
@@ -223,17 +257,7 @@ po_status evolve_impl(const Batch& b, const PulseDev* d_desc, const double* d_A,
     d_units = static_cast<double*>(units.ptr);
   }
   PO_TRY(sel.alloc(sizeof(double) * 4 * size_t(b.total_chunks), s));
-  double* d_ranges = static_cast<double*>(sel.ptr);
-  hipEvent_t e0 = nullptr;
-  const bool timed = timer_start(s, &e0);
-  PO_TRY(launch_chunk_ranges(b, d_desc, d_A, d_ranges, s));
-  PO_TRY(launch_evolve_grid(b, d_desc, d_A, d_A_edge, d_ranges, d_f, d_units, s));
-  if (timed) {
-    timer_stop(s, e0);
-    PO_TRY(timer_count(b.n_pulses, d_desc, d_ranges, s));
-  }
-  if (d_J) PO_TRY(launch_yield_from_units(b, d_desc, d_units, d_J, s));
-  return PO_OK;
+  return evolve_into(b, d_desc, d_A, d_A_edge, d_f, d_J, s, d_units, static_cast<double*>(sel.ptr), true);
 }
 
 // Gradient of J with respect to the tables (forward + adjoint sweep per mode, fixed-order sums).
@@ -454,6 +478,36 @@ po_status po_evolve_modes_m4(int32_t n, const po_pulse_spec* specs, const po_gri
   double* d_ranges = static_cast<double*>(sel.ptr);
   PO_TRY(launch_chunk_ranges4(b, d_desc, d_Ag, d_ranges, s));
   PO_TRY(launch_evolve4_grid(b, d_desc, d_Ag, d_A_edge, d_ranges, d_f, d_units, s));
+  if (d_J) PO_TRY(launch_yield_from_units(b, d_desc, d_units, d_J, s));
+  return PO_OK;
+}
+
+po_status po_evolve_modes_split(int32_t n, const po_pulse_spec* specs, const po_grid* grids, int32_t order,
+                                const double* d_At, const double* d_A_edge, double* d_f, double* d_J, void* stream) {
+  if (n < 1) return set_error(PO_ERR_INVALID, "n_pulses must be >= 1");
+  if (order != 2 && order != 4) return set_error(PO_ERR_INVALID, "order must be 2 or 4");
+  PO_TRY(check_specs(n, specs));
+  PO_TRY(check_grids(n, grids));
+  if (!d_f && !d_J) return set_error(PO_ERR_INVALID, "at least one of d_f, d_J must be non-NULL");
+  std::vector<PulseDev> h(n);
+  Batch b;
+  PO_TRY(build_batch(n, specs, grids, h.data(), &b));
+  const int nsub = order == 2 ? 1 : 3;
+  PO_TRY(check_device_range(d_At, sizeof(double) * 2 * nsub * b.total_rows, 16, "d_At"));
+  PO_TRY(check_device_range(d_A_edge, sizeof(double) * 4 * n, 16, "d_A_edge"));
+  if (d_f) PO_TRY(check_device_range(d_f, sizeof(double) * b.total_modes, 8, "d_f"));
+  if (d_J) PO_TRY(check_device_range(d_J, sizeof(double) * n, 8, "d_J"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Scratch desc, units, sel;
+  PO_TRY(upload(h, desc, s));
+  double* d_units = nullptr;
+  if (d_J) {
+    PO_TRY(units.alloc(sizeof(double) * size_t(b.total_units), s));
+    d_units = static_cast<double*>(units.ptr);
+  }
+  PO_TRY(sel.alloc(sizeof(double) * 4 * size_t(b.total_chunks), s));
+  const PulseDev* d_desc = static_cast<PulseDev*>(desc.ptr);
+  PO_TRY(launch_evolve_split_grid(b, order, d_desc, d_At, d_A_edge, static_cast<double*>(sel.ptr), d_f, d_units, s));
   if (d_J) PO_TRY(launch_yield_from_units(b, d_desc, d_units, d_J, s));
   return PO_OK;
 }

@@ -139,6 +139,11 @@ po_status launch_chunk_ranges4(const Batch& b, const PulseDev* d_desc, const dou
                                hipStream_t s);
 po_status launch_evolve4_grid(const Batch& b, const PulseDev* d_desc, const double* d_Ag, const double* d_A_edge,
                               const double* d_ranges, double* d_f, double* d_units, hipStream_t s);
+// Split-operator evolution (order 2: Strang, order 4: triple jump): table ranges into d_ranges
+// [total_chunks][4], then one workgroup per 256 modes; d_At is [sum nt][1 or 3][2], desc.tab_off in steps.
+po_status launch_evolve_split_grid(const Batch& b, int order, const PulseDev* d_desc, const double* d_At,
+                                   const double* d_A_edge, double* d_ranges, double* d_f, double* d_units,
+                                   hipStream_t s);
 // Kinetic equation (qke.hip): tables at the 2 nt + 1 half-step points, desc.tab_off in points.
 po_status launch_qke_grid(const Batch& b, const PulseDev* d_desc, const double* d_E, const double* d_Ed,
                           const double* d_A, int linear, double* d_f, double* d_units, hipStream_t s);
@@ -152,7 +157,7 @@ po_status plan_evolve(const po_plan* plan, int32_t n, const po_pulse_spec* specs
 // Kernel timers (api.hip): start returns true (and records *e0) when timers are enabled;
 // timer_count enqueues the per-variant mode-step count of an evolution launch from its chunk
 // ranges (no-op when disabled).
-constexpr int kSeriesVariants = 9;  // T series of degree 6..13, then the angle-halving path
+constexpr int kSeriesVariants = 9;  // T fits of degree 4..11 (tan_fit.hpp), then the angle-halving path
 bool timer_start(hipStream_t s, hipEvent_t* e0);
 void timer_stop(hipStream_t s, hipEvent_t e0);
 po_status timer_count(int n_pulses, const PulseDev* d_desc, const double* d_ranges, hipStream_t s);

@@ -33,6 +33,8 @@
 // the launch shape or on scheduling.  Two launch forms share the item code: one workgroup per
 // 256-mode item, or persistent workgroups that pull items (longest pulses first) from a device
 // queue through an atomic counter.
+#include <algorithm>
+
 #include "dirac.hpp"
 #include "reduce.hpp"
 
@@ -116,7 +118,7 @@ __device__ __forceinline__ int2 block_variant(const BlockBox& bb, const double* 
 // Variant of chunk c given the block's (bmode).  A block within the T-series range: the lower of
 // the block's variant and the one for the chunk's own range (both cover the chunk's steps).  A
 // block on the angle-halving path: its chunks take that path with their own number of halvings,
-// or, when their own range allows any T series, the degree-13 one (two code paths only, so the
+// or, when their own range allows any T fit, the degree-11 one (two code paths only, so the
 // loop keeps to its register budget).
 template <int NODES = 1>
 __device__ __forceinline__ int2 chunk_variant(const BlockBox& bb, const double* rg, int c, int bmode, double dt) {
@@ -618,6 +620,223 @@ __global__ void __launch_bounds__(kItem) __attribute__((amdgpu_waves_per_eu(4)))
   process_item4(a, pi, (item - a.desc[pi].item_off) * kItem, lds);
 }
 
+// ---------------------------------------------------------------------------------------------
+// Split-operator steps: the frozen Hamiltonian splits into the part the field does not touch,
+// alpha_z p_z + beta m (in each 2x2 block e_perp tau_z), and the field-driven transverse part
+// P_x tau_x + s P_y tau_y; Strang's symmetric step with the field at the step midpoint is second
+// order (the split-operator scheme Sec. II A names), and the triple-jump composition of three such
+// steps of sizes w1 dt, w0 dt, w1 dt (w1 = 1/(2 - 2^(1/3)), w0 = 1 - 2 w1; Yoshida, Phys. Lett. A
+// 150 (1990) 262) is fourth order (the splitting Sec. V C leaves for future work).
+//
+// Per block the constant factor is R(theta) = exp(-i theta tau_z), theta a multiple of e_perp dt,
+// and the transverse one K = exp(-i Q_s) with Q_s = q_x tau_x + s q_y tau_y, q = (p - A) w dt.
+// Adjacent half steps of R merge, so the whole evolution is
+//     R(-theta_0) [prod over steps, substeps i: R(theta_i) K_i] R(theta_0),
+// theta_0 = e dt/2 (Strang) or w1 e dt/2, theta_i = e dt (Strang) or ((w1 + w0)/2, (w1 + w0)/2,
+// w1) e dt.  In tangent form R(theta) = cos(theta) (1 - i a tau_z), a = tan(theta), and
+// K = C (1 - i T Q_s) with T = tan|q| / |q| (the evolution's polynomial fits, x = |q|^2); since
+// tau_z Q_s = i (q_x tau_y - s q_y tau_x), the product is 1 - i w_s . tau with
+//     w_s = (u - s a v, s v + a u, a),   u = T q_x, v = T q_y,
+// again a scalar multiple of a unitary matrix, of the same norm for both blocks: one rescaling per
+// chunk, as in the midpoint step (34 + n VALU instructions per substep against 31 + n).  Beyond
+// the fits' range the exact C, S (angle halving) and c = cos(theta), s = sin(theta) give
+//     R K = c C - i (S (c q_x - s_b s q_y), S (s_b c q_y + s q_x), s C) . tau,   s_b = +-1.
+// ---------------------------------------------------------------------------------------------
+constexpr double kTripleW1 = 1.3512071919596576;   // 1 / (2 - 2^(1/3))
+constexpr double kTripleW0 = -1.7024143839193153;  // 1 - 2 w1
+
+template <int NSUB>
+struct SplitMode {
+  double pxw[NSUB == 1 ? 1 : 2], pyw[NSUB == 1 ? 1 : 2];  // p w dt for the distinct weights
+  double a[NSUB == 1 ? 1 : 2], c[NSUB == 1 ? 1 : 2], s[NSUB == 1 ? 1 : 2];  // tan, cos, sin of theta_i
+};
+
+// Weight index (into pxw, pyw) and angle index (into a, c, s) of substep i.
+__device__ __forceinline__ constexpr int split_w(int i) { return i == 1 ? 1 : 0; }
+__device__ __forceinline__ constexpr int split_t(int i) { return i == 2 ? 1 : 0; }
+
+// psi <- R(phi) psi for both blocks: a <- a e^{-i phi}, b <- b e^{i phi}.
+__device__ __forceinline__ void phase_z(State& v, double cp, double sp) {
+  double r, i;
+  r = fma(v.ai, sp, v.ar * cp); i = fma(-v.ar, sp, v.ai * cp); v.ar = r; v.ai = i;
+  r = fma(-v.bi, sp, v.br * cp); i = fma(v.br, sp, v.bi * cp); v.br = r; v.bi = i;
+  r = fma(v.ci, sp, v.cr * cp); i = fma(-v.cr, sp, v.ci * cp); v.cr = r; v.ci = i;
+  r = fma(-v.di, sp, v.dr * cp); i = fma(v.dr, sp, v.di * cp); v.dr = r; v.di = i;
+}
+
+template <int V>
+__device__ __forceinline__ void substep_split_tan(State& v, double2 rec, double pxw, double pyw, double a,
+                                                  const Fit<V>& f) {
+  const double qx = pxw + rec.x, qy = pyw + rec.y;  // rec = -A w dt
+  const double x = fma(qx, qx, qy * qy);
+  const double T = tan_ratio<V>(x, f);
+  const double u = T * qx, w = T * qy;
+  rotate_block_tan(v.ar, v.ai, v.br, v.bi, fma(-a, w, u), fma(a, u, w), a);
+  rotate_block_tan(v.cr, v.ci, v.dr, v.di, fma(a, w, u), fma(a, u, -w), a);
+}
+
+__device__ __forceinline__ void substep_split_halving(State& v, double2 rec, double pxw, double pyw, double c,
+                                                      double s, int h, double inv4h) {
+  const double qx = pxw + rec.x, qy = pyw + rec.y;
+  const double x = fma(qx, qx, qy * qy);
+  double C, S;
+  cos_sinc_halved(x, h, inv4h, C, S);
+  const double cC = c * C, sz = s * C;
+  const double cx = c * qx, cy = c * qy, sx = s * qx, sy = s * qy;
+  rotate_block(v.ar, v.ai, v.br, v.bi, cC, S * (cx - sy), S * (cy + sx), sz);
+  rotate_block(v.cr, v.ci, v.dr, v.di, cC, S * (cx + sy), S * (sx - cy), sz);
+}
+
+template <int NSUB, int MODE>
+__device__ __forceinline__ void run_chunk_split(State& v, const double2* buf, int len, const SplitMode<NSUB>& k,
+                                                int h) {
+  if constexpr (MODE < kFineHalving) {
+    const Fit<MODE> f = load_fit<MODE>();
+    if (len == kChunk) {
+#pragma unroll(NSUB == 1 ? 4 : 1)
+      for (int n = 0; n < kChunk; ++n)
+#pragma unroll
+        for (int i = 0; i < NSUB; ++i)
+          substep_split_tan<MODE>(v, buf[n * NSUB + i], k.pxw[split_w(i)], k.pyw[split_w(i)], k.a[split_t(i)], f);
+    } else {
+      for (int n = 0; n < len; ++n)
+#pragma unroll
+        for (int i = 0; i < NSUB; ++i)
+          substep_split_tan<MODE>(v, buf[n * NSUB + i], k.pxw[split_w(i)], k.pyw[split_w(i)], k.a[split_t(i)], f);
+    }
+    renormalise(v);
+  } else {
+    const double inv4h = ldexp(1.0, -2 * h);
+    for (int n = 0; n < len; ++n)
+#pragma unroll
+      for (int i = 0; i < NSUB; ++i)
+        substep_split_halving(v, buf[n * NSUB + i], k.pxw[split_w(i)], k.pyw[split_w(i)], k.c[split_t(i)],
+                              k.s[split_t(i)], h, inv4h);
+  }
+}
+
+struct SplitArgs {
+  const PulseDev* desc;
+  int n_pulses;
+  const double* At;  // [sum nt][NSUB][2] A at the substep midpoints
+  const double* Aedge;
+  const double* ranges;  // [total_chunks][4] range of the table per chunk (k_chunk_ranges<NSUB>)
+  double* f;
+  double* units;
+};
+
+// The chunks of an item: NSUB records per step staged through LDS as -A w_i dt (double-buffered,
+// one barrier per chunk), each chunk in its variant for steps of size w_max dt.
+template <int NSUB, bool HALVING>
+__device__ __forceinline__ void chunk_loop_split(State& v, const double2* tab, int nt, double dt, double dtw,
+                                                 const double* rg, const BlockBox& bb, int bmode,
+                                                 const SplitMode<NSUB>& k, double2 (*lds)[NSUB * kChunk]) {
+  const double wdt[3] = {NSUB == 1 ? -dt : -kTripleW1 * dt, -kTripleW0 * dt, -kTripleW1 * dt};
+  const int nchunks = (nt + kChunk - 1) / kChunk;
+#pragma unroll
+  for (int i = 0; i < NSUB; ++i) {
+    const double2 t = int(threadIdx.x) < nt ? tab[NSUB * threadIdx.x + i] : make_double2(0.0, 0.0);
+    lds[0][NSUB * threadIdx.x + i] = make_double2(t.x * wdt[i], t.y * wdt[i]);
+  }
+  __syncthreads();
+  for (int c = 0; c < nchunks; ++c) {
+    double2 pre[NSUB];
+    const int n = (c + 1) * kChunk + threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < NSUB; ++i) pre[i] = (c + 1 < nchunks && n < nt) ? tab[NSUB * n + i] : make_double2(0.0, 0.0);
+    const double2* buf = lds[c & 1];
+    const int len = min(kChunk, nt - c * kChunk);
+    const int2 cv = chunk_variant<1>(bb, rg, c, bmode, dtw);
+    const int mode = __builtin_amdgcn_readfirstlane(cv.x);
+    if constexpr (HALVING) {
+      if (mode == kFineHalving)
+        run_chunk_split<NSUB, kFineHalving>(v, buf, len, k, __builtin_amdgcn_readfirstlane(cv.y));
+      else
+        run_chunk_split<NSUB, kNumFine - 1>(v, buf, len, k, 0);
+    } else {
+      switch (mode) {
+        case 0: run_chunk_split<NSUB, 0>(v, buf, len, k, 0); break;
+        case 1: run_chunk_split<NSUB, 1>(v, buf, len, k, 0); break;
+        case 2: run_chunk_split<NSUB, 2>(v, buf, len, k, 0); break;
+        case 3: run_chunk_split<NSUB, 3>(v, buf, len, k, 0); break;
+        case 4: run_chunk_split<NSUB, 4>(v, buf, len, k, 0); break;
+        case 5: run_chunk_split<NSUB, 5>(v, buf, len, k, 0); break;
+        case 6: run_chunk_split<NSUB, 6>(v, buf, len, k, 0); break;
+        default: run_chunk_split<NSUB, 7>(v, buf, len, k, 0); break;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NSUB; ++i)
+      lds[(c + 1) & 1][NSUB * threadIdx.x + i] = make_double2(pre[i].x * wdt[i], pre[i].y * wdt[i]);
+    __syncthreads();
+  }
+}
+
+// One 256-mode item of pulse pi, one mode per lane, the structure of process_item4.  The series
+// variant per (selection block, chunk) bounds |q|^2 <= |p - A|^2 (w_max dt)^2 through the
+// second-order bound at step w_max dt (which also counts (1 + p_z^2)(w_max dt)^2: conservative).
+template <int NSUB>
+__device__ __forceinline__ void process_item_split(const SplitArgs& a, int pi, int first,
+                                                   double2 (*lds)[NSUB * kChunk]) {
+  const PulseDev& d = a.desc[pi];
+  const int nt = d.nt;
+  const double dt = d.dt;
+  const double dtw = NSUB == 1 ? dt : -kTripleW0 * dt;  // the largest substep
+  const int64_t nmodes = int64_t(d.n[0]) * d.n[1] * d.n[2];
+  const double2* tab = reinterpret_cast<const double2*>(a.At) + NSUB * d.tab_off;
+  const double2* edge = reinterpret_cast<const double2*>(a.Aedge) + 2 * pi;
+  const int64_t m = int64_t(first) + threadIdx.x;
+  double px, py, pz;
+  mode_momentum(d, m < nmodes ? m : 0, px, py, pz);
+  const double ep = sqrt(fma(pz, pz, 1.0));
+  SplitMode<NSUB> k;
+  double th0;
+  if constexpr (NSUB == 1) {
+    k.pxw[0] = px * dt;
+    k.pyw[0] = py * dt;
+    sincos(ep * dt, &k.s[0], &k.c[0]);
+    th0 = 0.5 * ep * dt;
+  } else {
+    k.pxw[0] = px * (kTripleW1 * dt); k.pyw[0] = py * (kTripleW1 * dt);
+    k.pxw[1] = px * (kTripleW0 * dt); k.pyw[1] = py * (kTripleW0 * dt);
+    sincos(0.5 * (kTripleW1 + kTripleW0) * ep * dt, &k.s[0], &k.c[0]);
+    sincos(kTripleW1 * ep * dt, &k.s[1], &k.c[1]);
+    th0 = 0.5 * kTripleW1 * ep * dt;
+  }
+#pragma unroll
+  for (int j = 0; j < (NSUB == 1 ? 1 : 2); ++j) k.a[j] = k.s[j] / k.c[j];
+  double s0, c0;
+  sincos(th0, &s0, &c0);
+  State v;
+  const double2 ain = edge[0];
+  init_state(v, px - ain.x, py - ain.y, ep);
+  phase_z(v, c0, s0);
+  const BlockBox bb = block_box(d, first / kSelBlock);
+  const double* rg = a.ranges + 4 * int64_t(d.chk_off);
+  const int bmode = __builtin_amdgcn_readfirstlane(block_variant<1>(bb, rg, (nt + kChunk - 1) / kChunk, dtw).x);
+  if (bmode == kFineHalving)
+    chunk_loop_split<NSUB, true>(v, tab, nt, dt, dtw, rg, bb, bmode, k, lds);
+  else
+    chunk_loop_split<NSUB, false>(v, tab, nt, dt, dtw, rg, bb, bmode, k, lds);
+  phase_z(v, c0, -s0);
+
+  const double2 aout = edge[1];
+  double fv = 0.0;
+  if (m < nmodes) {
+    fv = project(v, px - aout.x, py - aout.y, ep);
+    if (a.f) a.f[d.mode_off + m] = fv;
+  }
+  if (a.units) write_unit(d, a.units, m, nmodes, fv);
+}
+
+template <int NSUB>
+__global__ void __launch_bounds__(kItem) k_evolve_split(SplitArgs a) {
+  __shared__ double2 lds[2][NSUB * kChunk];
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  const int pi = find_pulse_item(a.desc, a.n_pulses, item);
+  process_item_split<NSUB>(a, pi, (item - a.desc[pi].item_off) * kItem, lds);
+}
+
 }  // namespace
 
 po_status launch_block_select(const Batch& b, const PulseDev* d_desc, const double* d_A, int2* d_bsel,
@@ -643,11 +862,34 @@ po_status launch_evolve_grid(const Batch& b, const PulseDev* d_desc, const doubl
   return PO_OK;
 }
 
+template <int THREADS, int MPL>
+int resident_persistent_t() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_evolve_persistent<THREADS, MPL>),
+                                                   THREADS, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return n;
+}
+
 int evolve_workgroups_per_cu(const EvolveConfig& cfg) {
-  // waves resident per SIMD at the kernel's register use (4 with one mode per lane, 3 with two),
-  // four SIMDs per CU, THREADS / 64 waves per workgroup
-  const int waves_per_simd = cfg.mpl == 1 ? 4 : 3;
-  return waves_per_simd * 4 / (cfg.threads / 64);
+  // workgroups of the instantiated persistent kernel that fit on one CU at its register and LDS
+  // use (the runtime's occupancy query); if the query fails, the waves-per-SIMD bound each
+  // instantiation is compiled for (4 with one mode per lane, 2 with two), four SIMDs per CU
+  int n = 0;
+  switch (cfg.threads * 10 + cfg.mpl) {
+    case 641: n = resident_persistent_t<64, 1>(); break;
+    case 642: n = resident_persistent_t<64, 2>(); break;
+    case 1281: n = resident_persistent_t<128, 1>(); break;
+    case 1282: n = resident_persistent_t<128, 2>(); break;
+    case 2561: n = resident_persistent_t<256, 1>(); break;
+    case 2562: n = resident_persistent_t<256, 2>(); break;
+    default: break;
+  }
+  if (n > 0) return n;
+  const int waves_per_simd = cfg.mpl == 1 ? 4 : 2;
+  return std::max(1, waves_per_simd * 4 / (cfg.threads / 64));
 }
 
 po_status launch_evolve_persistent(const EvolveConfig& cfg, int n_pulses, const PulseDev* d_desc, const double* d_A,
@@ -703,6 +945,24 @@ po_status launch_evolve4_grid(const Batch& b, const PulseDev* d_desc, const doub
                               const double* d_ranges, double* d_f, double* d_units, hipStream_t s) {
   Evolve4Args a{d_desc, b.n_pulses, d_Ag, d_A_edge, d_ranges, d_f, d_units};
   hipLaunchKernelGGL(k_evolve4, dim3(b.total_items), dim3(kItem), 0, s, a);
+  PO_HIP(hipGetLastError());
+  return PO_OK;
+}
+
+po_status launch_evolve_split_grid(const Batch& b, int order, const PulseDev* d_desc, const double* d_At,
+                                   const double* d_A_edge, double* d_ranges, double* d_f, double* d_units,
+                                   hipStream_t s) {
+  const int max_chunks = (b.max_nt + kChunk - 1) / kChunk;
+  SplitArgs a{d_desc, b.n_pulses, d_At, d_A_edge, d_ranges, d_f, d_units};
+  if (order == 2) {
+    hipLaunchKernelGGL(k_chunk_ranges<1>, dim3(max_chunks, b.n_pulses), dim3(256), 0, s, d_desc, d_At, d_ranges);
+    PO_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_evolve_split<1>, dim3(b.total_items), dim3(kItem), 0, s, a);
+  } else {
+    hipLaunchKernelGGL(k_chunk_ranges<3>, dim3(max_chunks, b.n_pulses), dim3(256), 0, s, d_desc, d_At, d_ranges);
+    PO_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_evolve_split<3>, dim3(b.total_items), dim3(kItem), 0, s, a);
+  }
   PO_HIP(hipGetLastError());
   return PO_OK;
 }

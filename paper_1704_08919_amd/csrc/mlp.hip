@@ -2,106 +2,317 @@
 // weights, Adam.  n_in -> depth x (width, GELU) -> 1; the input is the pulse's coefficient
 // vector, the output a standardised log10 pair yield.
 //
-// Hidden layers are GEMMs on v_mfma_f32_16x16x32_bf16: one wave owns a 16x16 tile of C, each
-// lane feeding 8 consecutive-k bf16 values of one A row and one B column per instruction and
-// receiving 4 rows of one C column.  Epilogues are fused: bias + GELU + bf16 rounding in the
-// forward pass, GELU' in the backward pass.  The 1-wide output layer is a dot product per sample.
-// All reductions (bias gradients, loss, output layer) run in a fixed order, so a training step is
-// bitwise reproducible.
+// Every matrix product is C[m][n] = sum_k A[m][k] Bt[n][k] with both operands contiguous in k, so
+// each lane of a v_mfma_f32_16x16x32_bf16 fetches its 8 consecutive-k values of one A row and one
+// B column with one 16-byte load, straight from L2 (every operand of a step, ~1 MB, stays there).
+// One wave owns a 32x32 tile of C (2 x 2 MFMA tiles: each fragment feeds two instructions); four
+// independent waves per workgroup.  The layouts that make k contiguous are produced by the
+// epilogues that write the operands: the forward pass writes every hidden activation both
+// row-major ([batch][width], the next layer's A) and transposed ([width][batch], the A of the
+// weight gradient); the backward pass writes each pre-activation gradient row-major (A of the
+// next input gradient) and transposed (Bt of the weight gradient); the optimiser keeps every
+// weight matrix in bf16 both as W[k_in][width] (Bt of the input gradient) and as W^T (Bt of the
+// forward product).  Weight gradients (k = batch) are split over k into fixed partial sums that
+// the optimiser adds in order, bias gradients are column sums per 32-row tile fused into the
+// epilogue that produces the pre-activation gradient, and the output layer (a dot product per
+// sample), the loss, dL/dy and the last hidden layer's gradient are one kernel.  A training step
+// is 11 launches, captured once into a HIP graph and replayed; every reduction has a fixed order,
+// so a step is bitwise reproducible.
+//
+// Rounding points (the oracle emulates them): the input is rounded to bf16 through float, every
+// weight matrix used as an operand, every hidden activation gelu(z) and every pre-activation
+// gradient used as an operand are bf16; biases, pre-activations, GELU derivatives, weight and bias
+// gradients and the optimiser state are fp32.
+#include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <new>
-#include <vector>
+#include <type_traits>
 
 #include "common.hpp"
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
-
-struct po_mlp {
-  int n_in = 0, width = 0, depth = 0, max_batch = 0, device = 0;
-  int64_t n_params = 0;
-  int64_t t = 0;               // Adam steps taken
-  float* p = nullptr;          // master parameters, fp32 (layout of the header)
-  float* m = nullptr;          // Adam first moment
-  float* v = nullptr;          // Adam second moment
-  float* g = nullptr;          // last gradient
-  __bf16* wb = nullptr;        // bf16 copies of the weight matrices (same offsets as p)
-  __bf16* h = nullptr;         // activations [depth + 1][max_batch][max(width, n_in)] bf16
-  float* z = nullptr;          // pre-activations [depth][max_batch][width]
-  float* dz = nullptr;         // fp32 gradient of a pre-activation, two buffers [2][max_batch][width]
-  __bf16* dzb = nullptr;       // their bf16 copies (matrix operands), [2][max_batch][width]
-  float* y = nullptr;          // outputs [max_batch]
-  float* dy = nullptr;         // dL/dy [max_batch]
-  float* loss_parts = nullptr; // per-block partial squared errors
-};
 
 namespace po {
 namespace {
 
-constexpr int kLossBlocks = 64;
+constexpr int kTile = 32;      // C tile per wave (rows and columns)
+constexpr int kMaxSplit = 4;   // k-splits of the weight-gradient products
+
+// Device-side counters of a network: the Adam step, its bias corrections and the batch cursor of
+// indexed training (which minibatch of the index array the next step reads).
+struct Counters {
+  long long t;
+  float bc1, bc2;
+  int cursor;
+  int pad;
+};
+
+}  // namespace
+}  // namespace po
+
+struct po_mlp {
+  int n_in = 0, width = 0, depth = 0, max_batch = 0, device = 0;
+  int64_t n_params = 0;
+  float* p = nullptr;          // master parameters, fp32 (layout of the header)
+  float* m = nullptr;          // Adam first moment
+  float* v = nullptr;          // Adam second moment
+  float* g = nullptr;          // last assembled gradient
+  __bf16* wb = nullptr;        // bf16 weights, W_l[k][n] at the parameter offsets
+  __bf16* wt = nullptr;        // bf16 transposed weights, W_l^T[n][k] at the same offsets
+  __bf16* h = nullptr;         // activations h_1..h_depth [depth][max_batch][width] bf16
+  __bf16* hT = nullptr;        // transposed h_0 (the input)..h_{depth-1} [depth][hstride][max_batch]
+  float* gp = nullptr;         // gelu'(z_l) [depth][max_batch][width] fp32
+  __bf16* dz = nullptr;        // pre-activation gradients [2][max_batch][width] bf16 (ping-pong)
+  __bf16* dzT = nullptr;       // transposed [width][max_batch] bf16
+  float* y = nullptr;          // outputs [max_batch]
+  float* wpart = nullptr;      // weight-gradient partials, per layer [kMaxSplit][k_in][width]
+  float* bpart = nullptr;      // bias-gradient partials, per layer [max_batch / 32][width]
+  float* opart = nullptr;      // output layer partials [max_batch / 32][width + 2] (w, b, loss)
+  po::Counters* ctr = nullptr; // device counters
+  hipStream_t cap = nullptr;   // capture stream
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  // the captured step's arguments
+  const void* key_x = nullptr;
+  const void* key_t = nullptr;
+  const void* key_J = nullptr;
+  const void* key_idx = nullptr;
+  const void* key_loss = nullptr;
+  int key_batch = 0, key_rows = 0;
+  float key_lr = 0.0f;
+  double key_mean = 0.0, key_istd = 0.0;
+};
+
+namespace po {
+namespace {
 
 __device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad(float z) {
   return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
 }
 
-// C[M][N] += A[M][K] B[K][N] with A(m, k) = A[m sam + k sak], B(k, n) = B[k sbk + n sbn].
-// Requires M, N multiples of 16 and K a multiple of 32.  EPI selects the epilogue.
-enum { EPI_FWD = 0, EPI_BWD = 1, EPI_WGRAD = 2 };
+enum Epi { EPI_FWD = 0, EPI_FWD_TRAIN = 1, EPI_BWD = 2, EPI_PART = 3 };
 
-template <int EPI>
-__global__ void __launch_bounds__(256) k_gemm(const __bf16* __restrict__ A, int sam, int sak,
-                                              const __bf16* __restrict__ B, int sbk, int sbn, int M, int N, int K,
-                                              const float* __restrict__ bias, const float* __restrict__ zin,
-                                              float* __restrict__ Cf, __bf16* __restrict__ Cb) {
-  const int lane = threadIdx.x & 63;
-  const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int tiles_n = N / 16;
-  if (tile >= (M / 16) * tiles_n) return;
-  const int tm = tile / tiles_n, tn = tile % tiles_n;
-  const int arow = tm * 16 + (lane & 15), bcol = tn * 16 + (lane & 15), kq = (lane >> 4) * 8;
-  floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-  for (int k0 = 0; k0 < K; k0 += 32) {
-    bf16x8 a, b;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      a[i] = A[size_t(arow) * sam + size_t(k0 + kq + i) * sak];
-      b[i] = B[size_t(k0 + kq + i) * sbk + size_t(bcol) * sbn];
-    }
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+// Row map of indexed training: row m of a minibatch is row idx[cursor * batch + m] of the data
+// (rows outside [0, n_rows) read row 0).
+struct RowMap {
+  const int* idx;
+  const Counters* ctr;
+  int batch, n_rows;
+  __device__ __forceinline__ int row(int m) const {
+    if (!idx) return m;
+    const int r = idx[int64_t(ctr->cursor) * batch + m];
+    return (r >= 0 && r < n_rows) ? r : 0;
   }
-  const int col = tn * 16 + (lane & 15);
+};
+
+struct MMArgs {
+  const void* A;      // A[m][k] (bf16, or double rounded to bf16 through float), row stride lda
+  int lda;
+  RowMap rows;        // rows of A (double input only)
+  const __bf16* Bt;   // Bt[n][k], row stride ldb
+  int ldb;
+  int M, N, K, splits;
+  const float* bias;  // [N] (forward)
+  const float* gp_in; // [M][N] gelu' of the layer below (backward)
+  float* gp_out;      // [M][N] gelu'(z) (forward, training)
+  __bf16* C;          // row-major bf16 output [M][N] or NULL
+  __bf16* CT;         // transposed bf16 output [N][ldct] or NULL
+  int ldct;
+  float* part;        // EPI_PART: [splits][M][N]; EPI_BWD: column sums per 32-row tile [M / 32][N]
+  __bf16* AT;         // double input: its bf16 transpose [K][ldat], written by the tiles of column 0
+  int ldat;
+};
+
+__device__ __forceinline__ bf16x8 load8(const __bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
+
+__device__ __forceinline__ bf16x8 load8(const double* p) {
+  bf16x8 r;
+  const double2* q = reinterpret_cast<const double2*>(p);
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int row = tm * 16 + (lane >> 4) * 4 + i;
-    const size_t o = size_t(row) * N + col;
-    if constexpr (EPI == EPI_FWD) {
-      const float zz = acc[i] + bias[col];
-      Cf[o] = zz;
-      Cb[o] = __bf16(gelu(zz));
-    } else if constexpr (EPI == EPI_BWD) {
-      const float d = acc[i] * gelu_grad(zin[o]);
-      Cf[o] = d;
-      Cb[o] = __bf16(d);
-    } else {
-      Cf[o] = acc[i];
+    const double2 d = q[i];
+    r[2 * i] = __bf16(float(d.x));
+    r[2 * i + 1] = __bf16(float(d.y));
+  }
+  return r;
+}
+
+// C = A Bt^T for one 32x32 tile per wave; EPI selects what the tile writes.
+template <class TA, int EPI>
+__global__ void __launch_bounds__(256) k_mm(MMArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int tm_n = a.M / kTile, tn_n = a.N / kTile;
+  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= tm_n * tn_n * a.splits) return;
+  const int split = w / (tm_n * tn_n);
+  const int tt = w - split * tm_n * tn_n;
+  const int tm = tt / tn_n, tn = tt - tm * tn_n;
+  const int kc = a.K / a.splits;
+  const int k_beg = split * kc, k_end = k_beg + kc;
+  const int r16 = lane & 15, kq = (lane >> 4) * 8;
+  const TA* A = static_cast<const TA*>(a.A);
+  int arow[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int m = tm * kTile + i * 16 + r16;
+    arow[i] = std::is_same<TA, double>::value ? a.rows.row(m) : m;
+  }
+  floatx4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k0 = k_beg; k0 < k_end; k0 += 32) {
+    bf16x8 af[2], bf[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) af[i] = load8(A + size_t(arow[i]) * a.lda + k0 + kq);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) bf[j] = load8(a.Bt + size_t(tn * kTile + j * 16 + r16) * a.ldb + k0 + kq);
+    if constexpr (std::is_same<TA, double>::value) {
+      if (a.AT && tn == 0) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) a.AT[size_t(k0 + kq + e) * a.ldat + tm * kTile + i * 16 + r16] = af[i][e];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+  }
+  // lane holds rows tm*32 + i*16 + (lane >> 4)*4 + r, r = 0..3, of column tn*32 + j*16 + (lane & 15)
+  const int rq = (lane >> 4) * 4;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int n = tn * kTile + j * 16 + r16;
+    float colsum = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int m0 = tm * kTile + i * 16 + rq;
+      bf16x4 t4;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + r;
+        const size_t o = size_t(m) * a.N + n;
+        const float c = acc[i][j][r];
+        if constexpr (EPI == EPI_FWD || EPI == EPI_FWD_TRAIN) {
+          const float z = c + a.bias[n];
+          const __bf16 hb = __bf16(gelu(z));
+          a.C[o] = hb;
+          if constexpr (EPI == EPI_FWD_TRAIN) {
+            a.gp_out[o] = gelu_grad(z);
+            t4[r] = hb;
+          }
+        } else if constexpr (EPI == EPI_BWD) {
+          const float d = c * a.gp_in[o];
+          const __bf16 db = __bf16(d);
+          if (a.C) a.C[o] = db;
+          t4[r] = db;
+          colsum += d;
+        } else {
+          a.part[size_t(split) * a.M * a.N + o] = c;
+        }
+      }
+      if constexpr (EPI == EPI_FWD_TRAIN || EPI == EPI_BWD) {
+        if (a.CT) *reinterpret_cast<bf16x4*>(a.CT + size_t(n) * a.ldct + m0) = t4;
+      }
+    }
+    if constexpr (EPI == EPI_BWD) {
+      // column sum over the tile's 32 rows: lanes n, n + 16, n + 32, n + 48 hold 8 rows each
+      colsum += __shfl_xor(colsum, 16, 64);
+      colsum += __shfl_xor(colsum, 32, 64);
+      if (lane < 16) a.part[size_t(tm) * a.N + n] = colsum;
     }
   }
 }
 
-// Input coefficients (double) -> bf16 through float, round to nearest even.
-__global__ void k_input(const double* __restrict__ x, int64_t n, __bf16* __restrict__ out) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = __bf16(float(x[i]));
+// Output layer and loss of a training step, one workgroup per 32 samples b0..b0+31:
+// y = h w + b0, t the target (given, or the standardised log10 J of the sample's data row),
+// dy = 2 (y - t) / B; dz = dy w gelu'(z) of the last hidden layer (bf16 row-major and transposed);
+// per-workgroup partial sums (in sample order) of dL/dw = h dy, of the last layer's bias gradient
+// sum dz, of dL/db = sum dy and of the squared error.
+struct OutArgs {
+  const __bf16* h;    // [B][W] last hidden activations
+  const __bf16* w;    // [W] output weights (bf16)
+  const float* b0;    // [1] output bias
+  const float* gp;    // [B][W] gelu' of the last hidden layer
+  const float* target;  // [B] or NULL
+  const double* J;    // data yields (indexed training) or NULL
+  RowMap rows;
+  double mean, inv_std;
+  int W, B;
+  float* y;
+  __bf16* dz;         // [B][W]
+  __bf16* dzT;        // [W][ldt]
+  int ldt;
+  float* bpart;       // [B / 32][W] bias partials of the last hidden layer
+  float* opart;       // [B / 32][W + 2]: dL/dw partials, then dL/db, squared error
+};
+
+__global__ void __launch_bounds__(256) k_out_train(OutArgs a) {
+  __shared__ float s_dy[32], s_sq[32];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int b0 = blockIdx.x * 32;
+  for (int q = 0; q < 8; ++q) {
+    const int b = b0 + wv * 8 + q;
+    float acc = 0.0f;
+    for (int j = lane; j < a.W; j += 64) acc = fmaf(float(a.h[size_t(b) * a.W + j]), float(a.w[j]), acc);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) {
+      const float yb = acc + a.b0[0];
+      a.y[b] = yb;
+      float t;
+      if (a.J) {
+        const double Jv = a.J[a.rows.row(b)];
+        t = float((log10(fmax(Jv, 1e-300)) - a.mean) * a.inv_std);
+      } else {
+        t = a.target[b];
+      }
+      const float d = yb - t;
+      s_dy[wv * 8 + q] = 2.0f * d / float(a.B);
+      s_sq[wv * 8 + q] = d * d;
+    }
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < a.W; j += 256) {
+    const float wj = float(a.w[j]);
+    float sb = 0.0f, sw = 0.0f;
+    for (int r = 0; r < 32; r += 4) {
+      bf16x4 t4;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int b = b0 + r + e;
+        const size_t o = size_t(b) * a.W + j;
+        const float d = s_dy[r + e] * wj * a.gp[o];
+        const __bf16 db = __bf16(d);
+        a.dz[o] = db;
+        t4[e] = db;
+        sb += d;
+        sw = fmaf(float(a.h[o]), s_dy[r + e], sw);
+      }
+      *reinterpret_cast<bf16x4*>(a.dzT + size_t(j) * a.ldt + b0 + r) = t4;
+    }
+    a.bpart[size_t(blockIdx.x) * a.W + j] = sb;
+    a.opart[size_t(blockIdx.x) * (a.W + 2) + j] = sw;
+  }
+  if (threadIdx.x == 0) {
+    float sd = 0.0f, sq = 0.0f;
+    for (int r = 0; r < 32; ++r) {
+      sd += s_dy[r];
+      sq += s_sq[r];
+    }
+    a.opart[size_t(blockIdx.x) * (a.W + 2) + a.W] = sd;
+    a.opart[size_t(blockIdx.x) * (a.W + 2) + a.W + 1] = sq;
+  }
 }
 
-// Master weights -> bf16 copies (weights only; biases are used in fp32).
-__global__ void k_weights_to_bf16(const float* __restrict__ p, int64_t n, __bf16* __restrict__ wb) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) wb[i] = __bf16(p[i]);
-}
-
-// Output layer: y[b] = sum_j h[b][j] w[j] + b0, one wave per sample, fixed butterfly order.
+// Output layer for inference: y[b] = sum_j h[b][j] w[j] + b0, one wave per sample.
 __global__ void __launch_bounds__(256) k_out_fwd(const __bf16* __restrict__ h, const __bf16* __restrict__ w,
                                                  const float* __restrict__ b0, int width, int batch,
                                                  float* __restrict__ y) {
@@ -115,80 +326,120 @@ __global__ void __launch_bounds__(256) k_out_fwd(const __bf16* __restrict__ h, c
   if (lane == 0) y[s] = acc + b0[0];
 }
 
-// dL/dy = 2 (y - t) / B, per-block partial squared errors.
-__global__ void __launch_bounds__(256) k_out_loss(const float* __restrict__ y, const float* __restrict__ t, int batch,
-                                                  float* __restrict__ dy, float* __restrict__ parts) {
-  __shared__ float red[256];
-  float sq = 0.0f;
-  for (int i = blockIdx.x * 256 + threadIdx.x; i < batch; i += gridDim.x * 256) {
-    const float d = y[i] - t[i];
-    dy[i] = 2.0f * d / float(batch);
-    sq = fmaf(d, d, sq);
-  }
-  red[threadIdx.x] = sq;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (int(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) parts[blockIdx.x] = red[0];
+// Where parameter i lives: hidden layer l weight (k, n) or bias n, or the output layer.
+struct ParamMap {
+  int n_in, width, depth, splits, nblk, batch;
+  int64_t n_params;
+  const float* wpart;  // per layer [kMaxSplit][k_in][width]
+  const float* bpart;  // per layer [max_batch / 32][width]
+  const float* opart;  // [max_batch / 32][width + 2]
+  int64_t bpart_stride;  // max_batch / 32 * width
+};
+
+__device__ __forceinline__ int64_t wpart_off(const ParamMap& q, int l) {
+  return l == 0 ? 0 : int64_t(kMaxSplit) * q.n_in * q.width + int64_t(l - 1) * kMaxSplit * q.width * q.width;
 }
 
-__global__ void __launch_bounds__(256) k_loss_final(const float* __restrict__ parts, int n, int batch,
-                                                    float* __restrict__ loss) {
-  if (threadIdx.x == 0) {
-    float s = 0.0f;
-    for (int i = 0; i < n; ++i) s += parts[i];
-    *loss = s / float(batch);
-  }
-}
-
-// Output-layer gradients: gw[j] = sum_b h[b][j] dy[b] (one thread per j, b in order), gb = sum dy;
-// and dz[b][j] = dy[b] w[j] gelu'(z[b][j]) for the last hidden layer (fp32 and bf16).
-__global__ void __launch_bounds__(256) k_out_bwd(const __bf16* __restrict__ h, const __bf16* __restrict__ w,
-                                                 const float* __restrict__ dy, const float* __restrict__ z, int width,
-                                                 int batch, float* __restrict__ gw, float* __restrict__ gb,
-                                                 float* __restrict__ dz, __bf16* __restrict__ dzb) {
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j < width) {
-    float acc = 0.0f;
-    for (int b = 0; b < batch; ++b) acc = fmaf(float(h[size_t(b) * width + j]), dy[b], acc);
-    gw[j] = acc;
-    const float wj = float(w[j]);
-    for (int b = 0; b < batch; ++b) {
-      const size_t o = size_t(b) * width + j;
-      const float d = dy[b] * wj * gelu_grad(z[o]);
-      dz[o] = d;
-      dzb[o] = __bf16(d);
+// Gradient of parameter i: its partial sums added in a fixed order.
+__device__ __forceinline__ float assembled_grad(const ParamMap& q, int64_t i) {
+  int64_t off = 0;
+  int kin = q.n_in;
+  for (int l = 0; l < q.depth; ++l) {
+    const int64_t nw = int64_t(kin) * q.width;
+    if (i < off + nw) {
+      const int64_t e = i - off;
+      const float* pp = q.wpart + wpart_off(q, l);
+      float s = 0.0f;
+      for (int sp = 0; sp < q.splits; ++sp) s += pp[sp * nw + e];
+      return s;
     }
+    if (i < off + nw + q.width) {
+      const int n = int(i - off - nw);
+      const float* bp = q.bpart + l * q.bpart_stride;
+      float s = 0.0f;
+      for (int t = 0; t < q.nblk; ++t) s += bp[int64_t(t) * q.width + n];
+      return s;
+    }
+    off += nw + q.width;
+    kin = q.width;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    float s = 0.0f;
-    for (int b = 0; b < batch; ++b) s += dy[b];
-    gb[0] = s;
-  }
-}
-
-// Bias gradient: column sums of dz over the batch, in batch order.
-__global__ void __launch_bounds__(256) k_colsum(const float* __restrict__ dz, int width, int batch,
-                                                float* __restrict__ gb) {
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= width) return;
+  const int j = int(i - off);  // 0..width-1: output weights; width: output bias
   float s = 0.0f;
-  for (int b = 0; b < batch; ++b) s += dz[size_t(b) * width + j];
-  gb[j] = s;
+  for (int t = 0; t < q.nblk; ++t) s += q.opart[int64_t(t) * (q.width + 2) + j];
+  return s;
 }
 
-__global__ void k_adam(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
-                       const float* __restrict__ g, int64_t n, float lr, float bc1, float bc2) {
+// Transposed position of parameter i (weights of a hidden layer; others map to themselves).
+__device__ __forceinline__ int64_t transposed_index(const ParamMap& q, int64_t i) {
+  int64_t off = 0;
+  int kin = q.n_in;
+  for (int l = 0; l < q.depth; ++l) {
+    const int64_t nw = int64_t(kin) * q.width;
+    if (i < off + nw) {
+      const int64_t e = i - off;
+      const int64_t k = e / q.width, n = e - k * q.width;
+      return off + n * kin + k;
+    }
+    if (i < off + nw + q.width) return i;  // the layer's bias
+    off += nw + q.width;
+    kin = q.width;
+  }
+  return i;
+}
+
+// Starts an optimiser step: t += 1 and its bias corrections; advances the indexed-training cursor.
+__global__ void k_adam_begin(Counters* c) {
+  const long long t = c->t + 1;
+  c->t = t;
+  c->bc1 = float(1.0 - pow(0.9, double(t)));
+  c->bc2 = float(1.0 - pow(0.999, double(t)));
+  c->cursor += 1;
+}
+
+// Assembles the gradient (from the partials, or takes g_in), then Adam and the bf16 copies.
+// Thread 0 of block 0 also writes the loss of the step (sum of the squared-error partials / B).
+__global__ void __launch_bounds__(256) k_adam(ParamMap q, const float* __restrict__ g_in, float* __restrict__ p,
+                                              float* __restrict__ m, float* __restrict__ v, float* __restrict__ g_out,
+                                              __bf16* __restrict__ wb, __bf16* __restrict__ wt, float lr,
+                                              const Counters* __restrict__ c, float* __restrict__ loss,
+                                              int loss_by_cursor) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float gi = g[i];
+  if (i == 0 && loss) {
+    float s = 0.0f;
+    for (int t = 0; t < q.nblk; ++t) s += q.opart[int64_t(t) * (q.width + 2) + q.width + 1];
+    loss[loss_by_cursor ? c->cursor - 1 : 0] = s / float(q.batch);
+  }
+  if (i >= q.n_params) return;
+  const float gi = g_in ? g_in[i] : assembled_grad(q, i);
+  if (g_out) g_out[i] = gi;
+  if (lr < 0.0f) return;  // gradient only
   const float mi = 0.9f * m[i] + 0.1f * gi;
   const float vi = 0.999f * v[i] + 0.001f * gi * gi;
   m[i] = mi;
   v[i] = vi;
-  p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + 1e-8f);
+  const float pi = p[i] - lr * (mi / c->bc1) / (sqrtf(vi / c->bc2) + 1e-8f);
+  p[i] = pi;
+  const __bf16 pb = __bf16(pi);
+  wb[i] = pb;
+  wt[transposed_index(q, i)] = pb;
+}
+
+// Master weights -> bf16 copies, row-major and transposed.
+__global__ void k_weights_to_bf16(ParamMap q, const float* __restrict__ p, __bf16* __restrict__ wb,
+                                  __bf16* __restrict__ wt) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= q.n_params) return;
+  const __bf16 pb = __bf16(p[i]);
+  wb[i] = pb;
+  wt[transposed_index(q, i)] = pb;
+}
+
+__global__ void k_reset_counters(Counters* c, int reset_t) {
+  if (reset_t) {
+    c->t = 0;
+    c->bc1 = c->bc2 = 1.0f;
+  }
+  c->cursor = 0;
 }
 
 // Philox4x32-10 (Salmon et al., SC'11) for the initial weights.
@@ -252,88 +503,213 @@ int64_t layer_w_off(const po_mlp* a, int l) {
   }
   return o;
 }
-int64_t layer_k(const po_mlp* a, int l) { return l == 0 ? a->n_in : a->width; }
-
+int layer_k(const po_mlp* a, int l) { return l == 0 ? a->n_in : a->width; }
+int hstride(const po_mlp* a) { return std::max(a->width, a->n_in); }
 int blocks(int64_t n, int t = 256) { return int((n + t - 1) / t); }
 
-po_status forward_impl(po_mlp* a, const double* d_x, int B, float* d_y, hipStream_t s) {
-  const int W = a->width;
-  const int hstride = std::max(a->width, a->n_in);
-  hipLaunchKernelGGL(k_input, dim3(blocks(int64_t(B) * a->n_in)), dim3(256), 0, s, d_x, int64_t(B) * a->n_in, a->h);
-  PO_HIP(hipGetLastError());
-  for (int l = 0; l < a->depth; ++l) {
-    const int K = int(layer_k(a, l));
-    const int64_t wo = layer_w_off(a, l);
-    const __bf16* hin = a->h + size_t(l) * a->max_batch * hstride;
-    __bf16* hout = a->h + size_t(l + 1) * a->max_batch * hstride;
-    float* z = a->z + size_t(l) * a->max_batch * W;
-    const int tiles = (B / 16) * (W / 16);
-    hipLaunchKernelGGL(k_gemm<EPI_FWD>, dim3(blocks(tiles, 4)), dim3(256), 0, s, hin, K, 1, a->wb + wo, W, 1, B, W, K,
-                       a->p + wo + int64_t(K) * W, nullptr, z, hout);
-    PO_HIP(hipGetLastError());
-  }
-  const int64_t wo = layer_w_off(a, a->depth);
-  const __bf16* hl = a->h + size_t(a->depth) * a->max_batch * hstride;
-  hipLaunchKernelGGL(k_out_fwd, dim3(blocks(B, 4)), dim3(256), 0, s, hl, a->wb + wo, a->p + wo + W, W, B,
-                     d_y ? d_y : a->y);
+int splits_for(int B) {
+  const int kt = B / 32;
+  return kt % 4 == 0 ? 4 : (kt % 2 == 0 ? 2 : 1);
+}
+
+ParamMap param_map(const po_mlp* a, int B) {
+  ParamMap q;
+  q.n_in = a->n_in;
+  q.width = a->width;
+  q.depth = a->depth;
+  q.splits = splits_for(B);
+  q.nblk = B / 32;
+  q.batch = B;
+  q.n_params = a->n_params;
+  q.wpart = a->wpart;
+  q.bpart = a->bpart;
+  q.opart = a->opart;
+  q.bpart_stride = int64_t(a->max_batch / 32) * a->width;
+  return q;
+}
+
+int64_t wpart_offset(const po_mlp* a, int l) {
+  return l == 0 ? 0 : int64_t(kMaxSplit) * a->n_in * a->width + int64_t(l - 1) * kMaxSplit * a->width * a->width;
+}
+
+template <class TA, int EPI>
+po_status launch_mm(const MMArgs& m, hipStream_t s) {
+  const int waves = (m.M / kTile) * (m.N / kTile) * m.splits;
+  hipLaunchKernelGGL((k_mm<TA, EPI>), dim3(blocks(waves, 4)), dim3(256), 0, s, m);
   PO_HIP(hipGetLastError());
   return PO_OK;
 }
 
-po_status grad_impl(po_mlp* a, const double* d_x, const float* d_t, int B, float* d_loss, hipStream_t s) {
-  const int W = a->width;
-  const int hstride = std::max(a->width, a->n_in);
-  PO_TRY(forward_impl(a, d_x, B, a->y, s));
-  const int lb = std::min(kLossBlocks, blocks(B));
-  hipLaunchKernelGGL(k_out_loss, dim3(lb), dim3(256), 0, s, a->y, d_t, B, a->dy, a->loss_parts);
-  PO_HIP(hipGetLastError());
-  if (d_loss) {
-    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, s, a->loss_parts, lb, B, d_loss);
-    PO_HIP(hipGetLastError());
+MMArgs mm_base() {
+  MMArgs m;
+  std::memset(&m, 0, sizeof m);
+  m.splits = 1;
+  return m;
+}
+
+// Forward pass through the hidden layers.  train: also gelu' and the transposed activations.
+po_status hidden_forward(po_mlp* a, const double* d_x, RowMap rows, int B, bool train, hipStream_t s) {
+  const int W = a->width, hs = hstride(a);
+  for (int l = 0; l < a->depth; ++l) {
+    const int K = layer_k(a, l);
+    const int64_t wo = layer_w_off(a, l);
+    MMArgs m = mm_base();
+    m.lda = K;
+    m.Bt = a->wt + wo;
+    m.ldb = K;
+    m.M = B;
+    m.N = W;
+    m.K = K;
+    m.bias = a->p + wo + int64_t(K) * W;
+    m.C = a->h + size_t(l) * a->max_batch * W;
+    if (train) {
+      m.gp_out = a->gp + size_t(l) * a->max_batch * W;
+      m.CT = l + 1 < a->depth ? a->hT + size_t(l + 1) * hs * a->max_batch : nullptr;
+      m.ldct = a->max_batch;
+    }
+    if (l == 0) {
+      m.A = d_x;
+      m.rows = rows;
+      if (train) {
+        m.AT = a->hT;
+        m.ldat = a->max_batch;
+      }
+      PO_TRY((train ? launch_mm<double, EPI_FWD_TRAIN>(m, s) : launch_mm<double, EPI_FWD>(m, s)));
+    } else {
+      m.A = a->h + size_t(l - 1) * a->max_batch * W;
+      PO_TRY((train ? launch_mm<__bf16, EPI_FWD_TRAIN>(m, s) : launch_mm<__bf16, EPI_FWD>(m, s)));
+    }
   }
-  const int D = a->depth;
-  const int64_t wo = layer_w_off(a, D);
-  const __bf16* hl = a->h + size_t(D) * a->max_batch * hstride;
-  const size_t slot = size_t(a->max_batch) * W;
-  int cur = 0;
-  hipLaunchKernelGGL(k_out_bwd, dim3(blocks(W)), dim3(256), 0, s, hl, a->wb + wo, a->dy,
-                     a->z + size_t(D - 1) * a->max_batch * W, W, B, a->g + wo, a->g + wo + W, a->dz, a->dzb);
+  return PO_OK;
+}
+
+po_status forward_impl(po_mlp* a, const double* d_x, int B, float* d_y, hipStream_t s) {
+  RowMap rows{nullptr, nullptr, B, B};
+  PO_TRY(hidden_forward(a, d_x, rows, B, false, s));
+  const int64_t wo = layer_w_off(a, a->depth);
+  hipLaunchKernelGGL(k_out_fwd, dim3(blocks(B, 4)), dim3(256), 0, s, a->h + size_t(a->depth - 1) * a->max_batch * a->width,
+                     a->wb + wo, a->p + wo + a->width, a->width, B, d_y);
   PO_HIP(hipGetLastError());
+  return PO_OK;
+}
+
+// Forward and backward pass of one minibatch: fills the gradient partials and the loss partials.
+// Targets: d_t[b], or (d_J != NULL) the standardised log10 of the yield of the sample's data row.
+po_status grad_impl(po_mlp* a, const double* d_x, RowMap rows, const float* d_t, const double* d_J, double mean,
+                    double inv_std, int B, hipStream_t s) {
+  const int W = a->width, D = a->depth, hs = hstride(a);
+  const int S = splits_for(B);
+  PO_TRY(hidden_forward(a, d_x, rows, B, true, s));
+  const size_t slot = size_t(a->max_batch) * W;
+  OutArgs o;
+  std::memset(&o, 0, sizeof o);
+  const int64_t wo = layer_w_off(a, D);
+  o.h = a->h + size_t(D - 1) * slot;
+  o.w = a->wb + wo;
+  o.b0 = a->p + wo + W;
+  o.gp = a->gp + size_t(D - 1) * slot;
+  o.target = d_t;
+  o.J = d_J;
+  o.rows = rows;
+  o.mean = mean;
+  o.inv_std = inv_std;
+  o.W = W;
+  o.B = B;
+  o.y = a->y;
+  o.dz = a->dz;
+  o.dzT = a->dzT;
+  o.ldt = a->max_batch;
+  o.bpart = a->bpart + size_t(D - 1) * (a->max_batch / 32) * W;
+  o.opart = a->opart;
+  hipLaunchKernelGGL(k_out_train, dim3(B / 32), dim3(256), 0, s, o);
+  PO_HIP(hipGetLastError());
+  int cur = 0;
   for (int l = D - 1; l >= 0; --l) {
-    const int K = int(layer_k(a, l));
-    const int64_t o = layer_w_off(a, l);
-    const __bf16* hin = a->h + size_t(l) * a->max_batch * hstride;
-    const float* dz = a->dz + cur * slot;
-    const __bf16* dzb = a->dzb + cur * slot;
-    // dW_l[k][n] = sum_b h_l[b][k] dz[b][n]: A = h_l^T (K x B), B = dz (B x W)
-    const int tiles_w = (K / 16) * (W / 16);
-    hipLaunchKernelGGL(k_gemm<EPI_WGRAD>, dim3(blocks(tiles_w, 4)), dim3(256), 0, s, hin, 1, K, dzb, W, 1, K, W, B,
-                       nullptr, nullptr, a->g + o, nullptr);
-    PO_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_colsum, dim3(blocks(W)), dim3(256), 0, s, dz, W, B, a->g + o + int64_t(K) * W);
-    PO_HIP(hipGetLastError());
+    const int K = layer_k(a, l);
+    const int64_t off = layer_w_off(a, l);
+    // dW_l[k][n] = sum_b h_l[b][k] dz_l[b][n]: A = h_l^T [K][B], Bt = dz_l^T [W][B], split over b
+    MMArgs g = mm_base();
+    g.A = a->hT + size_t(l) * hs * a->max_batch;
+    g.lda = a->max_batch;
+    g.Bt = a->dzT;
+    g.ldb = a->max_batch;
+    g.M = K;
+    g.N = W;
+    g.K = B;
+    g.splits = S;
+    g.part = a->wpart + wpart_offset(a, l);
+    PO_TRY((launch_mm<__bf16, EPI_PART>(g, s)));
     if (l > 0) {
-      // dh_l[b][k] = sum_n dz[b][n] W_l[k][n]: A = dz (B x W), B = W_l^T (W x K); times gelu'(z_{l-1}),
-      // written to the other buffer of the pair
-      const int tiles_h = (B / 16) * (K / 16);
-      hipLaunchKernelGGL(k_gemm<EPI_BWD>, dim3(blocks(tiles_h, 4)), dim3(256), 0, s, dzb, W, 1, a->wb + o, 1, W, B, K, W,
-                         nullptr, a->z + size_t(l - 1) * a->max_batch * W, a->dz + (1 - cur) * slot,
-                         a->dzb + (1 - cur) * slot);
-      PO_HIP(hipGetLastError());
+      // dh_{l}[b][k] = sum_n dz_l[b][n] W_l[k][n]: A = dz_l [B][W], Bt = W_l [K][W]; times gelu'(z_{l-1})
+      MMArgs d = mm_base();
+      d.A = a->dz + cur * slot;
+      d.lda = W;
+      d.Bt = a->wb + off;
+      d.ldb = W;
+      d.M = B;
+      d.N = K;
+      d.K = W;
+      d.gp_in = a->gp + size_t(l - 1) * slot;
+      d.C = l - 1 > 0 ? a->dz + (1 - cur) * slot : nullptr;
+      d.CT = a->dzT;
+      d.ldct = a->max_batch;
+      d.part = a->bpart + size_t(l - 1) * (a->max_batch / 32) * W;
+      PO_TRY((launch_mm<__bf16, EPI_BWD>(d, s)));
       cur = 1 - cur;
     }
   }
   return PO_OK;
 }
 
-po_status adam_impl(po_mlp* a, const float* g, float lr, hipStream_t s) {
-  a->t += 1;
-  const float bc1 = float(1.0 - std::pow(0.9, double(a->t)));
-  const float bc2 = float(1.0 - std::pow(0.999, double(a->t)));
-  hipLaunchKernelGGL(k_adam, dim3(blocks(a->n_params)), dim3(256), 0, s, a->p, a->m, a->v, g, a->n_params, lr, bc1, bc2);
+po_status adam_launch(po_mlp* a, int B, const float* g_in, float* g_out, float lr, float* loss, int loss_by_cursor,
+                      hipStream_t s) {
+  if (lr >= 0.0f) {
+    hipLaunchKernelGGL(k_adam_begin, dim3(1), dim3(1), 0, s, a->ctr);
+    PO_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_adam, dim3(blocks(a->n_params)), dim3(256), 0, s, param_map(a, B), g_in, a->p, a->m, a->v, g_out,
+                     a->wb, a->wt, lr, a->ctr, loss, loss_by_cursor);
   PO_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_weights_to_bf16, dim3(blocks(a->n_params)), dim3(256), 0, s, a->p, a->n_params, a->wb);
-  PO_HIP(hipGetLastError());
+  return PO_OK;
+}
+
+// Captures one training step (forward, backward, optimiser) with the given arguments unless the
+// graph already holds them, then replays it `steps` times on stream s.
+po_status train_replay(po_mlp* a, const double* d_x, const float* d_t, const double* d_J, const int* d_idx, int n_rows,
+                       double mean, double inv_std, int B, float lr, float* d_loss, int steps, hipStream_t s) {
+  const bool same = a->exec && a->key_x == d_x && a->key_t == d_t && a->key_J == d_J && a->key_idx == d_idx &&
+                    a->key_loss == d_loss && a->key_batch == B && a->key_rows == n_rows && a->key_lr == lr &&
+                    a->key_mean == mean && a->key_istd == inv_std;
+  if (!same) {
+    if (a->exec) (void)hipGraphExecDestroy(a->exec);
+    if (a->graph) (void)hipGraphDestroy(a->graph);
+    a->exec = nullptr;
+    a->graph = nullptr;
+    PO_HIP(hipStreamBeginCapture(a->cap, hipStreamCaptureModeThreadLocal));
+    RowMap rows{d_idx, a->ctr, B, n_rows};
+    po_status st = grad_impl(a, d_x, rows, d_t, d_J, mean, inv_std, B, a->cap);
+    if (st == PO_OK) st = adam_launch(a, B, nullptr, a->g, lr, d_loss, d_idx ? 1 : 0, a->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(a->cap, &g);
+    if (st != PO_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return device_error(e, "hipStreamEndCapture");
+    a->graph = g;
+    PO_HIP(hipGraphInstantiate(&a->exec, a->graph, nullptr, nullptr, 0));
+    a->key_x = d_x;
+    a->key_t = d_t;
+    a->key_J = d_J;
+    a->key_idx = d_idx;
+    a->key_loss = d_loss;
+    a->key_batch = B;
+    a->key_rows = n_rows;
+    a->key_lr = lr;
+    a->key_mean = mean;
+    a->key_istd = inv_std;
+  }
+  for (int i = 0; i < steps; ++i) PO_HIP(hipGraphLaunch(a->exec, s));
   return PO_OK;
 }
 
@@ -347,7 +723,11 @@ po_status check_batch(const po_mlp* a, int B) {
 }
 
 void mlp_free(po_mlp* a) {
-  void* bufs[] = {a->p, a->m, a->v, a->g, a->wb, a->h, a->z, a->dz, a->dzb, a->y, a->dy, a->loss_parts};
+  if (a->exec) (void)hipGraphExecDestroy(a->exec);
+  if (a->graph) (void)hipGraphDestroy(a->graph);
+  if (a->cap) (void)hipStreamDestroy(a->cap);
+  void* bufs[] = {a->p,  a->m, a->v,     a->g,     a->wb,    a->wt,    a->h,  a->hT,
+                  a->gp, a->dz, a->dzT,  a->y,     a->wpart, a->bpart, a->opart, a->ctr};
   for (void* q : bufs)
     if (q) (void)hipFree(q);
 }
@@ -369,21 +749,28 @@ po_status create_impl(po_mlp* a, uint64_t seed, hipStream_t s) {
   }
   np += a->width + 1;
   a->n_params = np;
-  const int hstride = std::max(a->width, a->n_in);
+  const int W = a->width, hs = hstride(a), MB = a->max_batch;
   PO_TRY(dalloc(&a->p, np));
   PO_TRY(dalloc(&a->m, np));
   PO_TRY(dalloc(&a->v, np));
   PO_TRY(dalloc(&a->g, np));
   PO_TRY(dalloc(&a->wb, np));
-  PO_TRY(dalloc(&a->h, size_t(a->depth + 1) * a->max_batch * hstride));
-  PO_TRY(dalloc(&a->z, size_t(a->depth) * a->max_batch * a->width));
-  PO_TRY(dalloc(&a->dz, 2 * size_t(a->max_batch) * a->width));
-  PO_TRY(dalloc(&a->dzb, 2 * size_t(a->max_batch) * a->width));
-  PO_TRY(dalloc(&a->y, a->max_batch));
-  PO_TRY(dalloc(&a->dy, a->max_batch));
-  PO_TRY(dalloc(&a->loss_parts, kLossBlocks));
+  PO_TRY(dalloc(&a->wt, np));
+  PO_TRY(dalloc(&a->h, size_t(a->depth) * MB * W));
+  PO_TRY(dalloc(&a->hT, size_t(a->depth) * hs * MB));
+  PO_TRY(dalloc(&a->gp, size_t(a->depth) * MB * W));
+  PO_TRY(dalloc(&a->dz, 2 * size_t(MB) * W));
+  PO_TRY(dalloc(&a->dzT, size_t(W) * MB));
+  PO_TRY(dalloc(&a->y, MB));
+  PO_TRY(dalloc(&a->wpart, size_t(kMaxSplit) * (size_t(a->n_in) * W + size_t(a->depth - 1) * W * W)));
+  PO_TRY(dalloc(&a->bpart, size_t(a->depth) * (MB / 32) * W));
+  PO_TRY(dalloc(&a->opart, size_t(MB / 32) * (W + 2)));
+  PO_TRY(dalloc(&a->ctr, 1));
+  PO_HIP(hipStreamCreateWithFlags(&a->cap, hipStreamNonBlocking));
   PO_HIP(hipMemsetAsync(a->m, 0, sizeof(float) * np, s));
   PO_HIP(hipMemsetAsync(a->v, 0, sizeof(float) * np, s));
+  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(1), 0, s, a->ctr, 1);
+  PO_HIP(hipGetLastError());
   k = a->n_in;
   for (int l = 0; l <= a->depth; ++l) {
     const int64_t kin = (l < a->depth) ? k : a->width;
@@ -393,7 +780,7 @@ po_status create_impl(po_mlp* a, uint64_t seed, hipStream_t s) {
     PO_HIP(hipGetLastError());
     k = a->width;
   }
-  hipLaunchKernelGGL(k_weights_to_bf16, dim3(blocks(np)), dim3(256), 0, s, a->p, np, a->wb);
+  hipLaunchKernelGGL(k_weights_to_bf16, dim3(blocks(np)), dim3(256), 0, s, param_map(a, 32), a->p, a->wb, a->wt);
   PO_HIP(hipGetLastError());
   PO_HIP(hipStreamSynchronize(s));
   return PO_OK;
@@ -448,8 +835,10 @@ po_status po_mlp_set_params(struct po_mlp* a, const float* d_params, void* strea
   PO_HIP(hipMemcpyAsync(a->p, d_params, sizeof(float) * a->n_params, hipMemcpyDeviceToDevice, s));
   PO_HIP(hipMemsetAsync(a->m, 0, sizeof(float) * a->n_params, s));
   PO_HIP(hipMemsetAsync(a->v, 0, sizeof(float) * a->n_params, s));
-  a->t = 0;
-  hipLaunchKernelGGL(k_weights_to_bf16, dim3(blocks(a->n_params)), dim3(256), 0, s, a->p, a->n_params, a->wb);
+  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(1), 0, s, a->ctr, 1);
+  PO_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_weights_to_bf16, dim3(blocks(a->n_params)), dim3(256), 0, s, param_map(a, 32), a->p, a->wb,
+                     a->wt);
   PO_HIP(hipGetLastError());
   return PO_OK;
 }
@@ -457,7 +846,7 @@ po_status po_mlp_set_params(struct po_mlp* a, const float* d_params, void* strea
 po_status po_mlp_forward(struct po_mlp* a, const double* d_x, int32_t batch, float* d_y, void* stream) {
   if (!a) return set_error(PO_ERR_INVALID, "network is NULL");
   PO_TRY(check_batch(a, batch));
-  PO_TRY(check_device_range(d_x, sizeof(double) * size_t(batch) * a->n_in, 8, "d_x"));
+  PO_TRY(check_device_range(d_x, sizeof(double) * size_t(batch) * a->n_in, 16, "d_x"));
   PO_TRY(check_device_range(d_y, sizeof(float) * batch, 4, "d_y"));
   return forward_impl(a, d_x, batch, d_y, static_cast<hipStream_t>(stream));
 }
@@ -466,12 +855,14 @@ po_status po_mlp_loss_grad(struct po_mlp* a, const double* d_x, const float* d_t
                            float* d_grad, void* stream) {
   if (!a) return set_error(PO_ERR_INVALID, "network is NULL");
   PO_TRY(check_batch(a, batch));
-  PO_TRY(check_device_range(d_x, sizeof(double) * size_t(batch) * a->n_in, 8, "d_x"));
+  PO_TRY(check_device_range(d_x, sizeof(double) * size_t(batch) * a->n_in, 16, "d_x"));
   PO_TRY(check_device_range(d_target, sizeof(float) * batch, 4, "d_target"));
   if (d_loss) PO_TRY(check_device_range(d_loss, sizeof(float), 4, "d_loss"));
   if (d_grad) PO_TRY(check_device_range(d_grad, sizeof(float) * a->n_params, 4, "d_grad"));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  PO_TRY(grad_impl(a, d_x, d_target, batch, d_loss, s));
+  RowMap rows{nullptr, nullptr, batch, batch};
+  PO_TRY(grad_impl(a, d_x, rows, d_target, nullptr, 0.0, 1.0, batch, s));
+  PO_TRY(adam_launch(a, batch, nullptr, a->g, -1.0f, d_loss, 0, s));  // assemble only
   if (d_grad) PO_HIP(hipMemcpyAsync(d_grad, a->g, sizeof(float) * a->n_params, hipMemcpyDeviceToDevice, s));
   return PO_OK;
 }
@@ -480,13 +871,39 @@ po_status po_mlp_adam_step(struct po_mlp* a, const float* d_grad, float lr, void
   if (!a) return set_error(PO_ERR_INVALID, "network is NULL");
   if (!(lr >= 0.0f) || !std::isfinite(lr)) return set_error(PO_ERR_INVALID, "lr must be finite and >= 0");
   if (d_grad) PO_TRY(check_device_range(d_grad, sizeof(float) * a->n_params, 4, "d_grad"));
-  return adam_impl(a, d_grad ? d_grad : a->g, lr, static_cast<hipStream_t>(stream));
+  return adam_launch(a, 32, d_grad ? d_grad : a->g, nullptr, lr, nullptr, 0, static_cast<hipStream_t>(stream));
 }
 
 po_status po_mlp_train_step(struct po_mlp* a, const double* d_x, const float* d_target, int32_t batch, float lr,
                             float* d_loss, void* stream) {
-  PO_TRY(po_mlp_loss_grad(a, d_x, d_target, batch, d_loss, nullptr, stream));
-  return po_mlp_adam_step(a, nullptr, lr, stream);
+  if (!a) return set_error(PO_ERR_INVALID, "network is NULL");
+  PO_TRY(check_batch(a, batch));
+  if (!(lr >= 0.0f) || !std::isfinite(lr)) return set_error(PO_ERR_INVALID, "lr must be finite and >= 0");
+  PO_TRY(check_device_range(d_x, sizeof(double) * size_t(batch) * a->n_in, 16, "d_x"));
+  PO_TRY(check_device_range(d_target, sizeof(float) * batch, 4, "d_target"));
+  if (d_loss) PO_TRY(check_device_range(d_loss, sizeof(float), 4, "d_loss"));
+  return train_replay(a, d_x, d_target, nullptr, nullptr, batch, 0.0, 1.0, batch, lr, d_loss, 1,
+                      static_cast<hipStream_t>(stream));
+}
+
+po_status po_mlp_train_indexed(struct po_mlp* a, const double* d_X, const double* d_J, int32_t n_rows,
+                               const int32_t* d_idx, int32_t steps, int32_t batch, double mean, double inv_std,
+                               float lr, float* d_losses, void* stream) {
+  if (!a) return set_error(PO_ERR_INVALID, "network is NULL");
+  PO_TRY(check_batch(a, batch));
+  if (n_rows < 1) return set_error(PO_ERR_INVALID, "n_rows must be >= 1");
+  if (steps < 0) return set_error(PO_ERR_INVALID, "steps must be >= 0");
+  if (!(lr >= 0.0f) || !std::isfinite(lr)) return set_error(PO_ERR_INVALID, "lr must be finite and >= 0");
+  if (!std::isfinite(mean) || !std::isfinite(inv_std)) return set_error(PO_ERR_INVALID, "mean and inv_std must be finite");
+  PO_TRY(check_device_range(d_X, sizeof(double) * size_t(n_rows) * a->n_in, 16, "d_X"));
+  PO_TRY(check_device_range(d_J, sizeof(double) * size_t(n_rows), 8, "d_J"));
+  if (steps == 0) return PO_OK;
+  PO_TRY(check_device_range(d_idx, sizeof(int32_t) * size_t(steps) * batch, 4, "d_idx"));
+  if (d_losses) PO_TRY(check_device_range(d_losses, sizeof(float) * size_t(steps), 4, "d_losses"));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(1), 0, s, a->ctr, 0);
+  PO_HIP(hipGetLastError());
+  return train_replay(a, d_X, nullptr, d_J, d_idx, n_rows, mean, inv_std, batch, lr, d_losses, steps, s);
 }
 
 void po_mlp_destroy(struct po_mlp* a) {

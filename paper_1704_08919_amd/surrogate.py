@@ -71,35 +71,26 @@ def log10_stats(J_host):
 def train(net, X, J, n, epochs=1, batch=1024, lr=1e-3, seed=0, stats=None, max_steps=None):
     """Minibatch Adam on (X[:n], standardised log10 J[:n]) for `epochs` passes over a fresh
     permutation each (or at most max_steps minibatches); returns (mean, std, mean loss of the
-    last pass)."""
+    last pass).  The minibatch indices of all steps are uploaded once and the steps run as
+    replays of the network's captured training step (po_mlp_train_indexed)."""
     mean, std = stats if stats is not None else log10_stats(J[:n, 0].cpu().numpy())
     rng = np.random.default_rng(seed)
     batch = min(batch, (n // 32) * 32)
     if batch < 32:
         raise ValueError("need at least 32 samples")
-    xb = torch.empty((batch, X.shape[1]), dtype=torch.float64, device="cuda")
-    jb = torch.empty((batch, 1), dtype=torch.float64, device="cuda")
-    tb = torch.empty(batch, dtype=torch.float32, device="cuda")
-    loss = torch.empty(1, dtype=torch.float32, device="cuda")
-    losses = torch.zeros(max(1, n // batch), dtype=torch.float32, device="cuda")
-    last, steps = float("nan"), 0
+    per_epoch = n // batch
+    idx = []
     for _ in range(epochs):
-        perm = rng.permutation(n).astype(np.int32)
-        cnt = 0
-        for s in range(0, n - batch + 1, batch):
-            if max_steps is not None and steps >= max_steps:
-                break
-            idx = torch.as_tensor(perm[s:s + batch], device="cuda")
-            api.po_gather_rows(X, idx, batch, xb)
-            api.po_gather_rows(J, idx, batch, jb)
-            api.po_log10_standardize(jb.view(-1), mean, 1.0 / std, out=tb)
-            net.train_step(xb, tb, lr=lr, loss=losses[cnt:cnt + 1])
-            cnt += 1
-            steps += 1
-        if cnt:
-            last = float(losses[:cnt].mean().item())
-        if max_steps is not None and steps >= max_steps:
+        idx.append(rng.permutation(n).astype(np.int32)[:per_epoch * batch])
+        if max_steps is not None and len(idx) * per_epoch >= max_steps:
             break
+    idx = np.concatenate(idx)
+    steps = len(idx) // batch if max_steps is None else min(len(idx) // batch, max_steps)
+    idx_d = torch.as_tensor(idx[:steps * batch], device="cuda")
+    losses = torch.zeros(max(steps, 1), dtype=torch.float32, device="cuda")
+    net.train_indexed(X, J.view(-1), idx_d, steps, batch, mean, 1.0 / std, lr=lr, losses=losses)
+    tail = losses[max(0, steps - per_epoch):steps]
+    last = float(tail.mean().item()) if steps else float("nan")
     return mean, std, last
 
 
@@ -140,24 +131,48 @@ def _best(fit):
 
 def run_de(spec, grid, pop=512, generations=200, seed=0, mode="surrogate", top=0.1, retrain_every=20,
            epochs_initial=60, epochs_retrain=15, retrain_steps=150, width=256, depth=3, time_limit=None,
-           target=None, F=0.8, CR=0.9, plan_config=None, progress_every=0):
+           target=None, F=0.8, CR=0.9, plan_config=None, progress_every=0, resume=None, time_budget=None,
+           record=None):
     """One DE run.  mode: "plain" (every trial evaluated), "surrogate" (network screening) or
     "random" (random screening, the ablation).  Stops after `generations`, at `time_limit`
     seconds, or once the best plain-evaluated J reaches `target`.  Returns a dict with the
     best-so-far history (seconds, plain evaluations, J).  progress_every > 0 prints the
-    best-so-far to stderr every that many generations."""
+    best-so-far to stderr every that many generations.
+
+    Plain runs can be split over processes: `resume` is the state a previous call returned
+    (keys pop, fit, generation, evals, history, wall_s); the run continues at that generation with
+    the same Philox stream, and its clock continues from wall_s (only the evaluation and DE work
+    of each process is counted, not its start-up).  `time_budget` stops this process after that
+    many seconds of its own work.  `record` (a list) receives (generation, trials, trial J) of
+    every generation, host arrays."""
     n_s = spec["n_s"]
     D = 4 * n_s
     k = pop if mode == "plain" else int(math.ceil(top * pop))
+    if resume is not None and mode != "plain":
+        raise ValueError("only plain runs resume")
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    X0 = torch.as_tensor(W.draw_coeff(seed, pop, n_s).reshape(pop, D), dtype=torch.float64, device="cuda")
     ev_pop = Evaluator(spec, grid, pop, plan_config)
     ev_k = ev_pop if k == pop else Evaluator(spec, grid, k, plan_config)
-    popu = X0.clone()
-    fit = ev_pop(popu).clone()
-    evals = pop
     prm = api.de_params(pop, D, n_s, F=F, CR=CR, seed=seed + 1)
+    if resume is None:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t_prev = 0.0
+        X0 = torch.as_tensor(W.draw_coeff(seed, pop, n_s).reshape(pop, D), dtype=torch.float64, device="cuda")
+        popu = X0.clone()
+        fit = ev_pop(popu).clone()
+        evals = pop
+        g_start = 0
+        hist = None
+    else:
+        popu = torch.as_tensor(np.asarray(resume["pop"]), dtype=torch.float64, device="cuda").reshape(pop, D).clone()
+        fit = torch.as_tensor(np.asarray(resume["fit"]), dtype=torch.float64, device="cuda").reshape(pop).clone()
+        evals = int(resume["evals"])
+        g_start = int(resume["generation"])
+        hist = [tuple(h) for h in np.asarray(resume["history"]).tolist()]
+        t_prev = float(resume["wall_s"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
     trial = torch.empty_like(popu)
     tfit = torch.empty_like(fit)
     net, archive, stats = None, None, None
@@ -169,13 +184,21 @@ def run_de(spec, grid, pop=512, generations=200, seed=0, mode="surrogate", top=0
         net = api.MLP(D, width, depth, max_batch=max(1024, ((pop + 31) // 32) * 32), seed=seed + 2)
         stats = train(net, archive.X, archive.J, archive.n, epochs_initial, seed=seed)[:2]
     sel = torch.empty((k, D), dtype=torch.float64, device="cuda")
-    hist = [(time.perf_counter() - t0, evals, _best(fit))]
+
+    def now():
+        return t_prev + time.perf_counter() - t0
+
+    if hist is None:
+        best0 = _best(fit)  # waits for the initial evaluation before the clock is read
+        hist = [(now(), evals, best0)]
     train_s = 0.0
-    g = 0
-    for g in range(generations):
+    g = g_start - 1
+    for g in range(g_start, generations):
         api.po_de_propose(prm, g, popu, trial)
         if mode == "plain":
             tfit.copy_(ev_pop(trial))
+            if record is not None:
+                record.append((g, trial.cpu().numpy(), tfit.cpu().numpy()))
             api.po_de_select(prm, popu, fit, trial, tfit)
         else:
             if mode == "surrogate":
@@ -197,7 +220,7 @@ def run_de(spec, grid, pop=512, generations=200, seed=0, mode="surrogate", top=0
                     train_s += time.perf_counter() - ts
         evals += k
         best = _best(fit)
-        hist.append((time.perf_counter() - t0, evals, best))
+        hist.append((now(), evals, best))
         if progress_every and (g + 1) % progress_every == 0:
             print(f"{mode} DE generation {g + 1}: {hist[-1][0]:.1f} s, {evals} plain evaluations, best J {best:.6e}",
                   file=sys.stderr, flush=True)
@@ -205,9 +228,11 @@ def run_de(spec, grid, pop=512, generations=200, seed=0, mode="surrogate", top=0
             break
         if time_limit is not None and hist[-1][0] >= time_limit:
             break
+        if time_budget is not None and time.perf_counter() - t0 >= time_budget:
+            break
     torch.cuda.synchronize()
     out = {"mode": mode, "pop": pop, "evaluated_per_generation": k, "generations": g + 1,
-           "wall_s": time.perf_counter() - t0, "plain_evaluations": evals, "best_J": _best(fit),
+           "wall_s": now(), "plain_evaluations": evals, "best_J": _best(fit),
            "history": hist, "train_s": train_s, "final_pop": popu.cpu().numpy(), "final_fit": fit.cpu().numpy()}
     for e in {id(ev_pop): ev_pop, id(ev_k): ev_k}.values():
         e.close()

@@ -121,6 +121,12 @@ def test_solver_entry_points_validate_on_host(lib):
     assert lib.po_qke_modes(1, _specs(), _grid1(), None, None, None, 0, None, None, None) == _lib.PO_ERR_INVALID
     assert lib.po_evolve_modes_m4(1, _specs(), _grid1(), None, None, None, None, None) == _lib.PO_ERR_INVALID
     assert lib.po_evolve_modes_m4(0, _specs(), _grid1(), None, None, None, None, None) == _lib.PO_ERR_INVALID
+    assert lib.po_probe_fp64_fma(2, 4, 16, None, None, None) == _lib.PO_ERR_INVALID
+    assert lib.po_probe_fp64_fma(4, 3, 16, None, None, None) == _lib.PO_ERR_INVALID
+    assert lib.po_probe_fp64_fma(4, 4, 0, None, None, None) == _lib.PO_ERR_INVALID
+    for order in (2, 3, 4):
+        assert lib.po_evolve_modes_split(1, _specs(), _grid1(), order, None, None, None, None,
+                                         None) == _lib.PO_ERR_INVALID
 
 
 @pytest.mark.parametrize("bad", [dict(islands=0), dict(islands=65), dict(pop=30, islands=4), dict(pop=12, islands=4),

@@ -1,5 +1,6 @@
-"""GPU parity of the field sampler, the kinetic-equation solver (Sec. II B) and the fourth-order
-Magnus step against the CPU oracle, through the C ABI.
+"""GPU parity of the field sampler, the kinetic-equation solver (Sec. II B), the fourth-order
+Magnus step and the split-operator steps (Strang and its fourth-order composition) against the CPU
+oracle, through the C ABI.
 
 Tolerances: samples |x_gpu - x_ref| <= 1e-12 max|x_ref| (E, A) and 1e-11 max|x_ref| (dE/dt).
 Dirac and Magnus steps: per mode the bound of the Dirac path, |f_gpu - f_ref| <= 1e-9 f_ref +
@@ -170,6 +171,41 @@ def test_magnus4_matches_oracle(orc, case):
     assert host(J2)[0] == J[0]
 
 
+def _split_tables(orc, spec, coeff, order):
+    if order == 2:
+        A, _, edge, _ = orc.synth(spec, coeff)
+        return A, edge
+    _, _, At = orc.field_samples(spec, coeff, api.SPLIT4_OFFSETS)
+    _, _, edge, _ = orc.synth(spec, coeff)
+    return At.reshape(-1, 3, 2), edge
+
+
+@pytest.mark.parametrize("order", [2, 4])
+@pytest.mark.parametrize("case", ["tan_series", "angle_halving", "ragged_grid", "zero_field"])
+def test_split_matches_oracle(orc, order, case):
+    w = W.single_pulse(0)
+    spec, coeff, grid = dict(w["specs"][0], nt=1024), w["coeff"][0], W.sheet_grid(12, 12, 1.5)
+    if case == "angle_halving":
+        spec = dict(spec, nt=96)  # |q| up to ~8: the cos/sin path with halvings
+    elif case == "ragged_grid":
+        spec = dict(spec, nt=700)
+        grid = W.grid((7, 5, 3), (-1.3, -0.9, -0.7), (1.1, 1.4, 0.8))
+    say(f"split order {order} case {case}")
+    At, edge = _split_tables(orc, spec, coeff, order)
+    if case == "zero_field":  # the constant-field splitting error, pinned in closed form on the CPU
+        grid = W.grid((7, 5, 3), (-1.3, -0.9, -0.7), (1.1, 1.4, 0.8))
+        At, edge = np.zeros_like(At) + 0.1, np.zeros_like(edge) + 0.1
+    f, J = api.evolve_split([spec], [grid], order, dev(At), dev(edge))
+    f, J = host(f), host(J)
+    p, _ = orc.grid_points(grid)
+    fr = orc.evolve_split_points(At, edge, spec["T"] / spec["nt"], p, order=order)
+    assert_modes(f, fr, spec["nt"], f"split{order} {case}")
+    assert_J(J[0], orc.pair_yield(grid, fr), f"split{order} {case}")
+    J2 = torch.empty(1, dtype=torch.float64, device="cuda")
+    api.po_pair_yield([grid], dev(f), J2)
+    assert host(J2)[0] == J[0]
+
+
 def test_three_solvers_agree_as_dt_shrinks():
     # Dirac (2nd order), Magnus (4th order) and the kinetic equation converge to one f; a field
     # along x, where the kinetic equation converges at its fourth order (no R term)
@@ -227,9 +263,39 @@ def test_circular_pulse_full_size_sampled(orc):
     iq = stable[np.linspace(0, stable.size - 1, 6).astype(int)]
     fqr, fm = orc.qke_tabulated(Er, Edr, Aqr, spec["T"] / spec["nt"], p_all[iq], precision="q", with_fmax=True)
     assert_qke(host(fq)[iq], fqr, fm, spec["nt"], "circular qke sampled")
+    # split-operator steps, second and fourth order
+    fs, Js = {}, {}
+    for order in (2, 4):
+        if order == 2:
+            At, edge_s, Atr, edge_sr = A, edge, Ar, edge_r
+        else:
+            _, _, At, edge_s, _ = api.field_samples(s, coeff, api.SPLIT4_OFFSETS)
+            Atr, edge_sr = _split_tables(orc, spec, c0, 4)
+        fs[order], Js[order] = api.evolve_split(s, [grid], order, At, edge_s)
+        assert_modes(host(fs[order])[idx], orc.evolve_split_points(Atr, edge_sr, spec["T"] / spec["nt"], p, order=order),
+                     spec["nt"], f"circular split{order} sampled")
     # every J is the exact sum of the kernel's own f
-    for f, J, name in ((f2, J2, "dirac2"), (f4, J4, "magnus4")):
+    for f, J, name in ((f2, J2, "dirac2"), (f4, J4, "magnus4"), (fs[2], Js[2], "split2"), (fs[4], Js[4], "split4")):
         fh = host(f)
         assert np.all(np.isfinite(fh)) and np.all(fh >= 0) and np.all(fh <= 2 + 1e-12)
         Jr = math.fsum(fh) * ((6.0 / 512) ** 2)
         assert abs(host(J)[0] - Jr) <= 1e-12 * Jr, name
+
+
+def test_fp64_fma_probe_rate():
+    # the issue-rate probe runs at every occupancy it supports and reports a rate within the
+    # device's FP64 peak (78.6 TFLOP/s, with 5% for clock and timer slack)
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    sink = torch.empty(n_cu * 8 * 256, dtype=torch.float64, device="cuda")
+    for w in (3, 4, 8):
+        api.po_probe_fp64_fma(w, 4, 16, sink)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        flop = api.po_probe_fp64_fma(w, 4, 1024, sink)
+        e1.record()
+        torch.cuda.synchronize()
+        tf = flop / (e0.elapsed_time(e1) * 1e-3) / 1e12
+        say(f"fp64 fma probe: {w} waves/SIMD, 4 chains: {tf:.1f} TFLOP/s")
+        assert 10.0 < tf < 1.05 * 78.6
+        v = host(sink[:n_cu * w * 256])
+        assert np.all(np.isfinite(v)) and np.all((v > 3.9) & (v < 5.1))
