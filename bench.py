@@ -295,9 +295,12 @@ def surrogate_de_full(api, W, S, torch, phase, generations, seed=0, target_J=Non
         out.update({k: r[k] for k in ("generations", "wall_s", "plain_evaluations", "best_J", "train_s")})
         out.update({"target_J": target_J, "plain_wall_s": plain_wall_s, "time_to_target_s": tt,
                     "speedup_vs_plain_wall": plain_wall_s / tt if tt else None})
-        for key in ("rank_corr", "train_log"):
-            if key in r:
-                out[key] = r[key]
+        rc = r["rank_corr"]
+        if rc:
+            out["rank_corr_evaluated_trials"] = {"median": float(sorted(rc)[len(rc) // 2]),
+                                                 "first_20_mean": sum(rc[:20]) / len(rc[:20]),
+                                                 "last_20_mean": sum(rc[-20:]) / len(rc[-20:]),
+                                                 "per_generation": [round(v, 3) for v in rc]}
         hist = r["history"]
     out["history_every_10"] = [list(h) for h in hist[::10]] + [list(hist[-1])]
     return out

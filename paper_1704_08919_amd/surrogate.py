@@ -184,6 +184,7 @@ def run_de(spec, grid, pop=512, generations=200, seed=0, mode="surrogate", top=0
         net = api.MLP(D, width, depth, max_batch=max(1024, ((pop + 31) // 32) * 32), seed=seed + 2)
         stats = train(net, archive.X, archive.J, archive.n, epochs_initial, seed=seed)[:2]
     sel = torch.empty((k, D), dtype=torch.float64, device="cuda")
+    rank_corr = []
 
     def now():
         return t_prev + time.perf_counter() - t0
@@ -212,6 +213,10 @@ def run_de(spec, grid, pop=512, generations=200, seed=0, mode="surrogate", top=0
             api.po_scatter_values(Jsel, idx, k, tfit, fill=float("-inf"))
             api.po_de_select(prm, popu, fit, trial, tfit, mask)
             if mode == "surrogate":
+                # rank correlation of the network's scores with the plain J of the evaluated trials
+                sc = score[idx[:k].long()].cpu().numpy()
+                jt = np.log10(np.maximum(Jsel.cpu().numpy(), 1e-300))
+                rank_corr.append(float(np.corrcoef(np.argsort(np.argsort(sc)), np.argsort(np.argsort(jt)))[0, 1]))
                 archive.add(sel, Jsel)
                 if (g + 1) % retrain_every == 0:
                     ts = time.perf_counter()
@@ -233,7 +238,8 @@ def run_de(spec, grid, pop=512, generations=200, seed=0, mode="surrogate", top=0
     torch.cuda.synchronize()
     out = {"mode": mode, "pop": pop, "evaluated_per_generation": k, "generations": g + 1,
            "wall_s": now(), "plain_evaluations": evals, "best_J": _best(fit),
-           "history": hist, "train_s": train_s, "final_pop": popu.cpu().numpy(), "final_fit": fit.cpu().numpy()}
+           "history": hist, "train_s": train_s, "final_pop": popu.cpu().numpy(), "final_fit": fit.cpu().numpy(),
+           "rank_corr": rank_corr}
     for e in {id(ev_pop): ev_pop, id(ev_k): ev_k}.values():
         e.close()
     if net is not None:
