@@ -153,6 +153,24 @@ po_status po_evaluate(int32_t n_pulses, const po_pulse_spec* specs, const po_gri
                       double* d_f, double* d_J, const struct po_plan* plan, void* stream);
 
 /* ---------------------------------------------------------------------------------------
+ * po_evaluate_noalloc -- po_evaluate (plan NULL) for callers that cannot allocate: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation.  Same kernels, same
+ * results bit for bit; it calls no hipMalloc, hipFree or other allocating routine.  Its scratch
+ * (pulse descriptors, spectra, normalisation partials, per-64-mode partial sums and per-chunk
+ * table ranges) lives in one file-scope device array of 64 MiB that each device holds from
+ * the library's first use there until the process ends; the caller passes inputs and outputs as
+ * for po_evaluate.  Limits: at most 4096 pulses, and a batch whose scratch (about
+ * 8 (sum 4 lines + pulses (statistic blocks + 1) + sum modes / 64 + 4 sum ceil(nt/256)) bytes
+ * plus descriptors, each part rounded up to 256 bytes) exceeds 64 MiB is rejected with
+ * PO_ERR_INVALID before anything is enqueued.  Every call on a device shares that device's
+ * array: calls that overlap on one device (on different streams, or from several threads) race
+ * and must not be made; calls on one stream are ordered.  Kernel timers do not bracket it.
+ * --------------------------------------------------------------------------------------- */
+po_status po_evaluate_noalloc(int32_t n_pulses, const po_pulse_spec* specs, const po_grid* grids,
+                              const double* d_coeff, double* d_A, double* d_A_edge, double* d_scale,
+                              double* d_f, double* d_J, void* stream);
+
+/* ---------------------------------------------------------------------------------------
  * po_field_samples -- scaled E, dE/dt and A of synthesised pulses at chosen points inside
  * every step (Sec. III, Eq. field, Eq. hann and Eq. vector_potential, with the scale of the
  * spec's normalisation as in po_pulse_synth).  Row r of pulse i is the time

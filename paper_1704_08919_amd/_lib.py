@@ -73,6 +73,8 @@ SIGNATURES = {
                            ctypes.c_int),
     "po_evolve_modes_split": ([_I32, ctypes.POINTER(PulseSpec), ctypes.POINTER(Grid), _I32, _P, _P, _P, _P, _P],
                               ctypes.c_int),
+    "po_evaluate_noalloc": ([_I32, ctypes.POINTER(PulseSpec), ctypes.POINTER(Grid), _P, _P, _P, _P, _P, _P, _P],
+                            ctypes.c_int),
     "po_evaluate": ([_I32, ctypes.POINTER(PulseSpec), ctypes.POINTER(Grid), _P, _P, _P, _P, _P, _P, _P, _P],
                     ctypes.c_int),
     "po_de_propose": ([ctypes.POINTER(DEParams), _I64, _P, _P, _P, _P], ctypes.c_int),

@@ -132,6 +132,12 @@ def po_evaluate(specs, grids, coeff, A, A_edge, J, scale=None, f=None, stream=No
                              None, _stream(stream)))
 
 
+def po_evaluate_noalloc(specs, grids, coeff, A, A_edge, J, scale=None, f=None, stream=None):
+    sp, gr = _spec_array(specs), _grid_array(grids)
+    check(load().po_evaluate_noalloc(len(specs), sp, gr, _ptr(coeff), _ptr(A), _ptr(A_edge), _ptr(scale), _ptr(f),
+                                     _ptr(J), _stream(stream)))
+
+
 def po_de_propose(params, generation, pop, trial, idx=None, stream=None):
     check(load().po_de_propose(ctypes.byref(params), int(generation), _ptr(pop), _ptr(trial),
                                _ptr(idx, torch.int32), _stream(stream)))

@@ -329,6 +329,39 @@ void timer_stop(hipStream_t s, hipEvent_t e0) {
   g_timer_events.emplace_back(e0, e1);
 }
 
+// ---------------------------------------------------------------------------------------------
+// Allocation-free evaluation: every scratch buffer of po_evaluate_noalloc lives in this file-scope
+// device array (each device holds its own copy until the process ends).  In host code `scratch`
+// is only a stand-in for the symbol: its device address comes from hipGetSymbolAddress, taken once
+// per device with that device current, and only that address is handed to kernels and copies.
+// ---------------------------------------------------------------------------------------------
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+constexpr int kNoAllocMaxPulses = 4096;
+constexpr int kNoAllocMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+std::mutex g_noalloc_mu;                               // guards the two arrays below
+void* g_scratch_dev[kNoAllocMaxDevices] = {};          // device address of `scratch`, per device
+PulseDev g_noalloc_desc[kNoAllocMaxPulses];            // host staging of the pulse descriptors
+
+// Device address of `scratch` on the current device (looked up on the first call there).
+po_status noalloc_scratch(void** out) {
+  int dev = -1;
+  PO_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoAllocMaxDevices) return set_error(PO_ERR_UNSUPPORTED, "device %d out of range", dev);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return device_error(e == hipSuccess ? hipErrorInvalidSymbol : e, "hipGetSymbolAddress");
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return PO_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
 }  // namespace po
 
 using namespace po;
@@ -641,6 +674,46 @@ po_status po_evaluate(int32_t n, const po_pulse_spec* specs, const po_grid* grid
     return PO_OK;
   }
   return evolve_impl(b, d_desc, d_A, d_A_edge, d_f, d_J, s);
+}
+
+po_status po_evaluate_noalloc(int32_t n, const po_pulse_spec* specs, const po_grid* grids, const double* d_coeff,
+                              double* d_A, double* d_A_edge, double* d_scale, double* d_f, double* d_J, void* stream) {
+  if (n < 1) return set_error(PO_ERR_INVALID, "n_pulses must be >= 1");
+  if (n > kNoAllocMaxPulses) return set_error(PO_ERR_INVALID, "n_pulses must be <= %d", kNoAllocMaxPulses);
+  PO_TRY(check_specs(n, specs));
+  PO_TRY(check_grids(n, grids));
+  if (!d_f && !d_J) return set_error(PO_ERR_INVALID, "at least one of d_f, d_J must be non-NULL");
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  Batch b;
+  PO_TRY(build_batch(n, specs, grids, g_noalloc_desc, &b));
+  const EvalSizes z = eval_sizes(n, b);
+  const size_t o_desc = 0;
+  const size_t o_spec = o_desc + align256(sizeof(PulseDev) * size_t(n));
+  const size_t o_part = o_spec + align256(sizeof(double) * z.spec);
+  const size_t o_scl = o_part + align256(sizeof(double) * z.part);
+  const size_t o_units = o_scl + align256(sizeof(double) * z.scl);
+  const size_t o_ranges = o_units + align256(sizeof(double) * z.units);
+  const size_t need = o_ranges + align256(sizeof(double) * z.ranges);
+  if (need > kNoAllocScratchBytes)
+    return set_error(PO_ERR_INVALID, "batch needs %zu bytes of scratch, the allocation-free path holds %zu", need,
+                     kNoAllocScratchBytes);
+  PO_TRY(check_device_range(d_coeff, sizeof(double) * b.total_coeff, 8, "d_coeff"));
+  PO_TRY(check_device_range(d_A, sizeof(double) * 2 * b.total_rows, 8, "d_A"));
+  PO_TRY(check_device_range(d_A_edge, sizeof(double) * 4 * n, 8, "d_A_edge"));
+  if (d_scale) PO_TRY(check_device_range(d_scale, sizeof(double) * n, 8, "d_scale"));
+  if (d_f) PO_TRY(check_device_range(d_f, sizeof(double) * b.total_modes, 8, "d_f"));
+  if (d_J) PO_TRY(check_device_range(d_J, sizeof(double) * n, 8, "d_J"));
+  void* base = nullptr;
+  PO_TRY(noalloc_scratch(&base));
+  unsigned char* sc = static_cast<unsigned char*>(base);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  PulseDev* d_desc = reinterpret_cast<PulseDev*>(sc + o_desc);
+  PO_HIP(hipMemcpyAsync(d_desc, g_noalloc_desc, sizeof(PulseDev) * size_t(n), hipMemcpyHostToDevice, s));
+  PO_TRY(synth_into(specs, d_coeff, d_A, nullptr, d_A_edge, d_scale, s, b, d_desc,
+                    reinterpret_cast<double*>(sc + o_spec), reinterpret_cast<double*>(sc + o_part),
+                    reinterpret_cast<double*>(sc + o_scl)));
+  return evolve_into(b, d_desc, d_A, d_A_edge, d_f, d_J, s, reinterpret_cast<double*>(sc + o_units),
+                     reinterpret_cast<double*>(sc + o_ranges), false);
 }
 
 po_status po_timer_enable(int on) {
