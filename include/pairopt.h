@@ -248,7 +248,11 @@ po_status po_evolve_modes_split(int32_t n_pulses, const po_pulse_spec* specs, co
  *  d_J      out [n_pulses] or NULL.
  *  d_gA     out [sum nt][2]: dJ/dA at every step midpoint.
  *  d_gedge  out [n_pulses][2][2] or NULL: dJ/dA(t_i), dJ/dA(t_f) (initial state, projection).
- * Work buffers of (modes / 256) x nt x 16 bytes per pulse come from the stream-ordered pool.
+ * Work buffers of ceil(modes / 256) x nt x 16 bytes per pulse (the per-step partial sums of each
+ * 256-mode item, added in a fixed order by a second kernel) come from the stream-ordered pool: 64 MiB
+ * for a 64x64x16 pulse at nt = 16384, 1 GiB for a 128x128x32 pulse at nt = 32768.  A batch whose
+ * work buffers do not fit in device memory returns PO_ERR_NOMEM before the gradient kernels are
+ * enqueued; split it into several calls.
  *
  * po_synth_gradient -- chain rule through the synthesis (Sec. III) of po_pulse_synth:
  *  d_gA, d_gedge  as produced above (d_gedge may be NULL: no end-point terms).

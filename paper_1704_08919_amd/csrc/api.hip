@@ -270,9 +270,9 @@ po_status yield_grad_impl(const Batch& b, const std::vector<PulseDev>& h, const 
     tot += int64_t(h[i].nitems) * h[i].nt * 2;
   }
   Scratch sgoff, part, epart, units, sel, ged;
+  PO_TRY(part.alloc(sizeof(double) * size_t(tot), s));  // the large one first: fail before enqueueing work
   PO_TRY(sgoff.alloc(sizeof(int64_t) * goff.size(), s));
   PO_HIP(hipMemcpyAsync(sgoff.ptr, goff.data(), sizeof(int64_t) * goff.size(), hipMemcpyHostToDevice, s));
-  PO_TRY(part.alloc(sizeof(double) * size_t(tot), s));
   PO_TRY(epart.alloc(sizeof(double) * 4 * size_t(b.total_items), s));
   PO_TRY(units.alloc(sizeof(double) * size_t(b.total_units), s));
   PO_TRY(sel.alloc(sizeof(int2) * size_t(b.total_blocks), s));
