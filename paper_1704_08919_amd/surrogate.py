@@ -130,7 +130,7 @@ def _best(fit):
 
 
 def run_de(spec, grid, pop=512, generations=200, seed=0, mode="surrogate", top=0.1, retrain_every=20,
-           epochs_initial=60, epochs_retrain=15, retrain_steps=150, width=256, depth=3, time_limit=None,
+           train_steps=150, width=256, depth=3, time_limit=None,
            target=None, F=0.8, CR=0.9, plan_config=None, progress_every=0, resume=None, time_budget=None,
            record=None):
     """One DE run.  mode: "plain" (every trial evaluated), "surrogate" (network screening) or
@@ -138,6 +138,9 @@ def run_de(spec, grid, pop=512, generations=200, seed=0, mode="surrogate", top=0
     seconds, or once the best plain-evaluated J reaches `target`.  Returns a dict with the
     best-so-far history (seconds, plain evaluations, J).  progress_every > 0 prints the
     best-so-far to stderr every that many generations.
+
+    The network is trained for `train_steps` minibatch steps at the start and at every retraining,
+    whatever the archive's size (passes over fresh permutations of it).
 
     Plain runs can be split over processes: `resume` is the state a previous call returned
     (keys pop, fit, generation, evals, history, wall_s); the run continues at that generation with
@@ -182,7 +185,7 @@ def run_de(spec, grid, pop=512, generations=200, seed=0, mode="surrogate", top=0
         archive = Archive(pop + k * generations, D)
         archive.add(popu, fit)
         net = api.MLP(D, width, depth, max_batch=max(1024, ((pop + 31) // 32) * 32), seed=seed + 2)
-        stats = train(net, archive.X, archive.J, archive.n, epochs_initial, seed=seed)[:2]
+        stats = train(net, archive.X, archive.J, archive.n, epochs=10 ** 6, seed=seed, max_steps=train_steps)[:2]
     sel = torch.empty((k, D), dtype=torch.float64, device="cuda")
     rank_corr = []
 
@@ -220,8 +223,8 @@ def run_de(spec, grid, pop=512, generations=200, seed=0, mode="surrogate", top=0
                 archive.add(sel, Jsel)
                 if (g + 1) % retrain_every == 0:
                     ts = time.perf_counter()
-                    stats = train(net, archive.X, archive.J, archive.n, epochs_retrain, seed=seed + g,
-                                  max_steps=retrain_steps)[:2]
+                    stats = train(net, archive.X, archive.J, archive.n, epochs=10 ** 6, seed=seed + g,
+                                  max_steps=train_steps)[:2]
                     train_s += time.perf_counter() - ts
         evals += k
         best = _best(fit)

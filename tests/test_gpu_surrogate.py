@@ -79,7 +79,7 @@ def test_surrogate_de_accepts_only_plain_evaluated_fitness():
     out = {}
     for mode in ("plain", "surrogate", "random"):
         r = S.run_de(spec, grid, pop=64, generations=12, seed=3, mode=mode, top=0.1, retrain_every=5,
-                     epochs_initial=20, epochs_retrain=5, plan_config=dict(threads=256, modes_per_lane=1, persistent=1))
+                     train_steps=20, plan_config=dict(threads=256, modes_per_lane=1, persistent=1))
         out[mode] = r
         js = [h[2] for h in r["history"]]
         assert all(b >= a for a, b in zip(js, js[1:]))
