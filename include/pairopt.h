@@ -471,6 +471,23 @@ po_status po_log10_standardize(const double* d_J, int32_t n, double floor_value,
                                float* d_out, void* stream);
 
 /* ---------------------------------------------------------------------------------------
+ * po_set_check_finite -- optional check that results are finite (off by default).  While it is
+ * enabled, these calls count the non-finite entries of what they wrote, after their kernels:
+ *   po_pulse_synth    the A table (d_A);
+ *   po_evolve_modes   d_J, or d_f when d_J is NULL;
+ *   po_evaluate       the A table, then d_J (or d_f when d_J is NULL);
+ *   po_pair_yield     d_J;
+ *   po_de_generation  the trials' J (d_trial_fit; the selection has already run: a trial whose J
+ *                     is not finite never replaces its target).
+ * A nonzero count returns PO_ERR_NUMERIC, the count and the buffer named in po_last_error; the
+ * outputs are left as computed.  The check waits for the stream, so the calls become synchronous
+ * and must not be captured into a graph; it costs one pass over the checked values.  Other entry
+ * points (po_evaluate_noalloc included) are not checked.  The setting is process-wide; the call
+ * returns the previous one.
+ * --------------------------------------------------------------------------------------- */
+int32_t po_set_check_finite(int32_t enable);
+
+/* ---------------------------------------------------------------------------------------
  * Kernel timers (diagnostics, not part of the method).  While enabled, every po_evolve_modes /
  * po_evaluate / po_de_generation call records a pair of HIP events on its stream around the
  * launches of the per-mode evolution kernel.  po_timer_read waits for the recorded events,

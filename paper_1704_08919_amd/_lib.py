@@ -109,6 +109,7 @@ SIGNATURES = {
     "po_scatter_values": ([_P, _P, _I32, ctypes.c_double, _P, _I32, _P], ctypes.c_int),
     "po_probe_fp64_fma": ([_I32, _I32, _I64, _P, ctypes.POINTER(ctypes.c_double), _P], ctypes.c_int),
     "po_timer_enable": ([ctypes.c_int], ctypes.c_int),
+    "po_set_check_finite": ([_I32], ctypes.c_int32),
     "po_timer_read": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "po_timer_mode_steps": ([ctypes.POINTER(ctypes.c_uint64), _I32], ctypes.c_int),
 }

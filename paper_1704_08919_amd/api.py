@@ -221,6 +221,13 @@ class Plan:
             pass
 
 
+def po_set_check_finite(on=True):
+    """Enables (or disables) the library's check that results are finite; returns the previous
+    setting.  While enabled, the checked calls wait for their stream and raise POError
+    (PO_ERR_NUMERIC) when a result holds non-finite values."""
+    return bool(load().po_set_check_finite(1 if on else 0))
+
+
 def po_timer_enable(on=True):
     check(load().po_timer_enable(1 if on else 0))
 

@@ -1,5 +1,7 @@
 // C ABI of libpairopt.so: argument validation, per-pulse descriptors, scratch management and
 // the sequencing of the synthesis, evolution, reduction and differential-evolution kernels.
+#include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <mutex>
@@ -293,6 +295,50 @@ po_status check_differentiable(int32_t n, const po_pulse_spec* specs) {
   return PO_OK;
 }
 
+std::atomic<int32_t> g_check_finite{0};
+
+__global__ void k_zero_count(unsigned int* count) { *count = 0u; }
+
+// Adds the number of non-finite entries of v[0, n) to *count (grid-stride; one atomic per block).
+__global__ void __launch_bounds__(256) k_count_nonfinite(const double* __restrict__ v, int64_t n,
+                                                         unsigned int* __restrict__ count) {
+  __shared__ unsigned int part[256];
+  unsigned int c = 0;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
+    c += std::isfinite(v[i]) ? 0u : 1u;
+  part[threadIdx.x] = c;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (int(threadIdx.x) < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && part[0] != 0u) atomicAdd(count, part[0]);
+}
+
+// With the check enabled: counts the non-finite entries of d_v[0, n) on the stream, waits for it,
+// and returns PO_ERR_NUMERIC if there are any.
+po_status check_finite(const double* d_v, int64_t n, const char* what, hipStream_t s) {
+  if (!g_check_finite.load(std::memory_order_relaxed) || n <= 0) return PO_OK;
+  Scratch cnt;
+  PO_TRY(cnt.alloc(sizeof(unsigned int), s));
+  unsigned int* d_c = static_cast<unsigned int*>(cnt.ptr);
+  hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, d_c);
+  PO_HIP(hipGetLastError());
+  const int64_t blocks = std::min<int64_t>(1024, (n + 255) / 256);
+  hipLaunchKernelGGL(k_count_nonfinite, dim3(unsigned(blocks)), dim3(256), 0, s, d_v, n, d_c);
+  PO_HIP(hipGetLastError());
+  unsigned int h_c = 0;
+  PO_HIP(hipMemcpyAsync(&h_c, d_c, sizeof(h_c), hipMemcpyDeviceToHost, s));
+  PO_HIP(hipStreamSynchronize(s));
+  if (h_c != 0u) return set_error(PO_ERR_NUMERIC, "%u non-finite values in %s", h_c, what);
+  return PO_OK;
+}
+
+// The evolution's checked output: J, or f when J is not requested.
+po_status check_outputs(const Batch& b, const double* d_f, const double* d_J, hipStream_t s) {
+  return d_J ? check_finite(d_J, b.n_pulses, "d_J", s) : check_finite(d_f, b.total_modes, "d_f", s);
+}
+
 }  // namespace
 
 bool timer_start(hipStream_t s, hipEvent_t* e0) {
@@ -370,6 +416,8 @@ extern "C" {
 
 int po_abi_version(void) { return 1; }
 
+int32_t po_set_check_finite(int32_t enable) { return g_check_finite.exchange(enable ? 1 : 0); }
+
 const char* po_last_error(void) { return g_error.c_str(); }
 
 po_status po_pulse_synth(int32_t n, const po_pulse_spec* specs, const double* d_coeff, double* d_A, double* d_E,
@@ -387,7 +435,8 @@ po_status po_pulse_synth(int32_t n, const po_pulse_spec* specs, const double* d_
   hipStream_t s = static_cast<hipStream_t>(stream);
   Scratch desc;
   PO_TRY(upload(h, desc, s));
-  return synth_impl(n, specs, d_coeff, d_A, d_E, d_A_edge, d_scale, s, b, static_cast<PulseDev*>(desc.ptr));
+  PO_TRY(synth_impl(n, specs, d_coeff, d_A, d_E, d_A_edge, d_scale, s, b, static_cast<PulseDev*>(desc.ptr)));
+  return check_finite(d_A, 2 * b.total_rows, "d_A", s);
 }
 
 po_status po_evolve_modes(int32_t n, const po_pulse_spec* specs, const po_grid* grids, const double* d_A,
@@ -409,11 +458,12 @@ po_status po_evolve_modes(int32_t n, const po_pulse_spec* specs, const po_grid* 
     const bool timed = timer_start(s, &e0);
     PO_TRY(plan_evolve(plan, n, specs, grids, d_A, d_A_edge, d_f, d_J, s));
     if (timed) timer_stop(s, e0);
-    return PO_OK;
+    return check_outputs(b, d_f, d_J, s);
   }
   Scratch desc;
   PO_TRY(upload(h, desc, s));
-  return evolve_impl(b, static_cast<PulseDev*>(desc.ptr), d_A, d_A_edge, d_f, d_J, s);
+  PO_TRY(evolve_impl(b, static_cast<PulseDev*>(desc.ptr), d_A, d_A_edge, d_f, d_J, s));
+  return check_outputs(b, d_f, d_J, s);
 }
 
 po_status po_field_samples(int32_t n, const po_pulse_spec* specs, const double* d_coeff, int32_t n_sub,
@@ -642,7 +692,8 @@ po_status po_pair_yield(int32_t n, const po_grid* grids, const double* d_f, doub
   PO_TRY(units.alloc(sizeof(double) * size_t(b.total_units), s));
   const PulseDev* d_desc = static_cast<PulseDev*>(desc.ptr);
   PO_TRY(launch_unit_sums_from_f(b, d_desc, d_f, static_cast<double*>(units.ptr), s));
-  return launch_yield_from_units(b, d_desc, static_cast<double*>(units.ptr), d_J, s);
+  PO_TRY(launch_yield_from_units(b, d_desc, static_cast<double*>(units.ptr), d_J, s));
+  return check_finite(d_J, n, "d_J", s);
 }
 
 po_status po_evaluate(int32_t n, const po_pulse_spec* specs, const po_grid* grids, const double* d_coeff, double* d_A,
@@ -666,14 +717,16 @@ po_status po_evaluate(int32_t n, const po_pulse_spec* specs, const po_grid* grid
   PO_TRY(upload(h, desc, s));
   const PulseDev* d_desc = static_cast<PulseDev*>(desc.ptr);
   PO_TRY(synth_impl(n, specs, d_coeff, d_A, nullptr, d_A_edge, d_scale, s, b, d_desc));
+  PO_TRY(check_finite(d_A, 2 * b.total_rows, "d_A", s));
   if (plan) {
     hipEvent_t e0 = nullptr;
     const bool timed = timer_start(s, &e0);
     PO_TRY(plan_evolve(plan, n, specs, grids, d_A, d_A_edge, d_f, d_J, s));
     if (timed) timer_stop(s, e0);
-    return PO_OK;
+    return check_outputs(b, d_f, d_J, s);
   }
-  return evolve_impl(b, d_desc, d_A, d_A_edge, d_f, d_J, s);
+  PO_TRY(evolve_impl(b, d_desc, d_A, d_A_edge, d_f, d_J, s));
+  return check_outputs(b, d_f, d_J, s);
 }
 
 po_status po_evaluate_noalloc(int32_t n, const po_pulse_spec* specs, const po_grid* grids, const double* d_coeff,
@@ -827,7 +880,8 @@ po_status po_de_generation(const po_de_params* prm, int64_t generation, const po
   PO_TRY(launch_de_propose(*prm, generation, d_pop, d_trial, nullptr, s));
   PO_TRY(synth_impl(n, specs.data(), d_trial, d_A, nullptr, d_edge, nullptr, s, b, d_desc));
   PO_TRY(evolve_impl(b, d_desc, d_A, d_edge, nullptr, d_trial_fit, s));
-  return launch_de_select(*prm, d_pop, d_fit, d_trial, d_trial_fit, nullptr, s);
+  PO_TRY(launch_de_select(*prm, d_pop, d_fit, d_trial, d_trial_fit, nullptr, s));
+  return check_finite(d_trial_fit, n, "d_trial_fit", s);
 }
 
 static po_status check_jde(const po_jde_params* p) {

@@ -42,6 +42,18 @@ def test_abi_version(lib):
     assert lib.po_abi_version() == 1
 
 
+def test_check_finite_setting_returns_previous(lib):
+    # host-only switch: off by default, each call returns the setting it replaces
+    prev = lib.po_set_check_finite(1)
+    try:
+        assert prev == 0
+        assert lib.po_set_check_finite(1) == 1
+        assert lib.po_set_check_finite(0) == 1
+        assert lib.po_set_check_finite(0) == 0
+    finally:
+        lib.po_set_check_finite(0)
+
+
 def _specs(**kw):
     s = W.pulse_spec(n_s=4, order=4, T=400.0, nt=64)
     s.update(kw)

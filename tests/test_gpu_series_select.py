@@ -115,3 +115,41 @@ def test_non_finite_and_huge_tables_complete():
     assert J[0] == J0[0]
     assert not np.isfinite(J[1])
     assert not np.isfinite(J[2]) or abs(J[2] - J0[2]) > 1e-3 * abs(J0[2])
+
+
+def test_check_finite_reports_non_finite_results():
+    # with the finite check on, clean results pass through every checked entry point, and the
+    # infinite table entry of the test above (which the kernels complete) or a non-finite f makes
+    # the call return PO_ERR_NUMERIC; with the check off the same call returns normally
+    from paper_1704_08919_amd import _lib
+    spec, grid, seed = CASES["box"]
+    specs, grids = [spec] * 4, [grid] * 4
+    coeff = W.draw_coeff(seed, 4, spec["n_s"])
+    A, edge, _, _ = api.synth(specs, coeff)
+    prev = api.po_set_check_finite(True)
+    try:
+        A2, _, _, _ = api.synth(specs, coeff)
+        f, J = api.evolve(specs, grids, A, edge)
+        J2, _ = api.evaluate(specs, grids, coeff)
+        assert torch.equal(A, A2) and torch.equal(J, J2)
+        Jy = torch.empty_like(J)
+        api.po_pair_yield(grids, f, Jy)
+        prm = api.de_params(4, 4 * spec["n_s"], spec["n_s"], seed=seed)
+        pop = torch.as_tensor(coeff, dtype=torch.float64).reshape(4, -1).clone().cuda()
+        fit, trial, tfit = J.clone(), torch.empty_like(pop), torch.empty_like(J)
+        api.po_de_generation(prm, 0, spec, grid, pop, fit, trial, tfit)
+        assert torch.isfinite(tfit).all()
+        A[spec["nt"] + 5, 0] = float("inf")
+        with pytest.raises(_lib.POError, match=r"PO_ERR_NUMERIC.*non-finite values in d_J"):
+            api.evolve(specs, grids, A, edge, want_f=False)
+        with pytest.raises(_lib.POError, match=r"PO_ERR_NUMERIC.*non-finite values in d_f"):
+            api.evolve(specs, grids, A, edge, want_J=False)
+        f[3] = float("nan")
+        with pytest.raises(_lib.POError, match=r"PO_ERR_NUMERIC: 1 non-finite values in d_J"):
+            api.po_pair_yield(grids, f, Jy)
+    finally:
+        api.po_set_check_finite(prev)
+    _, Jbad = api.evolve(specs, grids, A, edge, want_f=False)
+    Jbad = Jbad.cpu().numpy()
+    say(f"check off: J with an infinite table entry in pulse 1 {Jbad}")
+    assert not np.isfinite(Jbad[1]) and np.all(np.isfinite(Jbad[[0, 2, 3]]))
