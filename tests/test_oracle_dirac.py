@@ -170,12 +170,13 @@ def test_kinetic_equation_linear_field(orc):
     spec["norm"] = W.NORM_NONE
     p = np.array([[0.1, 0.2, 0.0], [-0.5, 0.3, 0.4]])
     res = []
-    for nt in (8192, 16384):
+    for nt in (16384, 32768):
         A, E, edge, _ = orc.synth(dict(spec, nt=nt), coeff)
         res.append(orc.evolve_points(A, edge, spec["T"] / nt, p))
-    dirac = (4 * res[1] - res[0]) / 3
-    qke = orc.qke_points(spec, coeff, p, nt=32768, linear=True)
-    np.testing.assert_allclose(dirac, qke, rtol=2e-7)
+    dirac = (4 * res[1] - res[0]) / 3  # second-order step: Richardson limit
+    q = [orc.qke_points(spec, coeff, p, nt=nt, linear=True) for nt in (16384, 32768)]
+    qke = (16 * q[1] - q[0]) / 15  # RK4: Richardson limit
+    np.testing.assert_allclose(dirac, qke, rtol=1e-8)
 
 
 def _circular_tables(t, T, A0, Om):
@@ -204,8 +205,10 @@ def test_kinetic_equation_circular_field(orc):
         _, _, Ae = _circular_tables(np.array([-T / 2, T / 2]), T, A0, Om)
         res.append(orc.evolve_points(Am, Ae, dt, p))
     dirac = (4 * res[1] - res[0]) / 3
-    nq = 32768
-    th = -T / 2 + np.arange(2 * nq + 1) * (T / nq) / 2
-    E, Ed, A = _circular_tables(th, T, A0, Om)
-    qke = orc.qke_tabulated(E, Ed, A, T / nq, p)
-    np.testing.assert_allclose(dirac, qke, rtol=1e-7)
+    q = []
+    for nq in (16384, 32768):
+        th = -T / 2 + np.arange(2 * nq + 1) * (T / nq) / 2
+        E, Ed, A = _circular_tables(th, T, A0, Om)
+        q.append(orc.qke_tabulated(E, Ed, A, T / nq, p))
+    qke = (16 * q[1] - q[0]) / 15
+    np.testing.assert_allclose(dirac, qke, rtol=1e-8)
