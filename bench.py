@@ -89,6 +89,44 @@ def hbm_traffic_record():
     return rec if rec.get("evolve_sources_sha256") == sha else None
 
 
+def cpu_extrapolations(threads, sample_modes):
+    """The same oracle build on one pulse of the uneven batch (its largest) and of the full
+    surrogate-DE workload, extrapolated to the workload's unit of work: the evolution of the first
+    sample_modes modes for all steps, linearly in mode-steps (modes and pulses are independent),
+    plus the pulse's synthesis, scaled by the unit's sum of nt^2 (lines and steps both grow with
+    T at fixed dt)."""
+    import numpy as np
+    import oracle
+    from paper_1704_08919_amd import workloads as W
+
+    ub = W.uneven_batch(0)
+    k = max(range(len(ub["specs"])), key=lambda i: ub["specs"][i]["nt"] * W.n_modes(ub["grids"][i]))
+    spec5, grid5 = W.surrogate_de_spec()
+    nt_k = ub["specs"][k]["nt"]
+    cases = [(ub["name"], "one evaluation of the 256-pulse batch", ub["specs"][k], ub["grids"][k], ub["coeff"][k],
+              W.mode_steps(ub["specs"], ub["grids"]), sum((s["nt"] / nt_k) ** 2 for s in ub["specs"]),
+              f"pulse {k} (the largest)"),
+             ("surrogate_de_full_pop512_128x128x32_nt32768", "one plain DE generation (512 pulses)", spec5, grid5,
+              W.draw_coeff(0, 1, spec5["n_s"])[0], 512 * spec5["nt"] * W.n_modes(grid5), 512.0, "one pulse")]
+    out = []
+    for name, unit, spec, grid, coeff, total, synth_scale, which in cases:
+        p, _ = oracle.grid_points(grid)
+        p = p[:sample_modes]
+        t0 = time.perf_counter()
+        A, _, edge, _ = oracle.synth(spec, coeff, precision="d_fast", with_E=False)
+        t1 = time.perf_counter()
+        f = oracle.evolve_points(A, edge, spec["T"] / spec["nt"], p, precision="d_fast", nthreads=threads)
+        t2 = time.perf_counter()
+        assert np.all(np.isfinite(f))
+        rate = len(p) * spec["nt"] / (t2 - t1)
+        out.append({"workload": name, "unit": unit, "mode_steps_per_unit": total, "evolution_mode_steps_per_s": rate,
+                    "synthesis_s_sampled_pulse": t1 - t0,
+                    "s_per_unit_extrapolated": total / rate + synth_scale * (t1 - t0),
+                    "sample": f"{which}: synthesis, then the first {len(p)} of {W.n_modes(grid)} modes for all "
+                              f"{spec['nt']} steps ({t2 - t1:.1f} s)"})
+    return out
+
+
 def cpu_baseline(w, sample_modes, sample_pulses):
     import numpy as np
     import oracle
@@ -117,6 +155,7 @@ def cpu_baseline(w, sample_modes, sample_pulses):
         pass
     return {"value": ms / dt, "unit": "mode-steps/s", "cores": threads, "kind": "oracle",
             "cpu_model": cpu, "host_cpus": os.cpu_count(),
+            "extrapolated": cpu_extrapolations(threads, max(1, sample_modes // 4)),
             "build_flags": " ".join(oracle_build.FAST_FLAGS),
             "sample": f"pulses 0..{sample_pulses - 1} of {w['name']}: synthesis + first "
                       f"{min(sample_modes, n_modes)} of {n_modes} modes each, all {w['specs'][0]['nt']} steps "
