@@ -90,11 +90,12 @@ def hbm_traffic_record():
 
 
 def cpu_extrapolations(threads, sample_modes):
-    """The same oracle build on one pulse of the uneven batch (its largest) and of the full
-    surrogate-DE workload, extrapolated to the workload's unit of work: the evolution of the first
-    sample_modes modes for all steps, linearly in mode-steps (modes and pulses are independent),
-    plus the pulse's synthesis, scaled by the unit's sum of nt^2 (lines and steps both grow with
-    T at fixed dt)."""
+    """The same oracle build on one pulse of the uneven batch (its largest), of the full
+    surrogate-DE workload and of the surrogate training data, extrapolated to each workload's unit
+    of work: the evolution of the first sample_modes modes for all steps, linearly in mode-steps
+    (modes and pulses are independent), plus the pulse's synthesis times the number of pulses (in
+    the uneven batch weighted by (nt / nt_sampled)^2: lines and steps both grow with T at fixed
+    dt)."""
     import numpy as np
     import oracle
     from paper_1704_08919_amd import workloads as W
@@ -102,12 +103,15 @@ def cpu_extrapolations(threads, sample_modes):
     ub = W.uneven_batch(0)
     k = max(range(len(ub["specs"])), key=lambda i: ub["specs"][i]["nt"] * W.n_modes(ub["grids"][i]))
     spec5, grid5 = W.surrogate_de_spec()
+    spec4, grid4 = W.surrogate_data_spec()
     nt_k = ub["specs"][k]["nt"]
     cases = [(ub["name"], "one evaluation of the 256-pulse batch", ub["specs"][k], ub["grids"][k], ub["coeff"][k],
               W.mode_steps(ub["specs"], ub["grids"]), sum((s["nt"] / nt_k) ** 2 for s in ub["specs"]),
               f"pulse {k} (the largest)"),
              ("surrogate_de_full_pop512_128x128x32_nt32768", "one plain DE generation (512 pulses)", spec5, grid5,
-              W.draw_coeff(0, 1, spec5["n_s"])[0], 512 * spec5["nt"] * W.n_modes(grid5), 512.0, "one pulse")]
+              W.draw_coeff(0, 1, spec5["n_s"])[0], 512 * spec5["nt"] * W.n_modes(grid5), 512.0, "one pulse"),
+             ("surrogate_data_100k_T400_nt4096_64x64x16", "the 100,000-pulse training set", spec4, grid4,
+              W.draw_coeff(0, 1, spec4["n_s"])[0], 100000 * spec4["nt"] * W.n_modes(grid4), 100000.0, "one pulse")]
     out = []
     for name, unit, spec, grid, coeff, total, synth_scale, which in cases:
         p, _ = oracle.grid_points(grid)
