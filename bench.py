@@ -159,7 +159,7 @@ def cpu_baseline(w, sample_modes, sample_pulses):
         pass
     return {"value": ms / dt, "unit": "mode-steps/s", "cores": threads, "kind": "oracle",
             "cpu_model": cpu, "host_cpus": os.cpu_count(),
-            "extrapolated": cpu_extrapolations(threads, max(1, sample_modes // 4)),
+            "extrapolated": guarded(cpu_extrapolations, threads, max(1, sample_modes // 4)),
             "build_flags": " ".join(oracle_build.FAST_FLAGS),
             "sample": f"pulses 0..{sample_pulses - 1} of {w['name']}: synthesis + first "
                       f"{min(sample_modes, n_modes)} of {n_modes} modes each, all {w['specs'][0]['nt']} steps "
