@@ -91,3 +91,24 @@ def test_surrogate_de_accepts_only_plain_evaluated_fitness():
         assert np.array_equal(host(J), r["final_fit"]), mode
     # the same initial population: generation 0 best agrees across modes
     assert out["plain"]["history"][0][2] == out["surrogate"]["history"][0][2] == out["random"]["history"][0][2]
+
+
+def test_plain_de_resume_is_bitwise_exact():
+    # a plain run split over two calls (the state of the first handed to the second, as the
+    # full-configuration benchmark does between processes) ends with the population, fitness and
+    # best-so-far history of the same run done in one call: the Philox stream is keyed by the
+    # generation, so nothing of the first call is replayed or skipped
+    spec, grid = small_problem()
+    kw = dict(pop=32, seed=7, mode="plain", plan_config=dict(threads=256, modes_per_lane=1, persistent=1))
+    whole = S.run_de(spec, grid, generations=8, **kw)
+    first = S.run_de(spec, grid, generations=3, **kw)
+    state = dict(pop=first["final_pop"], fit=first["final_fit"], generation=first["generations"],
+                 evals=first["plain_evaluations"], history=np.asarray(first["history"]), wall_s=first["wall_s"])
+    second = S.run_de(spec, grid, generations=8, resume=state, **kw)
+    assert first["generations"] == 3 and second["generations"] == 8
+    assert np.array_equal(second["final_pop"], whole["final_pop"])
+    assert np.array_equal(second["final_fit"], whole["final_fit"])
+    assert second["plain_evaluations"] == whole["plain_evaluations"] == 32 * 9
+    assert [h[1:] for h in second["history"]] == [h[1:] for h in whole["history"]]
+    with pytest.raises(ValueError):
+        S.run_de(spec, grid, generations=8, resume=state, **dict(kw, mode="surrogate"))
