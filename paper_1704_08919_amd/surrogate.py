@@ -70,17 +70,20 @@ def log10_stats(J_host):
 
 def train(net, X, J, n, epochs=1, batch=1024, lr=1e-3, seed=0, stats=None, max_steps=None):
     """Minibatch Adam on (X[:n], standardised log10 J[:n]) for `epochs` passes over a fresh
-    permutation each (or at most max_steps minibatches); returns (mean, std, mean loss of the
-    last pass).  The minibatch indices of all steps are uploaded once and the steps run as
+    permutation each, or at most max_steps minibatches (epochs=None: exactly max_steps, over as
+    many passes as that takes); returns (mean, std, mean loss of the last pass).  The minibatch indices of all steps are uploaded once and the steps run as
     replays of the network's captured training step (po_mlp_train_indexed)."""
     mean, std = stats if stats is not None else log10_stats(J[:n, 0].cpu().numpy())
     rng = np.random.default_rng(seed)
     batch = min(batch, (n // 32) * 32)
     if batch < 32:
         raise ValueError("need at least 32 samples")
+    if epochs is None and max_steps is None:
+        raise ValueError("epochs=None needs max_steps")
     per_epoch = n // batch
+    n_epochs = epochs if epochs is not None else -(-max_steps // per_epoch)
     idx = []
-    for _ in range(epochs):
+    for _ in range(n_epochs):
         idx.append(rng.permutation(n).astype(np.int32)[:per_epoch * batch])
         if max_steps is not None and len(idx) * per_epoch >= max_steps:
             break
@@ -185,7 +188,7 @@ def run_de(spec, grid, pop=512, generations=200, seed=0, mode="surrogate", top=0
         archive = Archive(pop + k * generations, D)
         archive.add(popu, fit)
         net = api.MLP(D, width, depth, max_batch=max(1024, ((pop + 31) // 32) * 32), seed=seed + 2)
-        stats = train(net, archive.X, archive.J, archive.n, epochs=10 ** 6, seed=seed, max_steps=train_steps)[:2]
+        stats = train(net, archive.X, archive.J, archive.n, epochs=None, seed=seed, max_steps=train_steps)[:2]
     sel = torch.empty((k, D), dtype=torch.float64, device="cuda")
     rank_corr = []
 
@@ -223,7 +226,7 @@ def run_de(spec, grid, pop=512, generations=200, seed=0, mode="surrogate", top=0
                 archive.add(sel, Jsel)
                 if (g + 1) % retrain_every == 0:
                     ts = time.perf_counter()
-                    stats = train(net, archive.X, archive.J, archive.n, epochs=10 ** 6, seed=seed + g,
+                    stats = train(net, archive.X, archive.J, archive.n, epochs=None, seed=seed + g,
                                   max_steps=train_steps)[:2]
                     train_s += time.perf_counter() - ts
         evals += k
