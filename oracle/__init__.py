@@ -32,7 +32,7 @@ NORM_NONE, NORM_PEAK, NORM_ENERGY = 0, 1, 2
 def lib():
     global _lib
     if _lib is None:
-        path = _build.LIB
+        path = os.environ.get("ORACLE_LIB_PATH") or _build.LIB  # the override loads a sanitizer build
         if not os.path.exists(path):
             _build.build()
         L = ctypes.CDLL(path)

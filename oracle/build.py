@@ -28,6 +28,18 @@ def _compile(flags, out):
     os.replace(tmp, out)
 
 
+SANITIZE_FLAGS = ["-O1", "-g", "-std=c++17", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+                  "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                  "-Wno-unknown-pragmas"]
+
+
+def build_sanitized(out: str) -> str:
+    """The parity build's arithmetic with AddressSanitizer and UndefinedBehaviorSanitizer, into
+    `out` (host code only; loaded by a process that preloads the sanitizer runtimes)."""
+    _compile(SANITIZE_FLAGS, out)
+    return out
+
+
 def build(force: bool = True) -> str:
     for flags, out in ((FLAGS, LIB), (FAST_FLAGS, LIB_FAST)):
         if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(SRC):
