@@ -423,6 +423,27 @@ def local_search(api, W, torch, starts=10, seed=0):
             "gradient_mode_steps_per_s": ms / t["gradient"]}
 
 
+def cost_to_reach(rows, target):
+    """Per method, the time per momentum point at which eps first reaches `target`: rows in
+    increasing nt per method; log-log interpolation between the last row above the target and the
+    first at or below it (that row's cost if the method's first usable row is already below).
+    Unstable or unresolved rows (eps > 1) count as above the target and are not interpolated from;
+    a method that never reaches the target is absent."""
+    reach, prev = {}, {}
+    for row in rows:
+        m, us = row["method"], row["us_per_mode"]
+        e = None if (row.get("unstable") or row.get("unresolved")) else row["eps"]
+        if m not in reach and e is not None and e <= target:
+            p = prev.get(m)
+            if p is not None and p[1] is not None and p[1] > target:
+                a = math.log(target / p[1]) / math.log(e / p[1])
+                reach[m] = math.exp(math.log(p[0]) + a * (math.log(us) - math.log(p[0])))
+            else:
+                reach[m] = us
+        prev[m] = (us, e)
+    return reach
+
+
 def solver_comparison(api, W, torch, n_p=512, nts=(5000, 10000, 20000, 50000, 100000, 200000, 500000, 1000000),
                       nt_exact=2_000_000, target=1e-3):
     """The paper's accuracy-versus-time comparison (Sec. V C) on the circular multimode pulse of its
@@ -479,14 +500,13 @@ def solver_comparison(api, W, torch, n_p=512, nts=(5000, 10000, 20000, 50000, 10
 
     timed("dirac2", nt_exact)
     check = eps()
-    rows, reach = [], {}
+    rows = []
     for method in methods:
-        prev = None
         for nt in nts:
             ms = timed(method, nt)
             e = eps()
-            us = ms * 1e3 / M
-            row = {"method": method, "nt": nt, "eps": e, "us_per_mode": us, "mode_steps_per_s": M * nt / (ms * 1e-3)}
+            row = {"method": method, "nt": nt, "eps": e, "us_per_mode": ms * 1e3 / M,
+                   "mode_steps_per_s": M * nt / (ms * 1e-3)}
             if e is None or e > 1.0:
                 if method == "qke":
                     # RK4 outside its stability interval for the fastest modes: f grows without bound
@@ -494,15 +514,8 @@ def solver_comparison(api, W, torch, n_p=512, nts=(5000, 10000, 20000, 50000, 10
                 else:
                     # the unitary steps stay bounded; the step is too coarse for the fastest modes
                     row["unresolved"] = True
-                e = None
             rows.append(row)
-            if method not in reach and e is not None and e <= target:
-                if prev is not None and prev[1] is not None and prev[1] > target:  # log-log interpolation
-                    a = math.log(target / prev[1]) / math.log(e / prev[1])
-                    reach[method] = math.exp(math.log(prev[0]) + a * (math.log(us) - math.log(prev[0])))
-                else:
-                    reach[method] = us
-            prev = (us, e)
+    reach = cost_to_reach(rows, target)
     out = {"workload": w["name"], "modes": M, "nt_exact": nt_exact, "exact_ms": ms_exact,
            "exact_check_eps_dirac2": check, "target_eps": target, "rows": rows,
            "us_per_mode_to_target": reach}

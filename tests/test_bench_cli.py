@@ -1,6 +1,7 @@
 """Host-side checks of the benchmark script: it refuses more than one GPU with a message before
-touching any device, and the committed counter records it reads have the fields it uses and
-agree with the workload's sizes (64 pulses x 64x64x16 modes x nt = 16384)."""
+touching any device, the committed counter records it reads have the fields it uses and agree
+with the workload's sizes (64 pulses x 64x64x16 modes x nt = 16384), and the solver comparison's
+cost-to-accuracy interpolation."""
 import json
 import os
 import subprocess
@@ -53,3 +54,27 @@ def test_source_hash_ignores_comments_only():
     assert bench.code_lines(text) == "int a = 1;\n  b(a);\n"
     assert bench.code_lines(text + "// more\n") == bench.code_lines(text)
     assert bench.code_lines(text.replace("1;", "2;")) != bench.code_lines(text)
+
+
+def test_cost_to_reach_interpolates_in_log_log():
+    # eps = c us^-2 exactly (a second-order method at fixed cost per step): the log-log
+    # interpolation between the bracketing rows is then exact
+    c = 1e-5
+    rows = [{"method": "m2", "us_per_mode": us, "eps": c * us ** -2} for us in (0.02, 0.05, 0.2, 0.5)]
+    reach = bench.cost_to_reach(rows, 1e-3)
+    assert abs(reach["m2"] - (c / 1e-3) ** 0.5) <= 1e-12
+    # first usable row already below the target: its own cost
+    assert bench.cost_to_reach(rows, 1.0)["m2"] == 0.02
+
+
+def test_cost_to_reach_skips_unstable_and_unresolved_rows():
+    rows = [{"method": "qke", "us_per_mode": 0.1, "eps": None, "unstable": True},
+            {"method": "qke", "us_per_mode": 0.3, "eps": 5e-4},
+            {"method": "split2", "us_per_mode": 0.1, "eps": 30.0, "unresolved": True},
+            {"method": "split2", "us_per_mode": 0.2, "eps": 0.5},
+            {"method": "split2", "us_per_mode": 0.4, "eps": 2e-3},
+            {"method": "dirac2", "us_per_mode": 0.1, "eps": 40.0, "unresolved": True},
+            {"method": "dirac2", "us_per_mode": 0.2, "eps": 1e-4}]
+    reach = bench.cost_to_reach(rows, 1e-3)
+    assert reach["qke"] == 0.3 and reach["dirac2"] == 0.2  # nothing to interpolate from
+    assert "split2" not in reach  # never at or below the target
