@@ -24,7 +24,8 @@
  *  - Errors: every argument is validated before anything is enqueued.  Invalid arguments
  *    return PO_ERR_INVALID, HIP failures PO_ERR_DEVICE; in both cases po_last_error() gives a
  *    message (thread-local).  No C++ exception crosses the ABI.  Nothing is enqueued when a
- *    call returns an error from validation.
+ *    call returns an error from validation.  With po_set_check_finite enabled, the calls it
+ *    lists also return PO_ERR_NUMERIC for non-finite results (and are then synchronous).
  *  - Results are bitwise reproducible: reductions use a fixed order that depends only on the
  *    sizes of the problem, not on launch shapes or scheduling.
  *
