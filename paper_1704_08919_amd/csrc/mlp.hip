@@ -254,18 +254,42 @@ struct OutArgs {
   float* opart;       // [B / 32][W + 2]: dL/dw partials, then dL/db, squared error
 };
 
+// Output layer, loss, dL/dy and the last hidden layer's gradient for 32 samples per workgroup.
+// y[b] = sum_j h[b][j] w[j] is summed in one fixed grouping: partial p_l over the columns
+// l, l + 64, ... for l = 0..63, then pairwise p_l + p_(l^32), ^16, ^8, ^4, ^2, ^1.  A wave does its
+// 8 samples at once with 8 lanes per sample: lane `part` of a sample holds the partials of
+// l = 8 part + e (e = 0..7, one 16-byte load per 64 columns), combines l^32, ^16, ^8 across the
+// sample's lanes and l^4, ^2, ^1 in its registers.
 __global__ void __launch_bounds__(256) k_out_train(OutArgs a) {
   __shared__ float s_dy[32], s_sq[32];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int b0 = blockIdx.x * 32;
-  for (int q = 0; q < 8; ++q) {
-    const int b = b0 + wv * 8 + q;
-    float acc = 0.0f;
-    for (int j = lane; j < a.W; j += 64) acc = fmaf(float(a.h[size_t(b) * a.W + j]), float(a.w[j]), acc);
+  {
+    const int g = lane >> 3, part = lane & 7;
+    const int b = b0 + wv * 8 + g;
+    float p[8];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if (lane == 0) {
-      const float yb = acc + a.b0[0];
+    for (int e = 0; e < 8; ++e) p[e] = 0.0f;
+    for (int j0 = 8 * part; j0 < a.W; j0 += 64) {
+      const bf16x8 hv = load8(a.h + size_t(b) * a.W + j0);
+      const bf16x8 wv8 = load8(a.w + j0);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) p[e] = fmaf(float(hv[e]), float(wv8[e]), p[e]);
+    }
+#pragma unroll
+    for (int off = 4; off > 0; off >>= 1)  // l ^ 32, l ^ 16, l ^ 8
+#pragma unroll
+      for (int e = 0; e < 8; ++e) p[e] += __shfl_xor(p[e], off, 64);
+#pragma unroll
+    for (int off = 4; off > 0; off >>= 1) {  // l ^ 4, l ^ 2, l ^ 1
+      float q[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) q[e] = p[e] + p[e ^ off];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) p[e] = q[e];
+    }
+    if (part == 0) {
+      const float yb = p[0] + a.b0[0];
       a.y[b] = yb;
       float t;
       if (a.J) {
@@ -275,26 +299,34 @@ __global__ void __launch_bounds__(256) k_out_train(OutArgs a) {
         t = a.target[b];
       }
       const float d = yb - t;
-      s_dy[wv * 8 + q] = 2.0f * d / float(a.B);
-      s_sq[wv * 8 + q] = d * d;
+      s_dy[wv * 8 + g] = 2.0f * d / float(a.B);
+      s_sq[wv * 8 + g] = d * d;
     }
   }
   __syncthreads();
+  // one column per thread: its 32 rows are read before anything is written
   for (int j = threadIdx.x; j < a.W; j += 256) {
     const float wj = float(a.w[j]);
+    float gv[32], hv[32];
+#pragma unroll
+    for (int r = 0; r < 32; ++r) {
+      const size_t o = size_t(b0 + r) * a.W + j;
+      gv[r] = a.gp[o];
+      hv[r] = float(a.h[o]);
+    }
     float sb = 0.0f, sw = 0.0f;
+#pragma unroll
     for (int r = 0; r < 32; r += 4) {
       bf16x4 t4;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int b = b0 + r + e;
-        const size_t o = size_t(b) * a.W + j;
-        const float d = s_dy[r + e] * wj * a.gp[o];
+        const size_t o = size_t(b0 + r + e) * a.W + j;
+        const float d = s_dy[r + e] * wj * gv[r + e];
         const __bf16 db = __bf16(d);
         a.dz[o] = db;
         t4[e] = db;
         sb += d;
-        sw = fmaf(float(a.h[o]), s_dy[r + e], sw);
+        sw = fmaf(hv[r + e], s_dy[r + e], sw);
       }
       *reinterpret_cast<bf16x4*>(a.dzT + size_t(j) * a.ldt + b0 + r) = t4;
     }
