@@ -166,27 +166,60 @@ __global__ void __launch_bounds__(256) k_mm(MMArgs a) {
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-  for (int k0 = k_beg; k0 < k_end; k0 += 32) {
-    bf16x8 af[2], bf[2];
+  // k-steps in groups of four: the group's operands are all loaded before its products, so the
+  // loads of a group are in flight together (the products still run in k order)
+  for (int kb = k_beg; kb < k_end; kb += 4 * 32) {
+    bf16x8 af[4][2], bf[4][2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) af[i] = load8(A + size_t(arow[i]) * a.lda + k0 + kq);
+    for (int u = 0; u < 4; ++u) {
+      const int k0 = kb + 32 * u;
+      if (k0 < k_end) {
 #pragma unroll
-    for (int j = 0; j < 2; ++j) bf[j] = load8(a.Bt + size_t(tn * kTile + j * 16 + r16) * a.ldb + k0 + kq);
-    if constexpr (std::is_same<TA, double>::value) {
-      if (a.AT && tn == 0) {
+        for (int i = 0; i < 2; ++i) af[u][i] = load8(A + size_t(arow[i]) * a.lda + k0 + kq);
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int e = 0; e < 8; ++e) a.AT[size_t(k0 + kq + e) * a.ldat + tm * kTile + i * 16 + r16] = af[i][e];
+        for (int j = 0; j < 2; ++j) bf[u][j] = load8(a.Bt + size_t(tn * kTile + j * 16 + r16) * a.ldb + k0 + kq);
       }
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int u = 0; u < 4; ++u) {
+      const int k0 = kb + 32 * u;
+      if (k0 < k_end) {
+        if constexpr (std::is_same<TA, double>::value) {
+          if (a.AT && tn == 0) {
 #pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+              for (int e = 0; e < 8; ++e) a.AT[size_t(k0 + kq + e) * a.ldat + tm * kTile + i * 16 + r16] = af[u][i][e];
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[u][i], bf[u][j], acc[i][j], 0, 0, 0);
+      }
+    }
   }
   // lane holds rows tm*32 + i*16 + (lane >> 4)*4 + r, r = 0..3, of column tn*32 + j*16 + (lane & 15)
   const int rq = (lane >> 4) * 4;
+  // every value the epilogue reads is loaded before its first store (the stores could alias them)
+  float pre[2][2][4];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int n = tn * kTile + j * 16 + r16;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if constexpr (EPI == EPI_FWD || EPI == EPI_FWD_TRAIN) {
+          pre[j][i][r] = (i == 0 && r == 0) ? a.bias[n] : 0.0f;
+        } else if constexpr (EPI == EPI_BWD) {
+          pre[j][i][r] = a.gp_in[size_t(tm * kTile + i * 16 + rq + r) * a.N + n];
+        } else {
+          pre[j][i][r] = 0.0f;
+        }
+      }
+  }
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const int n = tn * kTile + j * 16 + r16;
@@ -201,7 +234,7 @@ __global__ void __launch_bounds__(256) k_mm(MMArgs a) {
         const size_t o = size_t(m) * a.N + n;
         const float c = acc[i][j][r];
         if constexpr (EPI == EPI_FWD || EPI == EPI_FWD_TRAIN) {
-          const float z = c + a.bias[n];
+          const float z = c + pre[j][0][0];
           const __bf16 hb = __bf16(gelu(z));
           a.C[o] = hb;
           if constexpr (EPI == EPI_FWD_TRAIN) {
@@ -209,7 +242,7 @@ __global__ void __launch_bounds__(256) k_mm(MMArgs a) {
             t4[r] = hb;
           }
         } else if constexpr (EPI == EPI_BWD) {
-          const float d = c * a.gp_in[o];
+          const float d = c * pre[j][i][r];
           const __bf16 db = __bf16(d);
           if (a.C) a.C[o] = db;
           t4[r] = db;
@@ -372,7 +405,8 @@ __device__ __forceinline__ int64_t wpart_off(const ParamMap& q, int l) {
   return l == 0 ? 0 : int64_t(kMaxSplit) * q.n_in * q.width + int64_t(l - 1) * kMaxSplit * q.width * q.width;
 }
 
-// Gradient of parameter i: its partial sums added in a fixed order.
+// Gradient of parameter i: its partial sums added in a fixed order (the loops are unrolled so that
+// their loads are in flight together; the additions stay in order).
 __device__ __forceinline__ float assembled_grad(const ParamMap& q, int64_t i) {
   int64_t off = 0;
   int kin = q.n_in;
@@ -382,6 +416,7 @@ __device__ __forceinline__ float assembled_grad(const ParamMap& q, int64_t i) {
       const int64_t e = i - off;
       const float* pp = q.wpart + wpart_off(q, l);
       float s = 0.0f;
+#pragma unroll 4
       for (int sp = 0; sp < q.splits; ++sp) s += pp[sp * nw + e];
       return s;
     }
@@ -389,6 +424,7 @@ __device__ __forceinline__ float assembled_grad(const ParamMap& q, int64_t i) {
       const int n = int(i - off - nw);
       const float* bp = q.bpart + l * q.bpart_stride;
       float s = 0.0f;
+#pragma unroll 8
       for (int t = 0; t < q.nblk; ++t) s += bp[int64_t(t) * q.width + n];
       return s;
     }
@@ -397,6 +433,7 @@ __device__ __forceinline__ float assembled_grad(const ParamMap& q, int64_t i) {
   }
   const int j = int(i - off);  // 0..width-1: output weights; width: output bias
   float s = 0.0f;
+#pragma unroll 8
   for (int t = 0; t < q.nblk; ++t) s += q.opart[int64_t(t) * (q.width + 2) + j];
   return s;
 }
@@ -438,6 +475,7 @@ __global__ void __launch_bounds__(256) k_adam(ParamMap q, const float* __restric
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i == 0 && loss) {
     float s = 0.0f;
+#pragma unroll 8
     for (int t = 0; t < q.nblk; ++t) s += q.opart[int64_t(t) * (q.width + 2) + q.width + 1];
     loss[loss_by_cursor ? c->cursor - 1 : 0] = s / float(q.batch);
   }
