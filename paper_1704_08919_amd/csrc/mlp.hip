@@ -66,7 +66,7 @@ struct po_mlp {
   __bf16* hT = nullptr;        // transposed h_0 (the input)..h_{depth-1} [depth][hstride][max_batch]
   float* gp = nullptr;         // gelu'(z_l) [depth][max_batch][width] fp32
   __bf16* dz = nullptr;        // pre-activation gradients [2][max_batch][width] bf16 (ping-pong)
-  __bf16* dzT = nullptr;       // transposed [width][max_batch] bf16
+  __bf16* dzT = nullptr;       // transposed [2][width][max_batch] bf16 (ping-pong)
   float* y = nullptr;          // outputs [max_batch]
   float* wpart = nullptr;      // weight-gradient partials, per layer [kMaxSplit][k_in][width]
   float* bpart = nullptr;      // bias-gradient partials, per layer [max_batch / 32][width]
@@ -141,12 +141,13 @@ __device__ __forceinline__ bf16x8 load8(const double* p) {
   return r;
 }
 
-// C = A Bt^T for one 32x32 tile per wave; EPI selects what the tile writes.
+// C = A Bt^T for one 32x32 tile per wave; EPI selects what the tile writes.  `block` is the
+// workgroup's index within this product.
 template <class TA, int EPI>
-__global__ void __launch_bounds__(256) k_mm(MMArgs a) {
+__device__ __forceinline__ void mm_body(const MMArgs& a, int block) {
   const int lane = threadIdx.x & 63;
   const int tm_n = a.M / kTile, tn_n = a.N / kTile;
-  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int w = block * 4 + (threadIdx.x >> 6);
   if (w >= tm_n * tn_n * a.splits) return;
   const int split = w / (tm_n * tn_n);
   const int tt = w - split * tm_n * tn_n;
@@ -262,6 +263,20 @@ __global__ void __launch_bounds__(256) k_mm(MMArgs a) {
       if (lane < 16) a.part[size_t(tm) * a.N + n] = colsum;
     }
   }
+}
+
+template <class TA, int EPI>
+__global__ void __launch_bounds__(256) k_mm(MMArgs a) {
+  mm_body<TA, EPI>(a, blockIdx.x);
+}
+
+// Two independent products in one launch: workgroups [0, nb1) do the first, the rest the second.
+template <class TA1, int EPI1, class TA2, int EPI2>
+__global__ void __launch_bounds__(256) k_mm2(MMArgs a1, int nb1, MMArgs a2) {
+  if (int(blockIdx.x) < nb1)
+    mm_body<TA1, EPI1>(a1, blockIdx.x);
+  else
+    mm_body<TA2, EPI2>(a2, int(blockIdx.x) - nb1);
 }
 
 // Output layer and loss of a training step, one workgroup per 32 samples b0..b0+31:
@@ -610,6 +625,16 @@ po_status launch_mm(const MMArgs& m, hipStream_t s) {
   return PO_OK;
 }
 
+int mm_blocks(const MMArgs& m) { return blocks(int64_t(m.M / kTile) * (m.N / kTile) * m.splits, 4); }
+
+template <class TA1, int EPI1, class TA2, int EPI2>
+po_status launch_mm2(const MMArgs& m1, const MMArgs& m2, hipStream_t s) {
+  const int nb1 = mm_blocks(m1);
+  hipLaunchKernelGGL((k_mm2<TA1, EPI1, TA2, EPI2>), dim3(nb1 + mm_blocks(m2)), dim3(256), 0, s, m1, nb1, m2);
+  PO_HIP(hipGetLastError());
+  return PO_OK;
+}
+
 MMArgs mm_base() {
   MMArgs m;
   std::memset(&m, 0, sizeof m);
@@ -693,6 +718,10 @@ po_status grad_impl(po_mlp* a, const double* d_x, RowMap rows, const float* d_t,
   o.opart = a->opart;
   hipLaunchKernelGGL(k_out_train, dim3(B / 32), dim3(256), 0, s, o);
   PO_HIP(hipGetLastError());
+  // dz_l row-major in dz[cur], transposed in dzT[cur]; the weight gradient of layer l and the
+  // gradient of layer l - 1 only read them, so both products run in one launch and the latter
+  // writes the other buffers.
+  const size_t tslot = size_t(W) * a->max_batch;
   int cur = 0;
   for (int l = D - 1; l >= 0; --l) {
     const int K = layer_k(a, l);
@@ -701,14 +730,13 @@ po_status grad_impl(po_mlp* a, const double* d_x, RowMap rows, const float* d_t,
     MMArgs g = mm_base();
     g.A = a->hT + size_t(l) * hs * a->max_batch;
     g.lda = a->max_batch;
-    g.Bt = a->dzT;
+    g.Bt = a->dzT + cur * tslot;
     g.ldb = a->max_batch;
     g.M = K;
     g.N = W;
     g.K = B;
     g.splits = S;
     g.part = a->wpart + wpart_offset(a, l);
-    PO_TRY((launch_mm<__bf16, EPI_PART>(g, s)));
     if (l > 0) {
       // dh_{l}[b][k] = sum_n dz_l[b][n] W_l[k][n]: A = dz_l [B][W], Bt = W_l [K][W]; times gelu'(z_{l-1})
       MMArgs d = mm_base();
@@ -721,11 +749,13 @@ po_status grad_impl(po_mlp* a, const double* d_x, RowMap rows, const float* d_t,
       d.K = W;
       d.gp_in = a->gp + size_t(l - 1) * slot;
       d.C = l - 1 > 0 ? a->dz + (1 - cur) * slot : nullptr;
-      d.CT = a->dzT;
+      d.CT = a->dzT + (1 - cur) * tslot;
       d.ldct = a->max_batch;
       d.part = a->bpart + size_t(l - 1) * (a->max_batch / 32) * W;
-      PO_TRY((launch_mm<__bf16, EPI_BWD>(d, s)));
+      PO_TRY((launch_mm2<__bf16, EPI_PART, __bf16, EPI_BWD>(g, d, s)));
       cur = 1 - cur;
+    } else {
+      PO_TRY((launch_mm<__bf16, EPI_PART>(g, s)));
     }
   }
   return PO_OK;
@@ -830,7 +860,7 @@ po_status create_impl(po_mlp* a, uint64_t seed, hipStream_t s) {
   PO_TRY(dalloc(&a->hT, size_t(a->depth) * hs * MB));
   PO_TRY(dalloc(&a->gp, size_t(a->depth) * MB * W));
   PO_TRY(dalloc(&a->dz, 2 * size_t(MB) * W));
-  PO_TRY(dalloc(&a->dzT, size_t(W) * MB));
+  PO_TRY(dalloc(&a->dzT, 2 * size_t(W) * MB));
   PO_TRY(dalloc(&a->y, MB));
   PO_TRY(dalloc(&a->wpart, size_t(kMaxSplit) * (size_t(a->n_in) * W + size_t(a->depth - 1) * W * W)));
   PO_TRY(dalloc(&a->bpart, size_t(a->depth) * (MB / 32) * W));
