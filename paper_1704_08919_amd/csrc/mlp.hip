@@ -15,9 +15,10 @@
 // forward product).  Weight gradients (k = batch) are split over k into fixed partial sums that
 // the optimiser adds in order, bias gradients are column sums per 32-row tile fused into the
 // epilogue that produces the pre-activation gradient, and the output layer (a dot product per
-// sample), the loss, dL/dy and the last hidden layer's gradient are one kernel.  A training step
-// is 11 launches, captured once into a HIP graph and replayed; every reduction has a fixed order,
-// so a step is bitwise reproducible.
+// sample), the loss, dL/dy and the last hidden layer's gradient are one kernel, and the weight
+// gradient of a layer shares a launch with the input gradient of the layer below (the transposed
+// gradients alternate between two buffers).  A training step is 9 launches, captured once into a
+// HIP graph and replayed; every reduction has a fixed order, so a step is bitwise reproducible.
 //
 // Rounding points (the oracle emulates them): the input is rounded to bf16 through float, every
 // weight matrix used as an operand, every hidden activation gelu(z) and every pre-activation
